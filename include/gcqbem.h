@@ -1,0 +1,290 @@
+/*
+ * gcqbem -- MI355X (gfx950) library for the frequency-domain hot path of a
+ * gCQ time-domain boundary element method with H-matrix based 3D-ACA
+ * (Schanz, Keshava, De Gersem, "Comparison of H-matrix- and FMM-based 3D-ACA
+ * for a time-domain boundary element method", arXiv 2505.00715).
+ *
+ * What the library computes, all for the single-layer operator of the
+ * acoustic wave equation in the Laplace domain (Sec. 2 eq. slp with the
+ * kernel replaced by its transform, Sec. 3):
+ *
+ *   U(r, s)      = exp(-s r / c) / (4 pi r),          Re s > 0
+ *   V(s)[i, j]   = int_{tau_j} U(|x_i - y|, s) dy      (piecewise-constant
+ *                  basis, collocation at the centroid x_i of triangle i)
+ *
+ * over a closed flat-triangle surface (eq. geomapprox) and a set of complex
+ * frequencies s_0..s_{L-1} (the gCQ integration points, Sec. 3 temporal
+ * discretisation and App. A).  On top of the entries it builds the H-matrix
+ * face of Sec. 4 (cluster tree, block cluster tree with eq. admissible, ACA
+ * with QR/SVD recompression of admissible blocks, dense near field), the
+ * 3D-ACA of Alg. 1 across the frequencies, and products with the compressed
+ * 3D array (eq. product), including a batched iterative solve.
+ *
+ * Conventions
+ *   - Every function returns an int status: 0 = OK, > 0 = warning, < 0 = error.
+ *     On error, gcq_last_error() gives a message (thread-local, valid until the
+ *     next call on the same thread).  No C++ exception crosses this boundary.
+ *   - Indices are 0-based and refer to the caller's triangle order; the
+ *     library's cluster permutation is internal.
+ *   - Complex numbers are interleaved (re, im): gcq_c128 for double, pairs of
+ *     float for single precision.
+ *   - "host" arguments are plain host pointers; the library copies what it
+ *     needs before returning and never keeps them.  "device" arguments are
+ *     device pointers owned by the caller (for example torch tensors on the
+ *     same GPU); the library checks that they are device memory, never frees
+ *     them, and only accesses them inside the call's stream work.
+ *   - All device work is enqueued on the context's stream.  Calls that return
+ *     host statistics synchronise that stream; the products do not.
+ *   - Call order: upload_mesh -> set_frequencies -> build_cluster_tree ->
+ *     {aca_blocks | aca3d} -> products / solve.  A call made too early returns
+ *     GCQ_ERR_STATE.  Uploading a mesh or frequencies invalidates everything
+ *     built on them.
+ */
+#ifndef GCQBEM_H
+#define GCQBEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GCQ_API __attribute__((visibility("default")))
+
+typedef struct gcq_context gcq_context;
+
+typedef struct {
+  double re, im;
+} gcq_c128;
+
+/* Arithmetic of a call.
+ *   GCQ_C128: complex128 throughout.
+ *   GCQ_C64:  complex64 far-field entries, low-rank factors and products with
+ *             float accumulation; the self and near-singular quadrature and
+ *             every stopping-criterion norm stay in float64. */
+enum { GCQ_C128 = 0, GCQ_C64 = 1 };
+
+/* Product modes of gcq_compressed_matvec.
+ *   GCQ_PER_FREQUENCY: Y[k] = V(s_k) X[k] for every frequency k, V(s_k)
+ *                      the 3D-ACA approximant.
+ *   GCQ_WEIGHTED_SUM:  y = sum_k V(s_k) X[k] (eq. product: the frequency sum
+ *                      is taken per slice before the spatial product).
+ *   GCQ_PLAIN_H:       Y[k] = V_H(s_k) X[k] with the per-frequency H-matrices
+ *                      of gcq_aca_blocks (no frequency compression). */
+enum { GCQ_PER_FREQUENCY = 0, GCQ_WEIGHTED_SUM = 1, GCQ_PLAIN_H = 2 };
+
+/* Status codes. */
+enum {
+  GCQ_OK = 0,
+  GCQ_NOT_CONVERGED = 1, /* solve: some system missed the tolerance            */
+  GCQ_RANK_CAPPED = 2,   /* aca_blocks / aca3d: some block hit its rank limit   */
+  GCQ_ERR_ARG = -1,      /* invalid argument (null, range, host-vs-device)     */
+  GCQ_ERR_NOMEM = -2,    /* device allocation failed                           */
+  GCQ_ERR_HIP = -3,      /* HIP runtime error                                  */
+  GCQ_ERR_STATE = -4,    /* call order violated                                */
+  GCQ_ERR_NUMERIC = -5,  /* degenerate geometry or non-finite data             */
+  GCQ_ERR_UNSUPPORTED = -6
+};
+
+/* Flags of gcq_aca_blocks. */
+enum {
+  GCQ_FLAG_RECOMPRESS = 1u,      /* QR/SVD recompression after ACA (Sec. 4)          */
+  GCQ_FLAG_USE_PREDICTOR = 2u,   /* size work tiles from the trained rank model      */
+  GCQ_FLAG_PER_FREQ_LAUNCH = 4u  /* one launch per frequency, no batching (baseline)  */
+};
+
+typedef struct {
+  int32_t n_clusters;
+  int32_t n_leaves;
+  int32_t depth;       /* levels below the root                       */
+  int32_t n_blocks;    /* leaves of the block cluster tree            */
+  int32_t n_far;       /* admissible blocks                           */
+  int32_t n_near;      /* inadmissible (dense) blocks                 */
+  int64_t far_dims;    /* sum over far blocks of |I| + |J|            */
+  int64_t near_entries;/* sum over near blocks of |I| |J|             */
+} gcq_tree_info;
+
+typedef struct {
+  int64_t n_pairs;          /* (far block, frequency) pairs approximated       */
+  int64_t aca_rank_sum;     /* sum of ACA ranks                                */
+  int64_t rank_sum;         /* sum of ranks after recompression                */
+  int32_t rank_max;
+  int32_t n_capped;         /* pairs that hit max_rank                         */
+  int64_t n_overflow;       /* pairs re-run because their tile was too small   */
+  int64_t entries;          /* kernel entries evaluated (rows + columns)       */
+  int64_t storage_bytes;    /* compressed far field + dense near field         */
+  double device_ms;         /* device time of the call                         */
+} gcq_aca_stats;
+
+typedef struct {
+  int32_t n_blocks;
+  int32_t rank_min, rank_max; /* frequency ranks r_b over blocks              */
+  double rank_mean;
+  int32_t n_capped;           /* blocks that reached max_freq_rank            */
+  int64_t slice_rank_sum;     /* sum over far slices of their ACA rank        */
+  int64_t storage_bytes;      /* slices + fibers                               */
+  double compression_rate;    /* storage / dense storage of all |K| matrices  */
+  double device_ms;
+} gcq_aca3d_stats;
+
+typedef struct {
+  int32_t n_systems;
+  int32_t n_converged;
+  int32_t iters_max;
+  double resid_max;           /* max over systems of |b - A x| / |b|          */
+  double device_ms;
+} gcq_solve_stats;
+
+typedef struct {
+  int32_t epochs;
+  int32_t batch;
+  float lr, beta1, beta2, eps;
+  uint64_t seed;              /* shuffling and initialisation                  */
+} gcq_train_cfg;
+
+typedef struct {
+  float loss_first, loss_last; /* mean loss of the first and last epoch        */
+  double device_ms;
+} gcq_train_stats;
+
+/* ---- context --------------------------------------------------------------
+ * gcq_create: context on HIP device `device`, enqueuing on `hip_stream`
+ *   (a hipStream_t; NULL = the device's null stream).  *out receives the
+ *   context; the caller releases it with gcq_destroy, which frees every device
+ *   allocation the library made for it. */
+GCQ_API int gcq_create(int device, void* hip_stream, gcq_context** out);
+GCQ_API int gcq_destroy(gcq_context* ctx);
+GCQ_API const char* gcq_last_error(void);
+/* Device time (ms) of the library's most recent kernel of the named kind
+ * ("aca", "recompress", "aca3d", "matvec", ...) as measured with HIP events,
+ * or -1 if none. */
+GCQ_API double gcq_kernel_ms(gcq_context* ctx, const char* name);
+
+/* ---- geometry and frequencies (Sec. 3; Sec. 2) ------------------------------
+ * gcq_upload_mesh: host xyz (n_vertices x 3 doubles, row-major) and tri
+ *   (n_triangles x 3 int32 vertex ids, outward orientation) of Gamma_h
+ *   (eq. geomapprox); wave speed c > 0.  Builds the panel tables on the device
+ *   (centroids, longest edges, 7-point quadrature of each triangle).
+ *   GCQ_ERR_NUMERIC for a zero-area triangle or non-finite coordinates. */
+GCQ_API int gcq_upload_mesh(gcq_context* ctx, const double* xyz, int64_t n_vertices,
+                            const int32_t* tri, int64_t n_triangles, double wave_speed);
+
+/* gcq_set_frequencies: host array of n_freq complex frequencies s_k (the
+ *   points at which the 3D array of Sec. 3 is sampled); Re s_k > 0 is
+ *   required (GCQ_ERR_ARG otherwise).  With use_conjugate_symmetry != 0, a
+ *   frequency k > n_freq/2 whose value is the conjugate of s_{n_freq-k} is
+ *   represented by that partner (V(conj s) = conj V(s)), so only the set
+ *   K = {0..n_freq/2} is ever approximated (Sec. 5.1; App. A). */
+GCQ_API int gcq_set_frequencies(gcq_context* ctx, const gcq_c128* s, int32_t n_freq,
+                                int32_t use_conjugate_symmetry);
+
+/* gcq_build_cluster_tree: cluster tree and block cluster tree of Sec. 4
+ *   (eq. admissible with parameter eta > 0, leaves of at most leaf_size
+ *   triangles).  info may be NULL. */
+GCQ_API int gcq_build_cluster_tree(gcq_context* ctx, int32_t leaf_size, double eta,
+                                   gcq_tree_info* info);
+
+/* gcq_get_tree: copies the partition to host arrays: perm (n_triangles:
+ *   internal position -> caller index) and blocks (n_blocks x 5 int32:
+ *   row_begin, row_end, col_begin, col_end in internal positions, admissible),
+ *   in depth-first order.  Either pointer may be NULL. */
+GCQ_API int gcq_get_tree(gcq_context* ctx, int32_t* perm, int32_t* blocks);
+
+/* ---- entries (Sec. 3) -----------------------------------------------------
+ * gcq_assemble_slices: dense entries V(s_f)[rows[a], cols[b]] for the host
+ *   index lists rows (n_rows), cols (n_cols) and frequency indices freq_idx
+ *   (n_fidx, each in 0..n_freq-1).  out_dev (device, caller-owned) receives
+ *   n_fidx x n_cols x n_rows complex values, rows fastest (column-major per
+ *   slice): complex128 for GCQ_C128, complex64 for GCQ_C64 (far entries then
+ *   computed in float; self and near entries always in double). */
+GCQ_API int gcq_assemble_slices(gcq_context* ctx, const int32_t* rows, int64_t n_rows,
+                                const int32_t* cols, int64_t n_cols, const int32_t* freq_idx,
+                                int32_t n_fidx, int32_t precision, void* out_dev);
+
+/* ---- H-matrix faces per frequency (Sec. 4) --------------------------------
+ * gcq_aca_blocks: ACA (partial pivoting, relative tolerance tol, at most
+ *   max_rank terms) of every admissible block at every frequency of K (or of
+ *   the n_fidx listed representatives when freq_idx != NULL), followed by
+ *   QR/SVD recompression when GCQ_FLAG_RECOMPRESS is set; near blocks are
+ *   assembled densely.  The result is kept in the context for GCQ_PLAIN_H
+ *   products and gcq_get_block_factors.  Returns GCQ_RANK_CAPPED if some pair
+ *   reached max_rank.  stats may be NULL. */
+GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_fidx,
+                           double tol, int32_t max_rank, int32_t precision, uint32_t flags,
+                           gcq_aca_stats* stats);
+
+/* gcq_get_block_factors: host copy of the factors of admissible block `block`
+ *   (index into the depth-first block list) at representative frequency
+ *   `freq`: U (|I| x rank) and V (|J| x rank), column-major complex128, rows
+ *   in internal order of the block's clusters, with A_b(s) ~ U V^H.  Buffers
+ *   must hold cap columns; *rank receives the rank (GCQ_ERR_ARG if > cap). */
+GCQ_API int gcq_get_block_factors(gcq_context* ctx, int32_t block, int32_t freq, gcq_c128* U,
+                                  gcq_c128* V, int32_t cap, int32_t* rank);
+
+/* ---- 3D-ACA (Sec. 4, Alg. 1, eq. norm) ------------------------------------
+ * gcq_aca3d: per block of the partition, the 3D-ACA over the frequencies of K
+ *   with slice tolerance tol_aca (ACA + recompression of far slices) and
+ *   frequency tolerance tol, at most max_freq_rank terms per block. */
+GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol, int32_t max_freq_rank,
+                      int32_t precision, uint32_t flags, gcq_aca3d_stats* stats);
+
+/* gcq_get_aca3d_block: host copy of block `block`'s 3D-ACA: *rank terms,
+ *   freqs (rank positions in K), fibers (rank x |K| complex128) and the dense
+ *   expansion of each slice (rank x |J| x |I| complex128, column-major per
+ *   slice, internal order).  Buffers must hold cap terms. */
+GCQ_API int gcq_get_aca3d_block(gcq_context* ctx, int32_t block, int32_t cap, int32_t* rank,
+                                int32_t* freqs, gcq_c128* fibers, gcq_c128* slices);
+
+/* ---- products (eq. product) -----------------------------------------------
+ * gcq_compressed_matvec: X_dev, Y_dev are device arrays of n_cols vectors of
+ *   length n_triangles, vector-major (torch shape (n_cols, n), contiguous);
+ *   complex128 for GCQ_C128, complex64 for GCQ_C64.  n_cols must equal
+ *   n_freq.  For GCQ_WEIGHTED_SUM, Y_dev holds one vector.  Enqueued on the
+ *   context stream without synchronisation. */
+GCQ_API int gcq_compressed_matvec(gcq_context* ctx, int32_t mode, int32_t precision,
+                                  const void* X_dev, void* Y_dev, int32_t n_cols);
+
+/* ---- batched solve ---------------------------------------------------------
+ * gcq_solve: solves V(s_k) x_k = b_k for every frequency k at once with
+ *   restarted GMRES(restart) on the 3D-ACA operator, orthogonalisation in
+ *   float64 (classical Gram-Schmidt twice), until |b - A x| <= rtol |b| or
+ *   max_iter iterations.  B_dev, X_dev: complex128 device arrays shaped like
+ *   the products' X.  The product inside uses `precision`.  Returns
+ *   GCQ_NOT_CONVERGED if some system missed the tolerance. */
+GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_dev, double rtol,
+                      int32_t max_iter, int32_t restart, int32_t precision,
+                      gcq_solve_stats* stats);
+
+/* ---- learned rank predictor -----------------------------------------------
+ * The network (5 -> 64 -> 64 -> 1, tanh, float) maps standardised features of
+ * a (far block, frequency) pair to log(1 + ACA rank).  Parameters are laid
+ * out W1(64x5) b1(64) W2(64x64) b2(64) W3(1x64) b3(1), row-major; 4545 floats.
+ *
+ * gcq_rank_features: host features (n_far x n_fidx x 5 floats, unstandardised)
+ *   of every admissible block at the listed representatives:
+ *   [diam |s|/c, dist Re(s)/c, dist |Im s|/c, log2|I|, log2|J|].
+ * gcq_rank_model_train: trains on m host samples (feat m x 5, unstandardised;
+ *   target m floats = log(1 + rank)) with the library's forward, backward and
+ *   Adam kernels; standardisation is fitted on the training set.
+ * gcq_rank_model_grad: one forward/backward pass at the current parameters
+ *   on m host samples (already standardised); writes the mean loss and the
+ *   gradient (4545 floats) to host memory.
+ * gcq_rank_model_predict: predicted log(1 + rank) for m host samples.
+ * gcq_rank_model_get / set: host copy of parameters (4545 floats) and of the
+ *   standardisation (mean[5], std[5]; either pointer may be NULL). */
+GCQ_API int gcq_rank_features(gcq_context* ctx, const int32_t* freq_idx, int32_t n_fidx,
+                              float* feat);
+GCQ_API int gcq_rank_model_train(gcq_context* ctx, const float* feat, const float* target,
+                                 int64_t m, const gcq_train_cfg* cfg, gcq_train_stats* stats);
+GCQ_API int gcq_rank_model_grad(gcq_context* ctx, const float* feat_std, const float* target,
+                                int64_t m, float* loss, float* grad);
+GCQ_API int gcq_rank_model_predict(gcq_context* ctx, const float* feat, int64_t m,
+                                   float* out);
+GCQ_API int gcq_rank_model_get(gcq_context* ctx, float* params, float* mean, float* std);
+GCQ_API int gcq_rank_model_set(gcq_context* ctx, const float* params, const float* mean,
+                               const float* std);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GCQBEM_H */

@@ -24,6 +24,7 @@ import math
 import numpy as np
 
 from . import quadrature
+from .geometry import sqnorm
 
 FOUR_PI = 4.0 * math.pi
 SELF, NEAR, FAR = 0, 1, 2
@@ -48,9 +49,10 @@ def phi(a):
 
 
 def tier(P, i: int, j: int) -> int:
+    """|x_i - x_j| < 2 h_j, evaluated as |x_i - x_j|^2 < 4 h_j^2."""
     if i == j:
         return SELF
-    if np.linalg.norm(P.centroid[i] - P.centroid[j]) < 2.0 * P.h[j]:
+    if sqnorm(P.centroid[i] - P.centroid[j]) < 4.0 * P.h2[j]:
         return NEAR
     return FAR
 
@@ -118,8 +120,8 @@ def block(P, rows, cols, s, c: float):
             r = np.sqrt((d * d).sum(-1))                            # (ma, n, 7)
             for f, sf in enumerate(s):
                 out[f, a:a + 64, :] = (kernel(r, sf, c) * P.qw[cols][None, :, :]).sum(-1)
-    cdist = np.linalg.norm(x[:, None, :] - P.centroid[cols][None, :, :], axis=-1)
-    close = (cdist < 2.0 * P.h[cols][None, :]) | (rows[:, None] == cols[None, :])
+    cd2 = sqnorm(x[:, None, :] - P.centroid[cols][None, :, :])
+    close = (cd2 < 4.0 * P.h2[cols][None, :]) | (rows[:, None] == cols[None, :])
     for a, b in zip(*np.nonzero(close)):
         out[:, a, b] = entry(P, int(rows[a]), int(cols[b]), s, c)
     return out

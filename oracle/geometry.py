@@ -13,6 +13,12 @@ import numpy as np
 from . import quadrature
 
 
+def sqnorm(d):
+    """Squared Euclidean length of 3-vectors (last axis), summed x, y, z in order."""
+    d = np.asarray(d, dtype=np.float64)
+    return d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1] + d[..., 2] * d[..., 2]
+
+
 class Panels:
     def __init__(self, xyz, tri):
         xyz = np.asarray(xyz, dtype=np.float64)
@@ -27,10 +33,10 @@ class Panels:
         self.area = 0.5 * np.linalg.norm(cr, axis=1)
         self.normal = cr / (2.0 * self.area[:, None])
         self.centroid = (self.v0 + self.v1 + self.v2) / 3.0
-        edges = np.stack([np.linalg.norm(self.v1 - self.v0, axis=1),
-                          np.linalg.norm(self.v2 - self.v1, axis=1),
-                          np.linalg.norm(self.v0 - self.v2, axis=1)], axis=1)
-        self.h = edges.max(axis=1)
+        e2 = np.stack([sqnorm(self.v1 - self.v0), sqnorm(self.v2 - self.v1),
+                       sqnorm(self.v0 - self.v2)], axis=1)
+        self.h2 = e2.max(axis=1)          # squared longest edge
+        self.h = np.sqrt(self.h2)
         bary, w = quadrature.radon7()
         # far rule: (n, 7, 3) points and (n, 7) weights
         self.qp = (bary[None, :, 0:1] * self.v0[:, None, :]

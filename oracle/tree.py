@@ -12,13 +12,16 @@ library):
   boxes   axis-aligned box of all vertices of the cluster's triangles;
           diam = box diagonal; dist = Euclidean distance between the boxes.
   blocks  starting from (root, root), depth first: admissible (dist > 0 and
-          min(diam) <= eta dist) -> far leaf; otherwise, if either cluster is a
+          min(diam) <= eta dist, evaluated on squares:
+          min(diam^2) <= (eta*eta) dist^2) -> far leaf; otherwise, if either cluster is a
           leaf -> near leaf; otherwise recurse into the 2 x 2 son pairs in the
           order (s0,t0), (s0,t1), (s1,t0), (s1,t1).
 """
 from __future__ import annotations
 
 import numpy as np
+
+from .geometry import sqnorm
 
 
 class ClusterTree:
@@ -67,17 +70,23 @@ class ClusterTree:
     def indices(self, c: int):
         return self.perm[self.begin[c]:self.end[c]]
 
+    def diam2(self, c: int) -> float:
+        return float(sqnorm(self.bmax[c] - self.bmin[c]))
+
+    def dist2(self, a: int, b: int) -> float:
+        gap = np.maximum(0.0, np.maximum(self.bmin[a] - self.bmax[b], self.bmin[b] - self.bmax[a]))
+        return float(sqnorm(gap))
+
     def diam(self, c: int) -> float:
-        return float(np.linalg.norm(self.bmax[c] - self.bmin[c]))
+        return float(np.sqrt(self.diam2(c)))
 
     def dist(self, a: int, b: int) -> float:
-        gap = np.maximum(0.0, np.maximum(self.bmin[a] - self.bmax[b], self.bmin[b] - self.bmax[a]))
-        return float(np.linalg.norm(gap))
+        return float(np.sqrt(self.dist2(a, b)))
 
 
 def admissible(T: ClusterTree, a: int, b: int, eta: float) -> bool:
-    d = T.dist(a, b)
-    return d > 0.0 and min(T.diam(a), T.diam(b)) <= eta * d
+    d2 = T.dist2(a, b)
+    return d2 > 0.0 and min(T.diam2(a), T.diam2(b)) <= (eta * eta) * d2
 
 
 def block_tree(T: ClusterTree, eta: float):

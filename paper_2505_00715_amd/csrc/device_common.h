@@ -1,0 +1,254 @@
+// Device-side building blocks shared by the library's kernels: complex
+// arithmetic, wave64 reductions, the panel table, and evaluation of the
+// Laplace-domain single-layer entries V(s)[i, j] (three quadrature tiers).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gcq {
+
+constexpr int WAVE = 64;
+constexpr int NQ_FAR = 7;       // 7-point degree-5 rule
+constexpr int NQ_NEAR = 112;    // 7 points on 16 sub-triangles
+constexpr int NGL = 16;         // Gauss-Legendre points of the self panel
+
+template <typename T>
+struct cpx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {  // conj(a) * b
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ T cabs2(cpx<T> a) {
+  return a.re * a.re + a.im * a.im;
+}
+
+// ---- wave64 reductions (every lane receives the result) --------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+// argmax of (val, idx) pairs: largest val, lowest idx among equal vals.
+// Lanes without a candidate pass val = -1.
+template <typename T>
+__device__ __forceinline__ void wave_argmax(T& val, int& idx) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T ov = __shfl_xor(val, o, WAVE);
+    int oi = __shfl_xor(idx, o, WAVE);
+    if (ov > val || (ov == val && oi < idx)) {
+      val = ov;
+      idx = oi;
+    }
+  }
+}
+
+// ---- constant tables (filled by the host at context creation) --------------
+struct Consts {
+  double gl_x[NGL], gl_w[NGL];        // Gauss-Legendre on [0, 1]
+  double nb[NQ_NEAR][3];              // barycentric points of the near rule
+  double nw[NQ_NEAR];                 // weights (sum 1) of the near rule
+};
+
+// ---- panel table (cluster-permuted order, structure of arrays) --------------
+// q64/q32 hold 28 arrays of n: qx[7], qy[7], qz[7], qw[7]; qw already
+// includes the panel area and 1/(4 pi).  c32/q32 are coordinates relative to
+// the mesh centre (`shift`), in float.
+struct Tab {
+  int n;
+  const double* cen;   // 3n: x[], y[], z[]
+  const double* h2;    // n: squared longest edge
+  const double* vert;  // 9n: v0x v0y v0z v1x ... v2z
+  const double* area;  // n
+  const double* q64;   // 28n
+  const float* c32;    // 3n
+  const float* q32;    // 28n
+  const Consts* K;
+};
+
+constexpr double INV4PI = 0.079577471545947667884441881686257181;
+
+// exp(-sigma r) / r  with sigma = s / c complex, for float or double
+__device__ __forceinline__ cpx<float> green(float r, float sr, float si) {
+  float e = expf(-sr * r) / r;
+  float sn, cs;
+  sincosf(si * r, &sn, &cs);
+  return {e * cs, -e * sn};
+}
+__device__ __forceinline__ cpx<double> green(double r, double sr, double si) {
+  double e = exp(-sr * r) / r;
+  double sn, cs;
+  sincos(si * r, &sn, &cs);
+  return {e * cs, -e * sn};
+}
+
+// far tier: 7-point rule, in T arithmetic
+template <typename T>
+struct FarData;
+template <>
+struct FarData<float> {
+  static __device__ __forceinline__ const float* q(const Tab& t) { return t.q32; }
+  static __device__ __forceinline__ const float* c(const Tab& t) { return t.c32; }
+};
+template <>
+struct FarData<double> {
+  static __device__ __forceinline__ const double* q(const Tab& t) { return t.q64; }
+  static __device__ __forceinline__ const double* c(const Tab& t) { return t.cen; }
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> far_entry(const Tab& t, T xi, T yi, T zi, int pj, T sr, T si) {
+  const T* q = FarData<T>::q(t);
+  const int n = t.n;
+  cpx<T> acc = {T(0), T(0)};
+#pragma unroll
+  for (int a = 0; a < NQ_FAR; ++a) {
+    T dx = xi - q[(a)*n + pj];
+    T dy = yi - q[(7 + a) * n + pj];
+    T dz = zi - q[(14 + a) * n + pj];
+    T w = q[(21 + a) * n + pj];
+    T r = sqrt(dx * dx + dy * dy + dz * dz);
+    cpx<T> g = green(r, sr, si);
+    acc.re += w * g.re;
+    acc.im += w * g.im;
+  }
+  return acc;
+}
+
+// near tier: 7-point rule on 16 sub-triangles, double
+__device__ __forceinline__ cpx<double> near_entry(const Tab& t, int pi, int pj, double sr,
+                                                   double si) {
+  const int n = t.n;
+  const double xi = t.cen[pi], yi = t.cen[n + pi], zi = t.cen[2 * n + pi];
+  double v[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) v[c] = t.vert[c * n + pj];
+  const double wa = t.area[pj] * INV4PI;
+  cpx<double> acc = {0.0, 0.0};
+  for (int a = 0; a < NQ_NEAR; ++a) {
+    const double b0 = t.K->nb[a][0], b1 = t.K->nb[a][1], b2 = t.K->nb[a][2];
+    double px = b0 * v[0] + b1 * v[3] + b2 * v[6];
+    double py = b0 * v[1] + b1 * v[4] + b2 * v[7];
+    double pz = b0 * v[2] + b1 * v[5] + b2 * v[8];
+    double dx = xi - px, dy = yi - py, dz = zi - pz;
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    cpx<double> g = green(r, sr, si);
+    double w = t.K->nw[a] * wa;
+    acc.re += w * g.re;
+    acc.im += w * g.im;
+  }
+  return acc;
+}
+
+// (1 - exp(-a)) / a for complex a; series below |a| = 1e-3
+__device__ __forceinline__ cpx<double> phi_c(double ar, double ai) {
+  double m2 = ar * ar + ai * ai;
+  if (m2 < 1e-6) {
+    // 1 - a/2 + a^2/6 - a^3/24
+    double a2r = ar * ar - ai * ai, a2i = 2.0 * ar * ai;
+    double a3r = a2r * ar - a2i * ai, a3i = a2r * ai + a2i * ar;
+    return {1.0 - 0.5 * ar + a2r / 6.0 - a3r / 24.0, -0.5 * ai + a2i / 6.0 - a3i / 24.0};
+  }
+  double e = exp(-ar);
+  double sn, cs;
+  sincos(ai, &sn, &cs);
+  double nr = 1.0 - e * cs, ni = e * sn;  // 1 - exp(-a)
+  // (nr + i ni) / (ar + i ai)
+  return {(nr * ar + ni * ai) / m2, (ni * ar - nr * ai) / m2};
+}
+
+// self tier: polar coordinates about the centroid; radial integral exact,
+// angle by 16-point Gauss-Legendre over each edge's angular range
+__device__ __forceinline__ cpx<double> self_entry(const Tab& t, int p, double sr, double si) {
+  const int n = t.n;
+  const double x[3] = {t.cen[p], t.cen[n + p], t.cen[2 * n + p]};
+  double v[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) v[c] = t.vert[c * n + p];
+  cpx<double> acc = {0.0, 0.0};
+  for (int e = 0; e < 3; ++e) {
+    const double* P = v + 3 * e;
+    const double* Q = v + 3 * ((e + 1) % 3);
+    double ex = Q[0] - P[0], ey = Q[1] - P[1], ez = Q[2] - P[2];
+    double el = sqrt(ex * ex + ey * ey + ez * ez);
+    ex /= el; ey /= el; ez /= el;
+    double px = P[0] - x[0], py = P[1] - x[1], pz = P[2] - x[2];
+    double qx = Q[0] - x[0], qy = Q[1] - x[1], qz = Q[2] - x[2];
+    double tp = px * ex + py * ey + pz * ez;
+    double tq = qx * ex + qy * ey + qz * ez;
+    double fx = px - tp * ex, fy = py - tp * ey, fz = pz - tp * ez;
+    double d = sqrt(fx * fx + fy * fy + fz * fz);
+    double ta = atan2(tp, d), tb = atan2(tq, d);
+    double span = tb - ta;
+    cpx<double> part = {0.0, 0.0};
+    for (int g = 0; g < NGL; ++g) {
+      double th = ta + span * t.K->gl_x[g];
+      double R = d / cos(th);
+      cpx<double> f = phi_c(sr * R, si * R);
+      double w = t.K->gl_w[g] * R;
+      part.re += w * f.re;
+      part.im += w * f.im;
+    }
+    acc.re += span * part.re;
+    acc.im += span * part.im;
+  }
+  acc.re *= INV4PI;
+  acc.im *= INV4PI;
+  return acc;
+}
+
+// tier decision in double on squared lengths: near iff |x_i - x_j|^2 < 4 h_j^2
+__device__ __forceinline__ bool is_near(const Tab& t, int pi, int pj) {
+#pragma clang fp contract(off)
+  const int n = t.n;
+  double dx = t.cen[pi] - t.cen[pj];
+  double dy = t.cen[n + pi] - t.cen[n + pj];
+  double dz = t.cen[2 * n + pi] - t.cen[2 * n + pj];
+  double d2 = dx * dx + dy * dy + dz * dz;
+  return d2 < 4.0 * t.h2[pj];
+}
+
+// entry at internal positions (pi, pj), frequency sigma = s / c; far tier in T
+// unless `all_far` says the caller's block has no self/near pairs
+template <typename T>
+__device__ __forceinline__ cpx<T> entry(const Tab& t, int pi, int pj, double sr, double si,
+                                        bool all_far) {
+  if (!all_far) {
+    if (pi == pj) {
+      cpx<double> e = self_entry(t, pi, sr, si);
+      return {T(e.re), T(e.im)};
+    }
+    if (is_near(t, pi, pj)) {
+      cpx<double> e = near_entry(t, pi, pj, sr, si);
+      return {T(e.re), T(e.im)};
+    }
+  }
+  const T* c = FarData<T>::c(t);
+  const int n = t.n;
+  return far_entry<T>(t, c[pi], c[n + pi], c[2 * n + pi], pj, T(sr), T(si));
+}
+
+}  // namespace gcq

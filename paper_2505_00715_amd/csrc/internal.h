@@ -1,0 +1,201 @@
+// Host-side state of a gcqbem context and helpers shared by the API files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gcqbem.h"
+#include "device_common.h"
+
+namespace gcq {
+
+// ---- errors -------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+
+#define GCQ_HIP(call)                                                            \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return ::gcq::fail(GCQ_ERR_HIP, "%s failed: %s (%s:%d)", #call,            \
+                         hipGetErrorString(e_), __FILE__, __LINE__);             \
+  } while (0)
+
+#define GCQ_TRY(call)          \
+  do {                         \
+    int s_ = (call);           \
+    if (s_ < 0) return s_;     \
+  } while (0)
+
+// ---- device memory owned by the library ----------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // (re)allocate to at least `n` bytes; contents are not preserved
+  int ensure(size_t n) {
+    if (n <= bytes && p) return GCQ_OK;
+    release();
+    if (n == 0) n = 256;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return fail(GCQ_ERR_NOMEM, "hipMalloc of %zu bytes failed: %s", n, hipGetErrorString(e));
+    }
+    bytes = n;
+    return GCQ_OK;
+  }
+  template <typename T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+template <typename T>
+int upload(DevBuf& b, const std::vector<T>& v, hipStream_t st) {
+  GCQ_TRY(b.ensure(v.size() * sizeof(T)));
+  if (!v.empty())
+    GCQ_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return GCQ_OK;
+}
+
+// ---- tree ------------------------------------------------------------------------
+struct Cluster {
+  int begin, end, son0, son1, depth;
+  double bmin[3], bmax[3];
+};
+struct Block {
+  int row, col;      // cluster ids
+  bool admissible;
+  bool all_far;      // no self or near-tier pair inside (guaranteed by box distance)
+};
+
+// ---- per-frequency H-matrices (aca_blocks) ---------------------------------------------
+struct HFaces {
+  bool valid = false;
+  int precision = GCQ_C128;
+  std::vector<int> freqs;        // representative frequencies held (positions in K order)
+  std::vector<int> fslot;        // L -> slot in freqs or -1
+  // far: per (far block f, slot q): offset (in complex elements) and rank
+  std::vector<int64_t> off;      // n_far * nslot
+  std::vector<int> rank;         // n_far * nslot
+  DevBuf d_off, d_rank;
+  DevBuf factors;                // pool: U (m x r) then V (n x r), column-major, per pair
+  // near: dense blocks per slot, column-major |I| x |J|
+  std::vector<int64_t> near_off; // n_near (offset within one slot)
+  int64_t near_slot_elems = 0;
+  DevBuf d_near_off;
+  DevBuf near;                   // nslot * near_slot_elems
+  int64_t storage_bytes = 0;
+};
+
+// ---- 3D-ACA result --------------------------------------------------------------------
+struct Faces3D {
+  bool valid = false;
+  int precision = GCQ_C128;
+  int nK = 0;
+  // per block: rank r_b, first term index into the term arrays
+  std::vector<int> brank, bterm;
+  // per term: frequency position, slice rank (far) or -1 (near), offset of the
+  // slice data (complex elements), offset of the fiber (complex elements)
+  std::vector<int> tfreq, trank;
+  std::vector<int64_t> toff;
+  DevBuf d_brank, d_bterm, d_trank, d_toff;
+  DevBuf slices;                 // far: U (m x r) then V (n x r); near: dense m x n
+  DevBuf fibers;                 // per term: nK complex
+  int64_t storage_bytes = 0;
+  int64_t dense_bytes = 0;
+};
+
+// ---- rank model ---------------------------------------------------------------------
+struct RankModel {
+  bool trained = false;
+  std::vector<float> params;     // 4545
+  float mean[5] = {0, 0, 0, 0, 0}, stdv[5] = {1, 1, 1, 1, 1};
+  DevBuf d_params;
+};
+
+}  // namespace gcq
+
+struct gcq_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::map<std::string, double> kernel_ms;
+
+  // mesh
+  bool have_mesh = false;
+  int n = 0;
+  int64_t nv = 0;
+  double c = 1.0;
+  double shift[3] = {0, 0, 0};
+  std::vector<double> cen, h2, area, vert;  // original order (host)
+
+  // frequencies
+  bool have_freq = false;
+  int L = 0;
+  std::vector<std::complex<double>> s;
+  std::vector<int> rep;    // L -> representative frequency index
+  std::vector<int> conj;   // L -> 1 if applied through the conjugate partner
+  std::vector<int> K;      // distinct representatives, increasing
+  std::vector<int> kpos;   // frequency index -> position of its representative in K
+
+  // tree
+  bool have_tree = false;
+  int leaf = 0;
+  double eta = 0;
+  std::vector<int> perm, iperm;
+  std::vector<gcq::Cluster> clusters;
+  std::vector<gcq::Block> blocks;
+  std::vector<int> far_ids, near_ids;       // block ids
+  int depth = 0;
+
+  // device tables (permuted order)
+  gcq::DevBuf d_cen, d_h2, d_vert, d_area, d_q64, d_c32, d_q32, d_consts, d_perm, d_iperm;
+  gcq::DevBuf d_blk;                         // per block: rb, re, cb, ce, flags (int32 x 5)
+
+  gcq::HFaces H;
+  gcq::Faces3D F;
+  gcq::RankModel M;
+
+  // scratch
+  gcq::DevBuf scratchA, scratchB, scratchC, scratchD;
+
+  gcq::Tab tab() const {
+    gcq::Tab t;
+    t.n = n;
+    t.cen = d_cen.as<double>();
+    t.h2 = d_h2.as<double>();
+    t.vert = d_vert.as<double>();
+    t.area = d_area.as<double>();
+    t.q64 = d_q64.as<double>();
+    t.c32 = d_c32.as<float>();
+    t.q32 = d_q32.as<float>();
+    t.K = d_consts.as<gcq::Consts>();
+    return t;
+  }
+};
+
+namespace gcq {
+// contexts created with device -1 hold geometry, trees and features only
+#define GCQ_NEED_DEVICE(ctx) \
+  do { if ((ctx)->device < 0) return ::gcq::fail(GCQ_ERR_STATE, "host-only context"); } while (0)
+int check_device_ptr(gcq_context* ctx, const void* p, const char* what);
+int timed_begin(gcq_context* ctx);
+double timed_end(gcq_context* ctx, const char* name);
+inline int csize(int precision) { return precision == GCQ_C128 ? 16 : 8; }
+}  // namespace gcq

@@ -1,0 +1,86 @@
+"""The C ABI without a GPU: the library loads and exports every entry point
+include/gcqbem.h declares; a host-only context builds exactly the oracle's
+cluster and block trees; argument and call-order errors are reported."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2505_00715_amd as g
+from synth import configs, freq, mesh
+from tests._oracle_tree_blocks import oracle_tree
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "gcqbem.h")
+
+
+def test_exports_every_declared_symbol():
+    decl = set(re.findall(r"GCQ_API\s+[\w\s\*]+?\b(gcq_\w+)\s*\(", open(HEADER).read()))
+    assert len(decl) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", g.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (gcq_\w+)", out))
+    assert decl <= exported, decl - exported
+    for name in decl:
+        getattr(g.lib, name)
+
+
+@pytest.mark.parametrize("name,leaf,eta", [("sphere320", 64, 1.0), ("sphere320", 16, 0.8),
+                                           ("sphere5120", 64, 1.0), ("housing3k", 32, 1.0),
+                                           ("housing3k", 20, 0.8)])
+def test_host_tree_matches_oracle_exactly(name, leaf, eta):
+    cfg = configs.get(name)
+    ctx = g.Context(-1)
+    ctx.upload_mesh(cfg["xyz"], cfg["tri"], cfg["c"])
+    info = ctx.build_cluster_tree(leaf, eta)
+    perm, blocks = ctx.get_tree()
+    _, T, B, operm, oblocks = oracle_tree(cfg["xyz"], cfg["tri"], leaf, eta)
+    assert np.array_equal(perm, operm)
+    assert np.array_equal(blocks, oblocks)
+    assert info.n_blocks == len(B) and info.n_far == int(oblocks[:, 4].sum())
+    assert info.n_clusters == len(T.begin)
+    ctx.destroy()
+
+
+def test_cube_tree_matches_oracle():
+    xyz, tri = mesh.unit_cube(3)
+    ctx = g.Context(-1)
+    ctx.upload_mesh(xyz, tri, 1.0)
+    ctx.build_cluster_tree(20, 0.8)
+    perm, blocks = ctx.get_tree()
+    _, _, _, operm, oblocks = oracle_tree(xyz, tri, 20, 0.8)
+    assert np.array_equal(perm, operm) and np.array_equal(blocks, oblocks)
+
+
+def test_argument_and_state_errors():
+    ctx = g.Context(-1)
+    xyz, tri = mesh.icosphere(1)
+    with pytest.raises(g.GcqError) as e:
+        ctx.build_cluster_tree(16, 1.0)
+    assert e.value.code == -4                       # GCQ_ERR_STATE: no mesh yet
+    bad = tri.copy(); bad[0, 0] = len(xyz)
+    with pytest.raises(g.GcqError) as e:
+        ctx.upload_mesh(xyz, bad, 1.0)
+    assert e.value.code == -1
+    with pytest.raises(g.GcqError) as e:
+        ctx.upload_mesh(xyz, tri, -1.0)
+    assert e.value.code == -1
+    deg = tri.copy(); deg[0, 2] = deg[0, 1]         # zero-area triangle
+    with pytest.raises(g.GcqError) as e:
+        ctx.upload_mesh(xyz, deg, 1.0)
+    assert e.value.code == -5
+    ctx.upload_mesh(xyz, tri, 1.0)
+    with pytest.raises(g.GcqError) as e:
+        ctx.set_frequencies(np.array([1.0 + 1j, -0.5 + 0j]))
+    assert e.value.code == -1                       # Re s <= 0
+    ctx.set_frequencies(freq.bdf2_circle(8, 0.05, 0.5))
+    with pytest.raises(g.GcqError) as e:
+        ctx.build_cluster_tree(0, 1.0)
+    assert e.value.code == -1
+    ctx.build_cluster_tree(16, 1.0)
+    # device work on a host-only context is a state error
+    rc = g.lib.gcq_aca3d(ctx._h, 1e-5, 1e-5, 10, 0, 0, None)
+    assert rc < 0
+    assert g.lib.gcq_destroy(None) == 0
+    ctx.destroy()
