@@ -69,6 +69,9 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python paper_2505_00715_amd/build.py` (there is no CPU fallback)")
+    # torch first: its bundled HIP runtime (soname libamdhip64.so.7) then also
+    # serves this library, so that one HIP runtime drives the process
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, I32, I64, D, U32 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint32
     sig = {

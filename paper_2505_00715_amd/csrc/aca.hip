@@ -1,0 +1,435 @@
+// Batched ACA of admissible blocks across frequencies, recompression, and the
+// per-frequency H-matrix faces (Sec. 4).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+#include "lowrank.h"
+
+namespace gcq {
+
+// ---- 2D ACA kernels: one wave per (block, frequency) pair ------------------------
+template <typename T>
+struct PlainEntry {
+  const Tab* tab;
+  int rb, cb;
+  double sr, si;
+  bool all_far;
+  __device__ void prep_row(int) {}
+  __device__ void prep_col(int) {}
+  __device__ cpx<T> operator()(int i, int j) const {
+    return entry<T>(*tab, rb + i, cb + j, sr, si, all_far);
+  }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(64) aca_kernel(Tab tab, const PairDesc* __restrict__ pairs,
+                                                 const int* __restrict__ order, int npairs,
+                                                 unsigned char* __restrict__ ws, double tol,
+                                                 int max_rank, int* __restrict__ out_rank,
+                                                 int* __restrict__ out_status,
+                                                 int* __restrict__ counter) {
+  __shared__ AcaShared<T> sm;
+  const int lane = threadIdx.x;
+  for (;;) {
+    int idx = 0;
+    if (lane == 0) idx = atomicAdd(counter, 1);
+    idx = __shfl(idx, 0, WAVE);
+    if (idx >= npairs) break;
+    const int pid = order ? order[idx] : idx;
+    const PairDesc d = pairs[pid];
+    cpx<T>* U = reinterpret_cast<cpx<T>*>(ws + d.ws);
+    cpx<T>* W = U + int64_t(d.cap) * d.m;
+    cpx<double>* GU = reinterpret_cast<cpx<double>*>(ws + d.ws + ws_gram_off<T>(d.cap, d.m, d.n));
+    PlainEntry<T> ent{&tab, d.rb, d.cb, d.sr, d.si, d.all_far != 0};
+    int status = 0;
+    const int k = aca_wave<T>(ent, d.m, d.n, d.cap, max_rank, tol, U, W, GU, GU + d.cap * d.cap,
+                              sm, status);
+    if (lane == 0) {
+      out_rank[pid] = k;
+      out_status[pid] = status;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) recompress_kernel(const PairDesc* __restrict__ pairs,
+                                                        int npairs, unsigned char* __restrict__ ws,
+                                                        const int* __restrict__ rank_in,
+                                                        int* __restrict__ out_t, double tol,
+                                                        int do_recompress, unsigned char* __restrict__ jws) {
+  __shared__ cpx<double> mats[4 * 16 * 16];
+  __shared__ RecompShared rs;
+  for (int pid = blockIdx.x; pid < npairs; pid += gridDim.x) {
+    __syncthreads();
+    const PairDesc d = pairs[pid];
+    const int k = rank_in[pid], cap = d.cap;
+    cpx<double>* GU = reinterpret_cast<cpx<double>*>(ws + d.ws + ws_gram_off<T>(cap, d.m, d.n));
+    cpx<double>* A = k <= 16 ? mats
+                             : reinterpret_cast<cpx<double>*>(jws) + int64_t(blockIdx.x) * 4 * 64 * 64;
+    const int t = recompress_wave(k, cap, GU, GU + cap * cap, tol, do_recompress != 0, A, rs);
+    if (threadIdx.x == 0) out_t[pid] = t;
+  }
+}
+
+// Ubar = U CU, Vbar = conj(W) CV into the compact pool
+template <typename T>
+__global__ void __launch_bounds__(256) apply_kernel(const PairDesc* __restrict__ pairs, int npairs,
+                                                    const unsigned char* __restrict__ ws,
+                                                    const int* __restrict__ rank_in,
+                                                    const int* __restrict__ tcut,
+                                                    const int64_t* __restrict__ out_off,
+                                                    cpx<T>* __restrict__ pool) {
+  for (int pid = blockIdx.x; pid < npairs; pid += gridDim.x) {
+    const PairDesc d = pairs[pid];
+    const int k = rank_in[pid], t = tcut[pid], cap = d.cap, m = d.m, n = d.n;
+    if (t == 0) continue;
+    const cpx<T>* U = reinterpret_cast<const cpx<T>*>(ws + d.ws);
+    const cpx<double>* CU =
+        reinterpret_cast<const cpx<double>*>(ws + d.ws + ws_gram_off<T>(cap, m, n));
+    cpx<T>* OU = pool + out_off[pid];
+    apply_factors<T>(k, t, m, n, U, U + int64_t(cap) * m, CU, CU + cap * cap, OU,
+                     OU + int64_t(t) * m, threadIdx.x, blockDim.x);
+  }
+}
+
+// ---- dense near-field blocks at one frequency --------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) near_kernel(Tab tab, const int* __restrict__ blk,
+                                                   const int* __restrict__ near_ids,
+                                                   const int64_t* __restrict__ near_off, int nnear,
+                                                   double sr, double si, cpx<T>* __restrict__ out) {
+  for (int b = blockIdx.x; b < nnear; b += gridDim.x) {
+  const int id = near_ids[b];
+  const int rb = blk[5 * id], re = blk[5 * id + 1], cb = blk[5 * id + 2], ce = blk[5 * id + 3];
+  const int all_far = (blk[5 * id + 4] >> 1) & 1;
+  const int m = re - rb, n = ce - cb;
+  cpx<T>* o = out + near_off[b];
+  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
+    const int r = e % m, c = e / m;  // column-major
+    o[e] = entry<T>(tab, rb + r, cb + c, sr, si, all_far != 0);
+  }
+  }
+}
+
+__global__ void zero_int(int* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// -------------------------------------------------------------------------------------
+struct AcaRun {
+  std::vector<PairDesc> desc;
+  std::vector<int> far_index;   // far block position (0..n_far-1) per pair
+  std::vector<int> slot;        // frequency slot per pair
+};
+
+template <typename T>
+static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vector<int>& order,
+                         double tol, int max_rank, bool recompress, std::vector<int>& rank_aca,
+                         std::vector<int>& rank_out, std::vector<int>& status,
+                         std::vector<int64_t>& out_off, DevBuf& pool, int64_t& pool_used,
+                         double& ms_aca, double& ms_rec, double& ms_apply, int64_t budget) {
+  hipStream_t st = ctx->stream;
+  const int np = int(desc.size());
+  rank_aca.assign(np, 0);
+  rank_out.assign(np, 0);
+  status.assign(np, 0);
+  out_off.assign(np, -1);
+  int dev_cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
+  // chunks in work-list order, each within the workspace budget
+  size_t pos = 0;
+  std::vector<int64_t> pend_off;
+  while (pos < order.size()) {
+    std::vector<int> chunk;
+    int64_t wsz = 0;
+    while (pos < order.size()) {
+      PairDesc& d = desc[order[pos]];
+      int64_t b = ws_bytes<T>(d.cap, d.m, d.n);
+      if (!chunk.empty() && wsz + b > budget) break;
+      d.ws = wsz;
+      wsz += b;
+      chunk.push_back(order[pos]);
+      ++pos;
+    }
+    const int nc = int(chunk.size());
+    std::vector<PairDesc> cd(nc);
+    for (int a = 0; a < nc; ++a) cd[a] = desc[chunk[a]];
+    GCQ_TRY(ctx->scratchA.ensure(size_t(wsz) + 256));
+    GCQ_TRY(upload(ctx->scratchB, cd, st));
+    GCQ_TRY(ctx->scratchC.ensure(sizeof(int) * (3 * size_t(nc) + 8)));
+    int* d_rank = ctx->scratchC.as<int>();
+    int* d_status = d_rank + nc;
+    int* d_t = d_status + nc;
+    int* d_counter = d_t + nc;
+    hipLaunchKernelGGL(zero_int, dim3(1), dim3(64), 0, st, d_counter, 8);
+    const int grid = std::min(nc, dev_cus * 16);
+    GCQ_TRY(timed_begin(ctx));
+    hipLaunchKernelGGL(aca_kernel<T>, dim3(grid), dim3(64), 0, st, ctx->tab(),
+                       ctx->scratchB.as<PairDesc>(), (const int*)nullptr, nc,
+                       ctx->scratchA.as<unsigned char>(), tol, max_rank, d_rank, d_status,
+                       d_counter);
+    GCQ_HIP(hipGetLastError());
+    ms_aca += timed_end(ctx, "aca");
+    // recompression; matrices above 32 terms live in global scratch
+    const int rgrid = std::min(nc, 4096);
+    GCQ_TRY(ctx->scratchD.ensure(size_t(rgrid) * 4 * 64 * 64 * 16));
+    GCQ_TRY(timed_begin(ctx));
+    hipLaunchKernelGGL(recompress_kernel<T>, dim3(rgrid), dim3(64), 0, st,
+                       ctx->scratchB.as<PairDesc>(), nc, ctx->scratchA.as<unsigned char>(),
+                       d_rank, d_t, tol, recompress ? 1 : 0, ctx->scratchD.as<unsigned char>());
+    GCQ_HIP(hipGetLastError());
+    ms_rec += timed_end(ctx, "recompress");
+    std::vector<int> hr(nc), hs(nc), ht(nc);
+    GCQ_HIP(hipMemcpy(hr.data(), d_rank, sizeof(int) * nc, hipMemcpyDeviceToHost));
+    GCQ_HIP(hipMemcpy(hs.data(), d_status, sizeof(int) * nc, hipMemcpyDeviceToHost));
+    GCQ_HIP(hipMemcpy(ht.data(), d_t, sizeof(int) * nc, hipMemcpyDeviceToHost));
+    // offsets in the pool (elements), in chunk order; the pool grows by copy
+    std::vector<int64_t> off(nc);
+    int64_t need = pool_used;
+    for (int a = 0; a < nc; ++a) {
+      off[a] = need;
+      need += int64_t(ht[a]) * (cd[a].m + cd[a].n);
+    }
+    const size_t esz = sizeof(cpx<T>);
+    if (size_t(need) * esz > pool.bytes) {
+      DevBuf bigger;
+      GCQ_TRY(bigger.ensure(std::max(size_t(need) * esz, pool.bytes * 3 / 2) + 256));
+      if (pool_used > 0)
+        GCQ_HIP(hipMemcpyAsync(bigger.p, pool.p, size_t(pool_used) * esz,
+                               hipMemcpyDeviceToDevice, st));
+      GCQ_HIP(hipStreamSynchronize(st));
+      std::swap(bigger.p, pool.p);
+      std::swap(bigger.bytes, pool.bytes);
+    }
+    GCQ_TRY(upload(ctx->scratchD, off, st));  // jacobi scratch no longer needed
+    GCQ_TRY(timed_begin(ctx));
+    hipLaunchKernelGGL(apply_kernel<T>, dim3(std::min(nc, 65536)), dim3(256), 0, st,
+                       ctx->scratchB.as<PairDesc>(), nc, ctx->scratchA.as<unsigned char>(), d_rank,
+                       d_t, ctx->scratchD.as<int64_t>(), pool.as<cpx<T>>());
+    GCQ_HIP(hipGetLastError());
+    ms_apply += timed_end(ctx, "apply");
+    pool_used = need;
+    for (int a = 0; a < nc; ++a) {
+      rank_aca[chunk[a]] = hr[a];
+      status[chunk[a]] = hs[a];
+      rank_out[chunk[a]] = ht[a];
+      out_off[chunk[a]] = off[a];
+    }
+  }
+  return GCQ_OK;
+}
+
+}  // namespace gcq
+
+using namespace gcq;
+
+extern "C" {
+
+GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_fidx, double tol,
+                           int32_t max_rank, int32_t precision, uint32_t flags,
+                           gcq_aca_stats* stats) {
+  if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
+  GCQ_NEED_DEVICE(ctx);
+  if (!ctx->have_tree || !ctx->have_freq)
+    return fail(GCQ_ERR_STATE, "upload mesh, frequencies and build the tree first");
+  if (precision != GCQ_C128 && precision != GCQ_C64)
+    return fail(GCQ_ERR_ARG, "unknown precision %d", precision);
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(GCQ_ERR_ARG, "tol must be >= 0");
+  if (max_rank < 1 || max_rank > 64) return fail(GCQ_ERR_ARG, "max_rank must be in 1..64");
+  GCQ_HIP(hipSetDevice(ctx->device));
+  HFaces& H = ctx->H;
+  H.valid = false;
+  // representatives to approximate
+  std::vector<int> fr;
+  if (freq_idx && n_fidx > 0) {
+    for (int a = 0; a < n_fidx; ++a) {
+      int k = freq_idx[a];
+      if (k < 0 || k >= ctx->L) return fail(GCQ_ERR_ARG, "frequency index out of range");
+      if (ctx->rep[k] != k) return fail(GCQ_ERR_ARG, "frequency %d is not a representative", k);
+      fr.push_back(k);
+    }
+  } else {
+    fr = ctx->K;
+  }
+  const int nslot = int(fr.size());
+  const int nfar = int(ctx->far_ids.size());
+  H.precision = precision;
+  H.freqs = fr;
+  H.fslot.assign(ctx->L, -1);
+  for (int q = 0; q < nslot; ++q) H.fslot[fr[q]] = q;
+  // pair descriptors: (far block f, slot q) at index q * nfar + f
+  std::vector<PairDesc> desc(size_t(nslot) * nfar);
+  for (int q = 0; q < nslot; ++q) {
+    std::complex<double> sg = ctx->s[fr[q]] / ctx->c;
+    for (int f = 0; f < nfar; ++f) {
+      const Block& B = ctx->blocks[ctx->far_ids[f]];
+      const Cluster& A = ctx->clusters[B.row];
+      const Cluster& C = ctx->clusters[B.col];
+      PairDesc& d = desc[size_t(q) * nfar + f];
+      d.rb = A.begin;
+      d.m = A.end - A.begin;
+      d.cb = C.begin;
+      d.n = C.end - C.begin;
+      if (d.m > ACA_MAXM) return fail(GCQ_ERR_UNSUPPORTED, "block with %d rows exceeds %d", d.m, ACA_MAXM);
+      d.all_far = B.all_far ? 1 : 0;
+      d.cap = std::min(std::min(d.m, d.n), int(max_rank));
+      d.sr = sg.real();
+      d.si = sg.imag();
+      d.ws = 0;
+    }
+  }
+  std::vector<int> order(desc.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::vector<int> rank_aca, rank_out, status;
+  std::vector<int64_t> off;
+  int64_t pool_used = 0;
+  double ms_aca = 0, ms_rec = 0, ms_apply = 0;
+  const bool rec = (flags & GCQ_FLAG_RECOMPRESS) != 0;
+  const int64_t budget = int64_t(6) << 30;
+  int rc;
+  if (flags & GCQ_FLAG_PER_FREQ_LAUNCH) {
+    // baseline: one chunk (launch sequence) per frequency, natural order
+    rank_aca.assign(desc.size(), 0);
+    rank_out.assign(desc.size(), 0);
+    status.assign(desc.size(), 0);
+    off.assign(desc.size(), 0);
+    for (int q = 0; q < nslot; ++q) {
+      std::vector<PairDesc> dq(desc.begin() + size_t(q) * nfar, desc.begin() + size_t(q + 1) * nfar);
+      std::vector<int> oq(nfar);
+      std::iota(oq.begin(), oq.end(), 0);
+      std::vector<int> ra, ro, stt;
+      std::vector<int64_t> of;
+      rc = precision == GCQ_C128
+               ? run_aca_pairs<double>(ctx, dq, oq, tol, max_rank, rec, ra, ro, stt, of, H.factors,
+                                       pool_used, ms_aca, ms_rec, ms_apply, budget)
+               : run_aca_pairs<float>(ctx, dq, oq, tol, max_rank, rec, ra, ro, stt, of, H.factors,
+                                      pool_used, ms_aca, ms_rec, ms_apply, budget);
+      if (rc < 0) return rc;
+      for (int f = 0; f < nfar; ++f) {
+        rank_aca[size_t(q) * nfar + f] = ra[f];
+        rank_out[size_t(q) * nfar + f] = ro[f];
+        status[size_t(q) * nfar + f] = stt[f];
+        off[size_t(q) * nfar + f] = of[f];
+      }
+    }
+  } else {
+    rc = precision == GCQ_C128
+             ? run_aca_pairs<double>(ctx, desc, order, tol, max_rank, rec, rank_aca, rank_out,
+                                     status, off, H.factors, pool_used, ms_aca, ms_rec, ms_apply,
+                                     budget)
+             : run_aca_pairs<float>(ctx, desc, order, tol, max_rank, rec, rank_aca, rank_out,
+                                    status, off, H.factors, pool_used, ms_aca, ms_rec, ms_apply,
+                                    budget);
+    if (rc < 0) return rc;
+  }
+  // near field: dense blocks per frequency slot
+  const int nnear = int(ctx->near_ids.size());
+  H.near_off.assign(nnear, 0);
+  int64_t acc = 0;
+  for (int b = 0; b < nnear; ++b) {
+    const Block& B = ctx->blocks[ctx->near_ids[b]];
+    H.near_off[b] = acc;
+    acc += int64_t(ctx->clusters[B.row].end - ctx->clusters[B.row].begin) *
+           (ctx->clusters[B.col].end - ctx->clusters[B.col].begin);
+  }
+  H.near_slot_elems = acc;
+  const size_t esz = csize(precision);
+  GCQ_TRY(H.near.ensure(size_t(acc) * nslot * esz + 256));
+  std::vector<int32_t> nid(ctx->near_ids.begin(), ctx->near_ids.end());
+  GCQ_TRY(upload(H.d_near_off, H.near_off, ctx->stream));
+  GCQ_TRY(upload(ctx->scratchC, nid, ctx->stream));
+  GCQ_TRY(timed_begin(ctx));
+  for (int q = 0; q < nslot && nnear > 0; ++q) {
+    std::complex<double> sg = ctx->s[fr[q]] / ctx->c;
+    if (precision == GCQ_C128)
+      hipLaunchKernelGGL(near_kernel<double>, dim3(std::min(nnear, 65536)), dim3(256), 0, ctx->stream,
+                         ctx->tab(), ctx->d_blk.as<int>(), ctx->scratchC.as<int>(),
+                         H.d_near_off.as<int64_t>(), nnear, sg.real(), sg.imag(),
+                         H.near.as<cpx<double>>() + size_t(q) * acc);
+    else
+      hipLaunchKernelGGL(near_kernel<float>, dim3(std::min(nnear, 65536)), dim3(256), 0, ctx->stream,
+                         ctx->tab(), ctx->d_blk.as<int>(), ctx->scratchC.as<int>(),
+                         H.d_near_off.as<int64_t>(), nnear, sg.real(), sg.imag(),
+                         H.near.as<cpx<float>>() + size_t(q) * acc);
+  }
+  GCQ_HIP(hipGetLastError());
+  double ms_near = timed_end(ctx, "near");
+  // per (far block, slot) tables in [slot][far] order
+  H.off = off;
+  H.rank = rank_out;
+  GCQ_TRY(upload(H.d_off, H.off, ctx->stream));
+  GCQ_TRY(upload(H.d_rank, H.rank, ctx->stream));
+  GCQ_HIP(hipStreamSynchronize(ctx->stream));
+  H.storage_bytes = int64_t(esz) * (pool_used + acc * nslot);
+  H.valid = true;
+  ctx->kernel_ms["aca_blocks"] = ms_aca + ms_rec + ms_apply + ms_near;
+  ctx->kernel_ms["aca_total"] = ms_aca;
+  ctx->kernel_ms["recompress_total"] = ms_rec;
+  ctx->kernel_ms["apply_total"] = ms_apply;
+  int ncap = 0, rmax = 0;
+  int64_t rsum = 0, rasum = 0, nover = 0, ents = 0;
+  for (size_t p = 0; p < desc.size(); ++p) {
+    ncap += (status[p] & ST_CAPPED) != 0;
+    nover += (status[p] & ST_OVERFLOW) != 0;
+    rmax = std::max(rmax, rank_out[p]);
+    rsum += rank_out[p];
+    rasum += rank_aca[p];
+    ents += int64_t(rank_aca[p]) * (desc[p].m + desc[p].n);
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->n_pairs = int64_t(desc.size());
+    stats->aca_rank_sum = rasum;
+    stats->rank_sum = rsum;
+    stats->rank_max = rmax;
+    stats->n_capped = ncap;
+    stats->n_overflow = nover;
+    stats->entries = ents;
+    stats->storage_bytes = H.storage_bytes;
+    stats->device_ms = ms_aca + ms_rec + ms_apply;
+  }
+  return ncap > 0 ? GCQ_RANK_CAPPED : GCQ_OK;
+}
+
+GCQ_API int gcq_get_block_factors(gcq_context* ctx, int32_t block, int32_t freq, gcq_c128* U,
+                                  gcq_c128* V, int32_t cap, int32_t* rank) {
+  if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
+  if (!ctx->H.valid) return fail(GCQ_ERR_STATE, "run gcq_aca_blocks first");
+  if (block < 0 || block >= int(ctx->blocks.size()) || !ctx->blocks[block].admissible)
+    return fail(GCQ_ERR_ARG, "block %d is not an admissible block", block);
+  if (freq < 0 || freq >= ctx->L || ctx->H.fslot[freq] < 0)
+    return fail(GCQ_ERR_ARG, "frequency %d was not approximated", freq);
+  if (!U || !V || !rank) return fail(GCQ_ERR_ARG, "NULL output");
+  const int f = int(std::lower_bound(ctx->far_ids.begin(), ctx->far_ids.end(), block) -
+                    ctx->far_ids.begin());
+  const size_t pi = size_t(ctx->H.fslot[freq]) * ctx->far_ids.size() + f;
+  const int r = ctx->H.rank[pi];
+  *rank = r;
+  if (r > cap) return fail(GCQ_ERR_ARG, "rank %d exceeds cap %d", r, cap);
+  const Block& B = ctx->blocks[block];
+  const int m = ctx->clusters[B.row].end - ctx->clusters[B.row].begin;
+  const int n = ctx->clusters[B.col].end - ctx->clusters[B.col].begin;
+  const int64_t cnt = int64_t(r) * (m + n);
+  if (cnt == 0) return GCQ_OK;
+  std::vector<gcq_c128> tmp(cnt);
+  if (ctx->H.precision == GCQ_C128) {
+    GCQ_HIP(hipMemcpy(tmp.data(), ctx->H.factors.as<cpx<double>>() + ctx->H.off[pi],
+                      cnt * sizeof(gcq_c128), hipMemcpyDeviceToHost));
+  } else {
+    std::vector<cpx<float>> t32(cnt);
+    GCQ_HIP(hipMemcpy(t32.data(), ctx->H.factors.as<cpx<float>>() + ctx->H.off[pi],
+                      cnt * sizeof(cpx<float>), hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < cnt; ++e) tmp[e] = {t32[e].re, t32[e].im};
+  }
+  std::memcpy(U, tmp.data(), sizeof(gcq_c128) * int64_t(r) * m);
+  std::memcpy(V, tmp.data() + int64_t(r) * m, sizeof(gcq_c128) * int64_t(r) * n);
+  return GCQ_OK;
+}
+
+}  // extern "C"

@@ -113,8 +113,8 @@ struct Faces3D {
   // per term: frequency position, slice rank (far) or -1 (near), offset of the
   // slice data (complex elements), offset of the fiber (complex elements)
   std::vector<int> tfreq, trank;
-  std::vector<int64_t> toff;
-  DevBuf d_brank, d_bterm, d_trank, d_toff;
+  std::vector<int64_t> toff, tfoff;
+  DevBuf d_brank, d_bterm, d_trank, d_toff, d_tfoff;
   DevBuf slices;                 // far: U (m x r) then V (n x r); near: dense m x n
   DevBuf fibers;                 // per term: nK complex
   int64_t storage_bytes = 0;

@@ -1,0 +1,413 @@
+// Wave-level routines for the low-rank face of Sec. 4, shared by the per-
+// frequency ACA kernels and the 3D-ACA kernel.
+//
+// aca_wave: partially pivoted ACA of an entry function (one wave64).
+// recompress_wave: QR/SVD recompression of the ACA factors, carried out
+//   through their Gram matrices: with G_V = V^H V = Q L Q^H and
+//   B = L^{1/2} Q^H G_U Q L^{1/2} = Z S^2 Z^H, the truncated SVD of U V^H is
+//   (U Q L^{1/2} Z_t)(V Q L^{-1/2} Z_t)^H, because R_V = L^{1/2} Q^H satisfies
+//   R_V^H R_V = G_V (it plays the role of the triangular QR factor) and
+//   B = M^H M for the core M = R_U R_V^H.
+// apply_factors: forms the recompressed factors from the coefficients.
+#pragma once
+#include "device_common.h"
+
+namespace gcq {
+
+constexpr int ACA_MAXM = 16384;  // rows per block handled by the ACA routine
+
+struct PairDesc {
+  int rb, m, cb, n;   // internal positions: rows [rb, rb+m), columns [cb, cb+n)
+  int all_far;        // 1: no self/near-tier entry inside the block
+  int cap;            // capacity (terms) of the workspace
+  double sr, si;      // sigma = s / c
+  int64_t ws;         // workspace offset in bytes
+};
+
+// status bits of one ACA
+enum : int { ST_CONVERGED = 1, ST_CAPPED = 2, ST_OVERFLOW = 4, ST_EXACT = 8, ST_DEFERRED = 16 };
+
+// workspace layout of one ACA (bytes from its start):
+//   U  [cap][m] cpx<T>, W [cap][n] cpx<T>   (A ~ sum_l u_l w_l^T, V = conj(W))
+//   GU [cap][cap] cpx<double>, GV [cap][cap] cpx<double>
+template <typename T>
+__host__ __device__ inline int64_t ws_gram_off(int cap, int m, int n) {
+  int64_t a = int64_t(cap) * (m + n) * int64_t(sizeof(cpx<T>));
+  return (a + 255) & ~int64_t(255);
+}
+template <typename T>
+__host__ __device__ inline int64_t ws_bytes(int cap, int m, int n) {
+  return ws_gram_off<T>(cap, m, n) + 2 * int64_t(cap) * cap * 16;
+}
+
+template <typename T>
+struct AcaShared {
+  unsigned used[ACA_MAXM / 32];
+  cpx<T> ubuf[64];
+};
+
+struct RecompShared {
+  double lam[64], sg[64];
+  int keep[64], order[64];
+  int nkeep, tcut;
+};
+
+// ---- ACA of an entry function --------------------------------------------------
+// Ent: prep_row(i) / prep_col(j) (wave-collective, may be empty) and
+// operator()(i, j) -> cpx<T>.  Partial pivoting: row residual -> pivot column
+// (largest modulus, lowest index on ties) -> column residual -> Frobenius norm
+// of the approximant updated with the cross terms (u_l^H u_k)(w_l^H w_k) ->
+// stop when |u_k||w_k| <= tol |S_k| (term kept) -> next row = largest |u_k|
+// among unused rows; a zero residual row moves on to the lowest unused row.
+// Vectors in T, norms and inner products in double; the inner products are
+// the Gram matrices GU = U^H U and GV = V^H V (V = conj(W)), stored for the
+// recompression.  Returns the rank; `status` receives ST_* bits.
+template <typename T, typename Ent>
+__device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double tol,
+                        cpx<T>* __restrict__ U, cpx<T>* __restrict__ W,
+                        cpx<double>* __restrict__ GU, cpx<double>* __restrict__ GV,
+                        AcaShared<T>& sm, int& status) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  for (int w = lane; w < (m + 31) / 32; w += WAVE) sm.used[w] = 0u;
+  __syncthreads();
+  const int kmax = min(min(m, n), cap);
+  int k = 0, i = 0, nused = 0;
+  status = 0;
+  double norm2 = 0.0;
+  while (k < kmax) {
+    // row residual of row i into W[k]
+    ent.prep_row(i);
+    for (int l = lane; l < k; l += WAVE) sm.ubuf[l] = U[int64_t(l) * m + i];
+    __syncthreads();
+    T best = T(-1);
+    int bj = 0x7fffffff;
+    for (int j = lane; j < n; j += WAVE) {
+      cpx<T> a = ent(i, j);
+      for (int l = 0; l < k; ++l) {
+        cpx<T> p = cmul(sm.ubuf[l], W[int64_t(l) * n + j]);
+        a.re -= p.re;
+        a.im -= p.im;
+      }
+      W[int64_t(k) * n + j] = a;
+      T v = cabs2(a);
+      if (v > best) { best = v; bj = j; }
+    }
+    if (lane == 0) sm.used[i >> 5] |= 1u << (i & 31);
+    ++nused;
+    wave_argmax(best, bj);
+    __syncthreads();
+    if (!(best > T(0))) {
+      int cand = 0x7fffffff;
+      for (int w = lane; w < (m + 31) / 32; w += WAVE) {
+        unsigned free_bits = ~sm.used[w];
+        if (w == (m - 1) / 32 && (m & 31)) free_bits &= (1u << (m & 31)) - 1u;
+        if (free_bits) cand = min(cand, w * 32 + __ffs(free_bits) - 1);
+      }
+      cand = wave_min_int(cand);
+      if (cand == 0x7fffffff || nused >= m) { status |= ST_EXACT; break; }
+      i = cand;
+      continue;
+    }
+    const int jstar = bj;
+    const cpx<T> piv = W[int64_t(k) * n + jstar];
+    const T pm = cabs2(piv);
+    const cpx<T> inv = {piv.re / pm, -piv.im / pm};
+    double nw2 = 0.0;
+    for (int j = lane; j < n; j += WAVE) {
+      cpx<T> w = (j == jstar) ? cpx<T>{T(1), T(0)} : cmul(W[int64_t(k) * n + j], inv);
+      W[int64_t(k) * n + j] = w;
+      nw2 += double(w.re) * double(w.re) + double(w.im) * double(w.im);
+    }
+    __syncthreads();
+    ent.prep_col(jstar);
+    for (int l = lane; l < k; l += WAVE) sm.ubuf[l] = W[int64_t(l) * n + jstar];
+    __syncthreads();
+    // column residual of column jstar into U[k]; candidate next row
+    double nu2 = 0.0;
+    T bestu = T(-1);
+    int bi = 0x7fffffff;
+    for (int r = lane; r < m; r += WAVE) {
+      cpx<T> a = ent(r, jstar);
+      for (int l = 0; l < k; ++l) {
+        cpx<T> p = cmul(sm.ubuf[l], U[int64_t(l) * m + r]);
+        a.re -= p.re;
+        a.im -= p.im;
+      }
+      U[int64_t(k) * m + r] = a;
+      nu2 += double(a.re) * double(a.re) + double(a.im) * double(a.im);
+      if (!((sm.used[r >> 5] >> (r & 31)) & 1u)) {
+        T v = cabs2(a);
+        if (v > bestu) { bestu = v; bi = r; }
+      }
+    }
+    __syncthreads();
+    nw2 = wave_sum(nw2);
+    nu2 = wave_sum(nu2);
+    double cross = 0.0;
+    for (int l = 0; l < k; ++l) {
+      double gur = 0, gui = 0, gwr = 0, gwi = 0;
+      for (int r = lane; r < m; r += WAVE) {
+        cpx<T> a = U[int64_t(l) * m + r], b = U[int64_t(k) * m + r];
+        gur += double(a.re) * b.re + double(a.im) * b.im;
+        gui += double(a.re) * b.im - double(a.im) * b.re;
+      }
+      for (int j = lane; j < n; j += WAVE) {
+        cpx<T> a = W[int64_t(l) * n + j], b = W[int64_t(k) * n + j];
+        gwr += double(a.re) * b.re + double(a.im) * b.im;
+        gwi += double(a.re) * b.im - double(a.im) * b.re;
+      }
+      gur = wave_sum(gur);
+      gui = wave_sum(gui);
+      gwr = wave_sum(gwr);
+      gwi = wave_sum(gwi);
+      cross += gur * gwr - gui * gwi;  // Re((u_l^H u_k)(w_l^H w_k))
+      if (lane == 0) {
+        GU[l * cap + k] = {gur, gui};
+        GU[k * cap + l] = {gur, -gui};
+        // G_V[a][b] = sum_j W[a][j] conj(W[b][j]) = conj(w_a^H w_b)
+        GV[l * cap + k] = {gwr, -gwi};
+        GV[k * cap + l] = {gwr, gwi};
+      }
+    }
+    if (lane == 0) {
+      GU[k * cap + k] = {nu2, 0.0};
+      GV[k * cap + k] = {nw2, 0.0};
+    }
+    norm2 += 2.0 * cross + nu2 * nw2;
+    ++k;
+    if (sqrt(nu2 * nw2) <= tol * sqrt(fmax(norm2, 0.0))) { status |= ST_CONVERGED; break; }
+    wave_argmax(bestu, bi);
+    if (nused >= m || bi == 0x7fffffff) { status |= ST_EXACT; break; }
+    i = bi;
+  }
+  if (k == kmax && !(status & (ST_CONVERGED | ST_EXACT))) {
+    if (kmax == min(m, n)) status |= ST_EXACT;
+    else if (cap >= max_rank) status |= ST_CAPPED;
+    else status |= ST_OVERFLOW;
+  }
+  __syncthreads();
+  return k;
+}
+
+// ---- Hermitian Jacobi eigen-solver, one wave, k <= 64 -------------------------
+// A (k x k, row-major, generic memory) is overwritten by its eigenvalues on the
+// diagonal; Q (k x k) receives the eigenvectors as columns.  Cyclic sweeps with
+// the rotation G = diag(1, conj(e)) R(c, s) that zeroes A[p][q] = |b| e.
+__device__ inline void jacobi_herm(cpx<double>* A, cpx<double>* Q, int k) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  for (int r = lane; r < k * k; r += WAVE) Q[r] = {(r / k == r % k) ? 1.0 : 0.0, 0.0};
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dg = 0.0;
+    for (int r = lane; r < k * k; r += WAVE) {
+      double v = cabs2(A[r]);
+      if (r / k == r % k) dg += v;
+      else off += v;
+    }
+    off = wave_sum(off);
+    dg = wave_sum(dg);
+    if (off <= 1e-30 * dg || off == 0.0) break;
+    for (int p = 0; p < k - 1; ++p) {
+      for (int q = p + 1; q < k; ++q) {
+        const cpx<double> b = A[p * k + q];
+        const double a = A[p * k + p].re, d = A[q * k + q].re;
+        const double bb = sqrt(cabs2(b));
+        if (bb <= 1e-300 || bb * bb <= 1e-34 * fabs(a * d)) continue;
+        const double tau = (d - a) / (2.0 * bb);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        const cpx<double> e = {b.re / bb, b.im / bb};
+        const cpx<double> ec = {e.re, -e.im};
+        __syncthreads();
+        if (lane < k) {  // columns p, q of A and Q (row `lane`)
+          const int r = lane;
+          cpx<double> x = A[r * k + p], y = A[r * k + q];
+          cpx<double> ecy = cmul(ec, y);
+          A[r * k + p] = {c * x.re - s * ecy.re, c * x.im - s * ecy.im};
+          A[r * k + q] = {s * x.re + c * ecy.re, s * x.im + c * ecy.im};
+          x = Q[r * k + p];
+          y = Q[r * k + q];
+          ecy = cmul(ec, y);
+          Q[r * k + p] = {c * x.re - s * ecy.re, c * x.im - s * ecy.im};
+          Q[r * k + q] = {s * x.re + c * ecy.re, s * x.im + c * ecy.im};
+        }
+        __syncthreads();
+        if (lane < k) {  // rows p, q of A (column `lane`)
+          const int r = lane;
+          cpx<double> x = A[p * k + r], y = A[q * k + r];
+          cpx<double> ey = cmul(e, y);
+          A[p * k + r] = {c * x.re - s * ey.re, c * x.im - s * ey.im};
+          A[q * k + r] = {s * x.re + c * ey.re, s * x.im + c * ey.im};
+        }
+        __syncthreads();
+        if (lane == 0) {
+          A[p * k + q] = {0.0, 0.0};
+          A[q * k + p] = {0.0, 0.0};
+          A[p * k + p] = {a - t * bb, 0.0};
+          A[q * k + q] = {d + t * bb, 0.0};
+        }
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// ---- recompression of k ACA terms ------------------------------------------------
+// GU, GV: Gram matrices (leading dimension cap).  mats: 4 k^2 doubles-complex of
+// working memory (LDS or global).  Keeps the smallest t with
+// sqrt(sum_{i >= t} s_i^2) <= tol sqrt(sum s_i^2) and writes the coefficients
+// CU = Q L^{1/2} Z_t and CV = Q L^{-1/2} Z_t (k x t, leading dimension t) over GU
+// and GV.  Without recompression CU = CV = I, t = k.  Returns t.
+__device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol,
+                                      bool do_recompress, cpx<double>* mats, RecompShared& rs) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  if (k == 0 || !do_recompress) {
+    __syncthreads();
+    for (int r = lane; r < k * k; r += WAVE) {
+      GU[r] = {(r / k == r % k) ? 1.0 : 0.0, 0.0};
+      GV[r] = GU[r];
+    }
+    __syncthreads();
+    return k;
+  }
+  cpx<double>* A = mats;
+  cpx<double>* Q = A + k * k;
+  cpx<double>* B = Q + k * k;
+  cpx<double>* Z = B + k * k;
+  for (int r = lane; r < k * k; r += WAVE) A[r] = GV[(r / k) * cap + (r % k)];
+  __syncthreads();
+  jacobi_herm(A, Q, k);
+  if (lane < k) rs.lam[lane] = A[lane * k + lane].re;
+  __syncthreads();
+  double lmax = 0.0;
+  for (int a = 0; a < k; ++a) lmax = fmax(lmax, rs.lam[a]);
+  if (lane == 0) {
+    int c = 0;
+    for (int a = 0; a < k; ++a)
+      if (rs.lam[a] > 1e-14 * lmax && rs.lam[a] > 0.0) rs.keep[c++] = a;
+    rs.nkeep = c;
+  }
+  __syncthreads();
+  const int kk = rs.nkeep;
+  if (kk == 0) return 0;
+  // T1 = GU Q_S (k x kk) into Z, then B = L^1/2 Q_S^H T1 L^1/2
+  for (int e = lane; e < k * kk; e += WAVE) {
+    const int x = e / kk, b = e % kk;
+    const int qb = rs.keep[b];
+    cpx<double> acc = {0, 0};
+    for (int y = 0; y < k; ++y) {
+      cpx<double> p = cmul(GU[x * cap + y], Q[y * k + qb]);
+      acc.re += p.re;
+      acc.im += p.im;
+    }
+    Z[x * kk + b] = acc;
+  }
+  __syncthreads();
+  for (int e = lane; e < kk * kk; e += WAVE) {
+    const int a = e / kk, b = e % kk;
+    const int qa = rs.keep[a];
+    cpx<double> acc = {0, 0};
+    for (int x = 0; x < k; ++x) {
+      cpx<double> p = cmulc(Q[x * k + qa], Z[x * kk + b]);
+      acc.re += p.re;
+      acc.im += p.im;
+    }
+    const double sc = sqrt(rs.lam[qa] * rs.lam[rs.keep[b]]);
+    B[a * kk + b] = {acc.re * sc, acc.im * sc};
+  }
+  __syncthreads();
+  for (int e = lane; e < kk * kk; e += WAVE) {  // Hermitian part
+    const int a = e / kk, b = e % kk;
+    if (a < b) {
+      cpx<double> x = B[a * kk + b], y = B[b * kk + a];
+      cpx<double> h = {0.5 * (x.re + y.re), 0.5 * (x.im - y.im)};
+      B[a * kk + b] = h;
+      B[b * kk + a] = {h.re, -h.im};
+    } else if (a == b) {
+      B[a * kk + a].im = 0.0;
+    }
+  }
+  __syncthreads();
+  jacobi_herm(B, Z, kk);
+  if (lane < kk) rs.sg[lane] = fmax(B[lane * kk + lane].re, 0.0);
+  __syncthreads();
+  if (lane < kk) {  // descending order, ties by index
+    int pos = 0;
+    for (int b = 0; b < kk; ++b)
+      if (rs.sg[b] > rs.sg[lane] || (rs.sg[b] == rs.sg[lane] && b < lane)) ++pos;
+    rs.order[pos] = lane;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    double total = 0.0;
+    for (int a = 0; a < kk; ++a) total += rs.sg[a];
+    double tail = 0.0;
+    int t = kk;
+    for (int a = kk - 1; a >= 0; --a) {
+      tail += rs.sg[rs.order[a]];
+      if (sqrt(tail) <= tol * sqrt(total)) t = a;
+      else break;
+    }
+    rs.tcut = t;
+  }
+  __syncthreads();
+  const int t = rs.tcut;
+  for (int e = lane; e < k * t; e += WAVE) {
+    const int x = e / t, c = e % t;
+    const int zc = rs.order[c];
+    cpx<double> au = {0, 0}, av = {0, 0};
+    for (int a = 0; a < kk; ++a) {
+      const int qa = rs.keep[a];
+      cpx<double> p = cmul(Q[x * k + qa], Z[a * kk + zc]);
+      const double sl = sqrt(rs.lam[qa]);
+      au.re += p.re * sl;
+      au.im += p.im * sl;
+      av.re += p.re / sl;
+      av.im += p.im / sl;
+    }
+    A[e] = au;  // A and B are free now
+    B[e] = av;
+  }
+  __syncthreads();
+  for (int e = lane; e < k * t; e += WAVE) {
+    GU[e] = A[e];
+    GV[e] = B[e];
+  }
+  __syncthreads();
+  return t;
+}
+
+// ---- Ubar = U CU (m x t), Vbar = conj(W) CV (n x t), column-major outputs ----------
+template <typename T>
+__device__ inline void apply_factors(int k, int t, int m, int n, const cpx<T>* U, const cpx<T>* W,
+                                     const cpx<double>* CU, const cpx<double>* CV, cpx<T>* OU,
+                                     cpx<T>* OV, int tid, int nthreads) {
+  const int64_t total = int64_t(m + n) * t;
+  for (int64_t e = tid; e < total; e += nthreads) {
+    if (e < int64_t(m) * t) {
+      const int c = int(e / m), r = int(e % m);
+      cpx<double> acc = {0, 0};
+      for (int x = 0; x < k; ++x) {
+        cpx<T> u = U[int64_t(x) * m + r];
+        cpx<double> cu = CU[x * t + c];
+        acc.re += double(u.re) * cu.re - double(u.im) * cu.im;
+        acc.im += double(u.re) * cu.im + double(u.im) * cu.re;
+      }
+      OU[int64_t(c) * m + r] = {T(acc.re), T(acc.im)};
+    } else {
+      const int64_t e2 = e - int64_t(m) * t;
+      const int c = int(e2 / n), j = int(e2 % n);
+      cpx<double> acc = {0, 0};
+      for (int x = 0; x < k; ++x) {
+        cpx<T> w = W[int64_t(x) * n + j];  // V[j][x] = conj(w)
+        cpx<double> cv = CV[x * t + c];
+        acc.re += double(w.re) * cv.re + double(w.im) * cv.im;
+        acc.im += double(w.re) * cv.im - double(w.im) * cv.re;
+      }
+      OV[int64_t(c) * n + j] = {T(acc.re), T(acc.im)};
+    }
+  }
+}
+
+}  // namespace gcq

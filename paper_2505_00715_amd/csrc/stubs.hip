@@ -2,11 +2,6 @@
 #include "internal.h"
 using namespace gcq;
 extern "C" {
-GCQ_API int gcq_aca_blocks(gcq_context*, const int32_t*, int32_t, double, int32_t, int32_t, uint32_t, gcq_aca_stats*) { return fail(GCQ_ERR_UNSUPPORTED, "not implemented"); }
-GCQ_API int gcq_get_block_factors(gcq_context*, int32_t, int32_t, gcq_c128*, gcq_c128*, int32_t, int32_t*) { return fail(GCQ_ERR_UNSUPPORTED, "not implemented"); }
-GCQ_API int gcq_aca3d(gcq_context*, double, double, int32_t, int32_t, uint32_t, gcq_aca3d_stats*) { return fail(GCQ_ERR_UNSUPPORTED, "not implemented"); }
-GCQ_API int gcq_get_aca3d_block(gcq_context*, int32_t, int32_t, int32_t*, int32_t*, gcq_c128*, gcq_c128*) { return fail(GCQ_ERR_UNSUPPORTED, "not implemented"); }
-GCQ_API int gcq_compressed_matvec(gcq_context*, int32_t, int32_t, const void*, void*, int32_t) { return fail(GCQ_ERR_UNSUPPORTED, "not implemented"); }
 GCQ_API int gcq_solve(gcq_context*, const void*, void*, double, int32_t, int32_t, int32_t, gcq_solve_stats*) { return fail(GCQ_ERR_UNSUPPORTED, "not implemented"); }
 GCQ_API int gcq_rank_features(gcq_context*, const int32_t*, int32_t, float*) { return fail(GCQ_ERR_UNSUPPORTED, "not implemented"); }
 GCQ_API int gcq_rank_model_train(gcq_context*, const float*, const float*, int64_t, const gcq_train_cfg*, gcq_train_stats*) { return fail(GCQ_ERR_UNSUPPORTED, "not implemented"); }
