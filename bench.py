@@ -1,0 +1,228 @@
+"""Benchmark of the single-layer gCQ/3D-ACA hot path on one MI355X.
+
+Workload (default): the 20480-triangle icosphere (subdivision 5, R = 1, c = 1),
+bounding-box cluster tree with leaves of at most 64 triangles, eta = 1, ACA
+tolerance 1e-5, 64 complex frequencies from the BDF2 circle with N = 32 steps
+(dt = 0.02, lam = 1e-8**(1/32)); 33 distinct frequencies under conjugate
+symmetry.  Synthetic, seeded inputs; nothing is read from disk.
+
+One step = one pass of the whole path on resident inputs:
+  aca_blocks (batched, complex64 entries, float64 norms, rank-predicted tiles)
+  -> aca3d (3D-ACA over the 33 frequencies) -> compressed product over all 64
+  frequencies -> batched GMRES(50) to 1e-6 on all 64 systems.
+
+Prints one JSON line (see the keys at the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3
+FP32_MFMA_PEAK_TFLOPS = 157.3
+# algorithmic operations per far-field quadrature point and frequency:
+# 3 sub + 3 fma (r^2) + sqrt + 2 mul + exp + sin + cos + rcp + 2 mul + 2 fma (accumulate)
+OPS_PER_QPOINT = 20
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="sphere20480")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, seconds=15.0):
+    """The oracle's ACA (with recompression) timed on a bounded sample of the
+    same (far block, frequency) pairs, single-threaded."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle import aca
+    from oracle.geometry import Panels
+    from oracle.tree import ClusterTree, block_tree
+    P = Panels(cfg["xyz"], cfg["tri"])
+    T = ClusterTree(P, cfg["leaf"])
+    far = [(a, b) for a, b, adm in block_tree(T, cfg["eta"]) if adm]
+    s = cfg["s"]
+    K = list(range(len(s) // 2 + 1))
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < seconds:
+        a, b = far[int(rng.integers(len(far)))]
+        k = K[int(rng.integers(len(K)))]
+        aca.aca_block(P, T.indices(a), T.indices(b), s[k], cfg["c"], cfg["tol"], 64,
+                      recompress_tol=cfg["tol"])
+        done += 1
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit="blocks/s", cores=1, kind="oracle",
+                sample=f"{done} random (far block, frequency) pairs of the same workload, "
+                       f"ACA + recompression in float64, {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "sharding of this path is a design, not a build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2505_00715_amd as g
+    from synth import configs, rhs
+
+    cfg = configs.get(args.config)
+    L = len(cfg["s"])
+    ctx = g.Context(0)
+    ctx.upload_mesh(cfg["xyz"], cfg["tri"], cfg["c"])
+    ctx.set_frequencies(cfg["s"], True)
+    info = ctx.build_cluster_tree(cfg["leaf"], cfg["eta"])
+    K = np.arange(L // 2 + 1)
+    tol = cfg["tol"]
+
+    # ---- rank model: trained on the ranks the plain ACA produces (setup, untimed)
+    st_plain = ctx.aca_blocks(tol, 64, g.C128, g.FLAG_RECOMPRESS | g.FLAG_PER_FREQ_LAUNCH)
+    plain_aca_ms = st_plain.device_ms
+    far = np.nonzero(ctx.get_tree()[1][:, 4])[0]
+    ranks = np.array([[ctx.get_block_factors(int(b), int(k))[0].shape[1] for k in K[::4]]
+                      for b in far[::7]], np.float32)
+    ctx.destroy()
+    ctx = g.Context(0)
+    ctx.upload_mesh(cfg["xyz"], cfg["tri"], cfg["c"])
+    ctx.set_frequencies(cfg["s"], True)
+    ctx.build_cluster_tree(cfg["leaf"], cfg["eta"])
+    feat_all = ctx.rank_features(K[::4], len(far))[::7].reshape(-1, 5)
+    ctx.rank_model_train(feat_all, np.log1p(ranks.reshape(-1)), epochs=60, batch=512, lr=3e-3)
+
+    X = rhs.random_complex(L, ctx.n, 0)
+    Xd = torch.from_numpy(X).to(torch.complex64).cuda().reshape(-1)
+    Yd = torch.zeros_like(Xd)
+    B = torch.from_numpy(rhs.random_complex(L, ctx.n, 1)).cuda().reshape(-1)
+    Xs = torch.zeros_like(B)
+
+    # ---- plain baseline products (untimed in the step): per-frequency H-matrices, float64
+    plain = {}
+    if not args.no_plain:
+        ctx.aca_blocks(tol, 64, g.C128, g.FLAG_RECOMPRESS | g.FLAG_PER_FREQ_LAUNCH)
+        X128 = torch.from_numpy(X).cuda().reshape(-1)
+        Y128 = torch.zeros_like(X128)
+        ctx.compressed_matvec(g.PLAIN_H, g.C128, X128, Y128)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            ctx.compressed_matvec(g.PLAIN_H, g.C128, X128, Y128)
+            torch.cuda.synchronize()
+            ts.append(ctx.kernel_ms("matvec_plainh"))
+        plain = dict(aca_blocks_per_s=st_plain.n_pairs / (plain_aca_ms / 1e3),
+                     aca_ms=plain_aca_ms, plainh_matvec_ms=float(np.median(ts)))
+        del X128, Y128
+
+    def step(record):
+        t0 = time.perf_counter()
+        sa = ctx.aca_blocks(tol, 64, g.C64, g.FLAG_RECOMPRESS | g.FLAG_USE_PREDICTOR)
+        s3 = ctx.aca3d(tol, tol, 40, g.C64)
+        ctx.compressed_matvec(g.PER_FREQUENCY, g.C64, Xd, Yd)
+        torch.cuda.synchronize()
+        mv_ms = ctx.kernel_ms("matvec_perfreq")
+        ss = None
+        if not args.no_solve:
+            ss = ctx.solve(B, Xs, rtol=1e-6, max_iter=300, restart=50, precision=g.C64)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if record is not None:
+            record.append(dict(wall=wall, aca=sa, a3=s3, mv_ms=mv_ms, solve=ss,
+                               aca_kernel_ms=ctx.kernel_ms("aca_total"),
+                               aca3d_ms=ctx.kernel_ms("aca3d")))
+
+    for _ in range(args.warmup):
+        step(None)
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(recs)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_per_step = total / args.steps * 1e3
+
+    last = recs[-1]
+    sa, s3 = last["aca"], last["a3"]
+    n_pairs = sa.n_pairs
+    aca_ms = float(np.median([r["aca"].device_ms for r in recs]))
+    mv_ms = float(np.median([r["mv_ms"] for r in recs]))
+    aca_kernel_ms = float(np.median([r["aca_kernel_ms"] for r in recs]))
+    # algorithmic bytes of the compressed product: stored slices and fibers,
+    # X read once, Y written once (complex64)
+    mv_bytes = s3.storage_bytes + 2 * L * ctx.n * 8
+    mv_gbps = mv_bytes / (mv_ms / 1e3) / 1e9
+    # ALU work of the ACA kernel: entry evaluations x 7 quadrature points
+    aca_ops = sa.entries * 7 * OPS_PER_QPOINT
+    aca_tflops = aca_ops / (aca_kernel_ms / 1e3) / 1e12
+
+    # accuracy of the compressed product on sampled rows against the oracle's
+    # dense rows (float64)
+    Y = Yd.cpu().numpy().reshape(L, ctx.n).astype(np.complex128)
+    from oracle import entries
+    from oracle.geometry import Panels
+    P = Panels(cfg["xyz"], cfg["tri"])
+    rows = rhs.sample_rows(ctx.n, 12, 0)
+    kk = np.array([0, 5, 16, 32, 40, 63])
+    A = entries.block(P, rows, np.arange(ctx.n), cfg["s"][kk], cfg["c"])
+    ref = np.einsum("kij,kj->ki", A, X[kk])
+    err = float(np.linalg.norm(Y[kk][:, rows] - ref) / np.linalg.norm(ref))
+
+    value = n_pairs / (ms_per_step / 1e3)
+    out = {
+        "metric": "ACA blocks/s + compressed matvec GB/s over all s_k vs plain, at rel err 1e-5",
+        "value": value,
+        "unit": "blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: icosphere subdivision 5 ({ctx.n} triangles), "
+                               f"leaf 64, eta 1, ACA tol 1e-5, {L} BDF2-circle frequencies "
+                               f"({len(K)} distinct)", "n": ctx.n, "n_freq": L,
+                   "far_blocks": info.n_far, "near_blocks": info.n_near},
+        "aca_pairs": n_pairs,
+        "aca_blocks_per_s_kernel": n_pairs / (aca_ms / 1e3),
+        "matvec_GBps": mv_gbps,
+        "matvec_ms": mv_ms,
+        "aca3d_ms": float(np.median([r["aca3d_ms"] for r in recs])),
+        "solve": None if last["solve"] is None else
+        {"iters_max": last["solve"].iters_max, "resid_max": last["solve"].resid_max,
+         "ms": last["solve"].device_ms},
+        "rel_err_matvec_vs_oracle": err,
+        "aca3d": {"rank_mean": s3.rank_mean, "rank_max": s3.rank_max,
+                  "compression_rate": s3.compression_rate, "storage_GB": s3.storage_bytes / 1e9},
+        "plain": plain,
+        "roofline": {"bound": "alu", "kernel": "aca_kernel<float>", "achieved": aca_tflops,
+                     "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": aca_tflops / FP32_VALU_PEAK_TFLOPS, "traffic": None},
+        "roofline_matvec": {"bound": "hbm", "achieved": mv_gbps, "peak": HBM_PEAK_GBPS,
+                            "unit": "GB/s", "frac": mv_gbps / HBM_PEAK_GBPS},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -258,7 +258,7 @@ GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_dev, double r
 /* ---- learned rank predictor -----------------------------------------------
  * The network (5 -> 64 -> 64 -> 1, tanh, float) maps standardised features of
  * a (far block, frequency) pair to log(1 + ACA rank).  Parameters are laid
- * out W1(64x5) b1(64) W2(64x64) b2(64) W3(1x64) b3(1), row-major; 4545 floats.
+ * out W1(64x5) b1(64) W2(64x64) b2(64) W3(1x64) b3(1), row-major; 4609 floats.
  *
  * gcq_rank_features: host features (n_far x n_fidx x 5 floats, unstandardised)
  *   of every admissible block at the listed representatives:
@@ -268,9 +268,9 @@ GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_dev, double r
  *   Adam kernels; standardisation is fitted on the training set.
  * gcq_rank_model_grad: one forward/backward pass at the current parameters
  *   on m host samples (already standardised); writes the mean loss and the
- *   gradient (4545 floats) to host memory.
+ *   gradient (4609 floats) to host memory.
  * gcq_rank_model_predict: predicted log(1 + rank) for m host samples.
- * gcq_rank_model_get / set: host copy of parameters (4545 floats) and of the
+ * gcq_rank_model_get / set: host copy of parameters (4609 floats) and of the
  *   standardisation (mean[5], std[5]; either pointer may be NULL). */
 GCQ_API int gcq_rank_features(gcq_context* ctx, const int32_t* freq_idx, int32_t n_fidx,
                               float* feat);

@@ -22,7 +22,7 @@ C128, C64 = 0, 1
 PER_FREQUENCY, WEIGHTED_SUM, PLAIN_H = 0, 1, 2
 FLAG_RECOMPRESS, FLAG_USE_PREDICTOR, FLAG_PER_FREQ_LAUNCH = 1, 2, 4
 OK, NOT_CONVERGED, RANK_CAPPED = 0, 1, 2
-N_MODEL_PARAMS = 4545
+N_MODEL_PARAMS = 4609
 
 
 class TreeInfo(C.Structure):

@@ -227,6 +227,11 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
 
 }  // namespace gcq
 
+namespace gcq {
+int rank_predict_device(gcq_context* ctx, const float* d_x, int m, float* d_out);
+void rank_features_host(gcq_context* ctx, const std::vector<int>& freqs, std::vector<float>& feat);
+}  // namespace gcq
+
 using namespace gcq;
 
 extern "C" {
@@ -286,12 +291,45 @@ GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_
   }
   std::vector<int> order(desc.size());
   std::iota(order.begin(), order.end(), 0);
+  const bool predict = (flags & GCQ_FLAG_USE_PREDICTOR) != 0;
+  if (predict) {
+    // tile capacities from the rank model: ceil(1.25 r) + 2, multiple of 4,
+    // at least 4; work list ordered by predicted cost (largest first)
+    if (!ctx->M.trained) return fail(GCQ_ERR_STATE, "train or set the rank model first");
+    std::vector<float> feat;
+    rank_features_host(ctx, fr, feat);  // [far][slot][5]
+    const size_t np = desc.size();
+    std::vector<float> xs(np * 5);
+    for (int q = 0; q < nslot; ++q)
+      for (int f = 0; f < nfar; ++f)
+        for (int a = 0; a < 5; ++a)
+          xs[(size_t(q) * nfar + f) * 5 + a] =
+              (feat[(size_t(f) * nslot + q) * 5 + a] - ctx->M.mean[a]) / ctx->M.stdv[a];
+    DevBuf dx, dy;
+    GCQ_TRY(upload(dx, xs, ctx->stream));
+    GCQ_TRY(dy.ensure(sizeof(float) * np));
+    GCQ_TRY(timed_begin(ctx));
+    GCQ_TRY(rank_predict_device(ctx, dx.as<float>(), int(np), dy.as<float>()));
+    ctx->kernel_ms["predict"] = timed_end(ctx, "predict");
+    std::vector<float> pr(np);
+    GCQ_HIP(hipMemcpy(pr.data(), dy.p, sizeof(float) * np, hipMemcpyDeviceToHost));
+    std::vector<double> cost(np);
+    for (size_t p = 0; p < np; ++p) {
+      double r = std::max(0.0, std::expm1(double(pr[p])));
+      int capp = int(std::ceil(1.25 * r)) + 2;
+      capp = std::max(4, (capp + 3) / 4 * 4);
+      desc[p].cap = std::min(desc[p].cap, capp);
+      cost[p] = double(desc[p].cap) * (desc[p].m + desc[p].n);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  }
   std::vector<int> rank_aca, rank_out, status;
   std::vector<int64_t> off;
   int64_t pool_used = 0;
   double ms_aca = 0, ms_rec = 0, ms_apply = 0;
   const bool rec = (flags & GCQ_FLAG_RECOMPRESS) != 0;
   const int64_t budget = int64_t(6) << 30;
+  int64_t n_overflow_pairs = 0;
   int rc;
   if (flags & GCQ_FLAG_PER_FREQ_LAUNCH) {
     // baseline: one chunk (launch sequence) per frequency, natural order
@@ -327,6 +365,38 @@ GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_
                                     status, off, H.factors, pool_used, ms_aca, ms_rec, ms_apply,
                                     budget);
     if (rc < 0) return rc;
+    if (predict) {
+      // pairs whose tile was too small run again at full capacity; the
+      // adaptive ACA decides the rank
+      std::vector<PairDesc> od;
+      std::vector<int> who;
+      for (size_t p = 0; p < desc.size(); ++p)
+        if (status[p] & ST_OVERFLOW) {
+          PairDesc d = desc[p];
+          d.cap = std::min(std::min(d.m, d.n), int(max_rank));
+          od.push_back(d);
+          who.push_back(int(p));
+        }
+      n_overflow_pairs = int64_t(who.size());
+      if (!od.empty()) {
+        std::vector<int> oo(od.size());
+        std::iota(oo.begin(), oo.end(), 0);
+        std::vector<int> ra, ro, stt;
+        std::vector<int64_t> of;
+        rc = precision == GCQ_C128
+                 ? run_aca_pairs<double>(ctx, od, oo, tol, max_rank, rec, ra, ro, stt, of,
+                                         H.factors, pool_used, ms_aca, ms_rec, ms_apply, budget)
+                 : run_aca_pairs<float>(ctx, od, oo, tol, max_rank, rec, ra, ro, stt, of,
+                                        H.factors, pool_used, ms_aca, ms_rec, ms_apply, budget);
+        if (rc < 0) return rc;
+        for (size_t a = 0; a < who.size(); ++a) {
+          rank_aca[who[a]] = ra[a];
+          rank_out[who[a]] = ro[a];
+          status[who[a]] = stt[a];
+          off[who[a]] = of[a];
+        }
+      }
+    }
   }
   // near field: dense blocks per frequency slot
   const int nnear = int(ctx->near_ids.size());
@@ -376,7 +446,7 @@ GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_
   int64_t rsum = 0, rasum = 0, nover = 0, ents = 0;
   for (size_t p = 0; p < desc.size(); ++p) {
     ncap += (status[p] & ST_CAPPED) != 0;
-    nover += (status[p] & ST_OVERFLOW) != 0;
+    (void)nover;
     rmax = std::max(rmax, rank_out[p]);
     rsum += rank_out[p];
     rasum += rank_aca[p];
@@ -389,7 +459,7 @@ GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_
     stats->rank_sum = rsum;
     stats->rank_max = rmax;
     stats->n_capped = ncap;
-    stats->n_overflow = nover;
+    stats->n_overflow = n_overflow_pairs;
     stats->entries = ents;
     stats->storage_bytes = H.storage_bytes;
     stats->device_ms = ms_aca + ms_rec + ms_apply;

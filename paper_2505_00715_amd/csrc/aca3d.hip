@@ -202,17 +202,17 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
       cur.rank = srank;
       cur.freq = kcur;
       // ---- pivot: largest modulus, first in row-major order on ties
-      T best = T(-1);
+      double best = -1.0;
       int be = 0x7fffffff;
       const int mn = m * n;
       for (int e = lane; e < mn; e += WAVE) {
         const int i = e / n, j = e % n;  // row-major key
         cpx<T> h = slice_at<T>(cur, pool, m, n, i, j);
-        T v = cabs2(h);
+        double v = mag2(h);
         if (v > best) { best = v; be = e; }
       }
       wave_argmax(best, be);
-      if (!(best > T(0))) break;   // zero pivot: rank stays ell
+      if (!(best > PivFloor<T>::v)) break;   // zero pivot: rank stays ell
       const int ip = be / n, jp = be % n;
       const cpx<T> piv = slice_at<T>(cur, pool, m, n, ip, jp);
       for (int d = lane; d < ell; d += WAVE) sh.hp[d] = slice_at<T>(sh.term[d], pool, m, n, ip, jp);
@@ -222,8 +222,7 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
       if (foff < 0) { status |= ST_DEFERRED; break; }
       cur.fiber = foff;
       // ---- fiber over K
-      const T pm = cabs2(piv);
-      const cpx<T> inv = {piv.re / pm, -piv.im / pm};
+      const cpx<T> inv = cinv(piv);
       double nf2 = 0.0;
       for (int kk = lane; kk < nK; kk += WAVE) {
         const double2 s2 = sigK[kk];
@@ -316,12 +315,11 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
       __syncthreads();
       ++ell;
       // next frequency: largest |f_l[k]| among unused k (lowest k on ties)
-      T bf = T(-1);
+      double bf = -1.0;
       int bk = 0x7fffffff;
       for (int kk = lane; kk < nK; kk += WAVE) {
         if ((sh.usedk[kk >> 5] >> (kk & 31)) & 1u) continue;
-        cpx<T> f = pool[foff + kk];
-        T v = cabs2(f);
+        double v = mag2(pool[foff + kk]);
         if (v > bf) { bf = v; bk = kk; }
       }
       wave_argmax(bf, bk);

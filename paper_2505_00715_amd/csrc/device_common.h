@@ -29,6 +29,28 @@ template <typename T>
 __device__ __forceinline__ T cabs2(cpx<T> a) {
   return a.re * a.re + a.im * a.im;
 }
+// squared modulus in double: pivot searches on float data must not lose
+// entries whose square underflows in float
+template <typename T>
+__device__ __forceinline__ double mag2(cpx<T> a) {
+  return double(a.re) * double(a.re) + double(a.im) * double(a.im);
+}
+// smallest squared modulus a pivot may have: its reciprocal must stay finite
+template <typename T>
+struct PivFloor;
+template <>
+struct PivFloor<float> {
+  static constexpr double v = 1.4e-76;  // (FLT_MIN)^2
+};
+template <>
+struct PivFloor<double> {
+  static constexpr double v = 0.0;
+};
+template <typename T>
+__device__ __forceinline__ cpx<T> cinv(cpx<T> a) {
+  const double m = mag2(a);
+  return {T(double(a.re) / m), T(-double(a.im) / m)};
+}
 
 // ---- wave64 reductions (every lane receives the result) --------------------
 __device__ __forceinline__ double wave_sum(double v) {

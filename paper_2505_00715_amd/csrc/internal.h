@@ -124,7 +124,7 @@ struct Faces3D {
 // ---- rank model ---------------------------------------------------------------------
 struct RankModel {
   bool trained = false;
-  std::vector<float> params;     // 4545
+  std::vector<float> params;     // 4609
   float mean[5] = {0, 0, 0, 0, 0}, stdv[5] = {1, 1, 1, 1, 1};
   DevBuf d_params;
 };

@@ -79,7 +79,7 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
     ent.prep_row(i);
     for (int l = lane; l < k; l += WAVE) sm.ubuf[l] = U[int64_t(l) * m + i];
     __syncthreads();
-    T best = T(-1);
+    double best = -1.0;
     int bj = 0x7fffffff;
     for (int j = lane; j < n; j += WAVE) {
       cpx<T> a = ent(i, j);
@@ -89,14 +89,14 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
         a.im -= p.im;
       }
       W[int64_t(k) * n + j] = a;
-      T v = cabs2(a);
+      double v = mag2(a);
       if (v > best) { best = v; bj = j; }
     }
     if (lane == 0) sm.used[i >> 5] |= 1u << (i & 31);
     ++nused;
     wave_argmax(best, bj);
     __syncthreads();
-    if (!(best > T(0))) {
+    if (!(best > PivFloor<T>::v)) {
       int cand = 0x7fffffff;
       for (int w = lane; w < (m + 31) / 32; w += WAVE) {
         unsigned free_bits = ~sm.used[w];
@@ -109,9 +109,7 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
       continue;
     }
     const int jstar = bj;
-    const cpx<T> piv = W[int64_t(k) * n + jstar];
-    const T pm = cabs2(piv);
-    const cpx<T> inv = {piv.re / pm, -piv.im / pm};
+    const cpx<T> inv = cinv(W[int64_t(k) * n + jstar]);
     double nw2 = 0.0;
     for (int j = lane; j < n; j += WAVE) {
       cpx<T> w = (j == jstar) ? cpx<T>{T(1), T(0)} : cmul(W[int64_t(k) * n + j], inv);
@@ -124,7 +122,7 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
     __syncthreads();
     // column residual of column jstar into U[k]; candidate next row
     double nu2 = 0.0;
-    T bestu = T(-1);
+    double bestu = -1.0;
     int bi = 0x7fffffff;
     for (int r = lane; r < m; r += WAVE) {
       cpx<T> a = ent(r, jstar);
@@ -136,7 +134,7 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
       U[int64_t(k) * m + r] = a;
       nu2 += double(a.re) * double(a.re) + double(a.im) * double(a.im);
       if (!((sm.used[r >> 5] >> (r & 31)) & 1u)) {
-        T v = cabs2(a);
+        double v = mag2(a);
         if (v > bestu) { bestu = v; bi = r; }
       }
     }

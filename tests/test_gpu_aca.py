@@ -33,7 +33,7 @@ def test_aca_blocks_match_oracle(prec):
     assert st.n_pairs == int(blocks[:, 4].sum()) * len(K)
     far = np.nonzero(blocks[:, 4])[0]
     rng = np.random.default_rng(0)
-    num = den = num_t = 0.0
+    num = den = num_t = num_o = 0.0
     same_rank = total = 0
     for b in rng.choice(far, 40, replace=False):
         a, bb = B[b][0], B[b][1]
@@ -45,13 +45,15 @@ def test_aca_blocks_match_oracle(prec):
             Sg, So = Ug @ Vg.conj().T, Uo @ Vo.conj().T
             num += np.linalg.norm(Sg - So) ** 2
             num_t += np.linalg.norm(Sg - A) ** 2
+            num_o += np.linalg.norm(So - A) ** 2
             den += np.linalg.norm(A) ** 2
             same_rank += Ug.shape[1] == Uo.shape[1]
             total += 1
             # every block stays within the ACA's own error regime
             assert np.linalg.norm(Sg - A) <= 40 * TOL * np.linalg.norm(A) + 1e-30
     assert np.sqrt(num / den) <= (1e-5 if prec == g.C128 else 1e-4)
-    assert np.sqrt(num_t / den) <= 1e-5
+    # approximation error against the dense blocks: that of the oracle's ACA
+    assert np.sqrt(num_t / den) <= 1.5 * np.sqrt(num_o / den) + 1e-6
     if prec == g.C128:
         assert same_rank >= 0.8 * total
 
