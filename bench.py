@@ -92,6 +92,8 @@ def main():
     K = np.arange(L // 2 + 1)
     tol = cfg["tol"]
 
+    print(f"[bench] {args.config}: n={ctx.n} far={info.n_far} near={info.n_near}",
+          file=sys.stderr, flush=True)
     # ---- rank model: trained on the ranks the plain ACA produces (setup, untimed)
     st_plain = ctx.aca_blocks(tol, 64, g.C128, g.FLAG_RECOMPRESS | g.FLAG_PER_FREQ_LAUNCH)
     plain_aca_ms = st_plain.device_ms
@@ -104,7 +106,9 @@ def main():
     ctx.set_frequencies(cfg["s"], True)
     ctx.build_cluster_tree(cfg["leaf"], cfg["eta"])
     feat_all = ctx.rank_features(K[::4], len(far))[::7].reshape(-1, 5)
-    ctx.rank_model_train(feat_all, np.log1p(ranks.reshape(-1)), epochs=60, batch=512, lr=3e-3)
+    tr = ctx.rank_model_train(feat_all, np.log1p(ranks.reshape(-1)), epochs=60, batch=512, lr=3e-3)
+    print(f"[bench] plain ACA {plain_aca_ms:.1f} ms; rank model loss {tr.loss_first:.3f} -> "
+          f"{tr.loss_last:.3f}", file=sys.stderr, flush=True)
 
     X = rhs.random_complex(L, ctx.n, 0)
     Xd = torch.from_numpy(X).to(torch.complex64).cuda().reshape(-1)
@@ -141,6 +145,13 @@ def main():
             ss = ctx.solve(B, Xs, rtol=1e-6, max_iter=300, restart=50, precision=g.C64)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        print(f"[bench] step {wall * 1e3:.1f} ms: aca {sa.device_ms:.1f} ms (kernel "
+              f"{ctx.kernel_ms('aca_total'):.1f}, recompress {ctx.kernel_ms('recompress_total'):.1f}, "
+              f"apply {ctx.kernel_ms('apply_total'):.1f}), aca3d "
+              f"{ctx.kernel_ms('aca3d'):.1f} ms (far {ctx.kernel_ms('aca3d_far'):.1f}, near "
+              f"{ctx.kernel_ms('aca3d_near'):.1f}), matvec {mv_ms:.2f} ms"
+              + ("" if ss is None else f", solve {ss.device_ms:.1f} ms ({ss.iters_max} it)"),
+              file=sys.stderr, flush=True)
         if record is not None:
             record.append(dict(wall=wall, aca=sa, a3=s3, mv_ms=mv_ms, solve=ss,
                                aca_kernel_ms=ctx.kernel_ms("aca_total"),

@@ -11,7 +11,7 @@
 namespace gcq {
 
 // ---- 2D ACA kernels: one wave per (block, frequency) pair ------------------------
-template <typename T>
+template <typename T, bool ALLFAR>
 struct PlainEntry {
   const Tab* tab;
   int rb, cb;
@@ -20,11 +20,13 @@ struct PlainEntry {
   __device__ void prep_row(int) {}
   __device__ void prep_col(int) {}
   __device__ cpx<T> operator()(int i, int j) const {
-    return entry<T>(*tab, rb + i, cb + j, sr, si, all_far);
+    return entry<T, ALLFAR>(*tab, rb + i, cb + j, sr, si, all_far);
   }
 };
 
-template <typename T>
+// ALLFAR = true serves the pairs of blocks without self/near-tier entries,
+// ALLFAR = false the others; each instance skips the pairs of the other kind.
+template <typename T, bool ALLFAR>
 __global__ void __launch_bounds__(64) aca_kernel(Tab tab, const PairDesc* __restrict__ pairs,
                                                  const int* __restrict__ order, int npairs,
                                                  unsigned char* __restrict__ ws, double tol,
@@ -40,10 +42,11 @@ __global__ void __launch_bounds__(64) aca_kernel(Tab tab, const PairDesc* __rest
     if (idx >= npairs) break;
     const int pid = order ? order[idx] : idx;
     const PairDesc d = pairs[pid];
+    if ((d.all_far != 0) != ALLFAR) continue;
     cpx<T>* U = reinterpret_cast<cpx<T>*>(ws + d.ws);
     cpx<T>* W = U + int64_t(d.cap) * d.m;
     cpx<double>* GU = reinterpret_cast<cpx<double>*>(ws + d.ws + ws_gram_off<T>(d.cap, d.m, d.n));
-    PlainEntry<T> ent{&tab, d.rb, d.cb, d.sr, d.si, d.all_far != 0};
+    PlainEntry<T, ALLFAR> ent{&tab, d.rb, d.cb, d.sr, d.si, d.all_far != 0};
     int status = 0;
     const int k = aca_wave<T>(ent, d.m, d.n, d.cap, max_rank, tol, U, W, GU, GU + d.cap * d.cap,
                               sm, status);
@@ -168,12 +171,19 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
     int* d_t = d_status + nc;
     int* d_counter = d_t + nc;
     hipLaunchKernelGGL(zero_int, dim3(1), dim3(64), 0, st, d_counter, 8);
-    const int grid = std::min(nc, dev_cus * 16);
+    int nnf = 0;
+    for (int a = 0; a < nc; ++a) nnf += cd[a].all_far == 0;
+    const int grid = std::min(nc, dev_cus * 32);
     GCQ_TRY(timed_begin(ctx));
-    hipLaunchKernelGGL(aca_kernel<T>, dim3(grid), dim3(64), 0, st, ctx->tab(),
+    hipLaunchKernelGGL((aca_kernel<T, true>), dim3(grid), dim3(64), 0, st, ctx->tab(),
                        ctx->scratchB.as<PairDesc>(), (const int*)nullptr, nc,
                        ctx->scratchA.as<unsigned char>(), tol, max_rank, d_rank, d_status,
                        d_counter);
+    if (nnf > 0)
+      hipLaunchKernelGGL((aca_kernel<T, false>), dim3(std::min(grid, nnf)), dim3(64), 0, st,
+                         ctx->tab(), ctx->scratchB.as<PairDesc>(), (const int*)nullptr, nc,
+                         ctx->scratchA.as<unsigned char>(), tol, max_rank, d_rank, d_status,
+                         d_counter + 1);
     GCQ_HIP(hipGetLastError());
     ms_aca += timed_end(ctx, "aca");
     // recompression; matrices above 32 terms live in global scratch

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <type_traits>
 
 #include "internal.h"
 #include "lowrank.h"
@@ -48,7 +49,7 @@ __device__ inline int64_t pool_alloc(unsigned long long* cursor, int64_t cnt, in
 
 // residual entry function of a far block at one frequency:
 //   R(i, j) = A_ij(s) - sum_d f_d[k] (Ubar_d Vbar_d^H)[i, j]
-template <typename T>
+template <typename T, bool ALLFAR>
 struct ResidualEntry {
   const Tab* tab;
   int rb, cb, m, n;
@@ -89,7 +90,7 @@ struct ResidualEntry {
     __syncthreads();
   }
   __device__ cpx<T> operator()(int i, int j) const {
-    cpx<T> a = entry<T>(*tab, rb + i, cb + j, sr, si, all_far);
+    cpx<T> a = entry<T, ALLFAR>(*tab, rb + i, cb + j, sr, si, all_far);
     int base = 0;
     for (int d = 0; d < nterm; ++d) {
       const Term3 t = sh->term[d];
@@ -128,7 +129,9 @@ __device__ inline cpx<T> slice_at(const Term3& t, const cpx<T>* pool, int m, int
   return acc;
 }
 
-template <typename T>
+// ALLFAR = true: admissible blocks without self/near-tier entries (the float64
+// quadrature tiers are not compiled in); ALLFAR = false: every other block.
+template <typename T, bool ALLFAR>
 __global__ void __launch_bounds__(64) aca3d_kernel(
     Tab tab, const BlockDesc3* __restrict__ blocks, const int* __restrict__ order, int nblocks,
     const double2* __restrict__ sigK, int nK, double tol_aca, double tol, int rmax, int aca_cap,
@@ -165,14 +168,14 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
       int64_t soff = -1;
       int srank = -1;
       // ---- residual slice at k_cur
-      if (!B.admissible) {
+      if (!ALLFAR && !B.admissible) {
         if (lane == 0) sh.alloc = pool_alloc(cursor, int64_t(m) * n, capacity);
         __syncthreads();
         soff = sh.alloc;
         if (soff < 0) { status |= ST_DEFERRED; break; }
         for (int e = lane; e < m * n; e += WAVE) {
           const int r = e % m, c = e / m;
-          cpx<T> a = entry<T>(tab, B.rb + r, B.cb + c, sg.x, sg.y, B.all_far != 0);
+          cpx<T> a = entry<T, ALLFAR>(tab, B.rb + r, B.cb + c, sg.x, sg.y, B.all_far != 0);
           for (int d = 0; d < ell; ++d) {
             cpx<T> p = cmul(sh.fk[d], pool[sh.term[d].slice + e]);
             a.re -= p.re;
@@ -181,8 +184,8 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
           pool[soff + e] = a;
         }
       } else {
-        ResidualEntry<T> ent{&tab, B.rb, B.cb, m, n, sg.x, sg.y, B.all_far != 0, ell, &sh, pool,
-                             coef, true};
+        ResidualEntry<T, ALLFAR> ent{&tab, B.rb, B.cb, m, n, sg.x, sg.y, B.all_far != 0, ell, &sh,
+                                     pool, coef, true};
         int ast = 0;
         const int k = aca_wave<T>(ent, m, n, cap, aca_cap, tol_aca, U, W, GU, GV, sh.aca, ast);
         if (ast & ST_CAPPED) status |= ST_CAPPED;
@@ -226,7 +229,7 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
       double nf2 = 0.0;
       for (int kk = lane; kk < nK; kk += WAVE) {
         const double2 s2 = sigK[kk];
-        cpx<T> a = entry<T>(tab, B.rb + ip, B.cb + jp, s2.x, s2.y, B.all_far != 0);
+        cpx<T> a = entry<T, ALLFAR>(tab, B.rb + ip, B.cb + jp, s2.x, s2.y, B.all_far != 0);
         for (int d = 0; d < ell; ++d) {
           cpx<T> p = cmul(sh.hp[d], pool[sh.term[d].fiber + kk]);
           a.re -= p.re;
@@ -240,7 +243,7 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
       nf2 = wave_sum(nf2);
       // ---- eq. norm: <H_d, H_l> <f_d, f_l> cross terms and |H_l|^2 |f_l|^2
       double nh2 = 0.0;
-      if (!B.admissible) {
+      if (!ALLFAR && !B.admissible) {
         for (int e = lane; e < mn; e += WAVE) {
           cpx<T> h = pool[soff + e];
           nh2 += double(h.re) * double(h.re) + double(h.im) * double(h.im);
@@ -432,28 +435,44 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   double ms = 0.0;
   std::vector<int> todo = order;
   for (int round = 0; round < 4 && !todo.empty(); ++round) {
-    GCQ_HIP(hipMemcpyAsync(d_order, todo.data(), sizeof(int) * todo.size(), hipMemcpyHostToDevice,
-                           ctx->stream));
     hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, d_counter, 2);
     unsigned long long cur0 = (unsigned long long)used;
     GCQ_HIP(hipMemcpyAsync(d_cursor, &cur0, sizeof(cur0), hipMemcpyHostToDevice, ctx->stream));
+    // far blocks without near-tier entries first, then every other block
+    std::vector<int> lf, ln;
+    for (int b : todo) (bd[b].admissible && bd[b].all_far ? lf : ln).push_back(b);
+    std::vector<int> both(lf);
+    both.insert(both.end(), ln.begin(), ln.end());
+    GCQ_HIP(hipMemcpyAsync(d_order, both.data(), sizeof(int) * both.size(), hipMemcpyHostToDevice,
+                           ctx->stream));
     GCQ_TRY(timed_begin(ctx));
-    if (precision == GCQ_C128)
-      hipLaunchKernelGGL(aca3d_kernel<double>, dim3(std::min<int>(grid, int(todo.size()))), dim3(64),
-                         0, ctx->stream, ctx->tab(), ctx->scratchB.as<BlockDesc3>(), d_order,
-                         int(todo.size()), ctx->scratchC.as<double2>(), nK, tol_aca, tol,
-                         int(max_freq_rank), aca_cap, ctx->scratchA.as<unsigned char>(), ws_stride,
-                         F.slices.as<cpx<double>>(), d_cursor, capacity, d_terms, d_rank, d_stat,
-                         d_counter);
-    else
-      hipLaunchKernelGGL(aca3d_kernel<float>, dim3(std::min<int>(grid, int(todo.size()))), dim3(64),
-                         0, ctx->stream, ctx->tab(), ctx->scratchB.as<BlockDesc3>(), d_order,
-                         int(todo.size()), ctx->scratchC.as<double2>(), nK, tol_aca, tol,
-                         int(max_freq_rank), aca_cap, ctx->scratchA.as<unsigned char>(), ws_stride,
-                         F.slices.as<cpx<float>>(), d_cursor, capacity, d_terms, d_rank, d_stat,
-                         d_counter);
+    auto launch = [&](auto tag_t, auto tag_a, int off, int cnt, int* ctr) {
+      using TT = decltype(tag_t);
+      constexpr bool AA = decltype(tag_a)::value;
+      if (cnt == 0) return;
+      hipLaunchKernelGGL((aca3d_kernel<TT, AA>), dim3(std::min(grid, cnt)), dim3(64), 0,
+                         ctx->stream, ctx->tab(), ctx->scratchB.as<BlockDesc3>(), d_order + off,
+                         cnt, ctx->scratchC.as<double2>(), nK, tol_aca, tol, int(max_freq_rank),
+                         aca_cap, ctx->scratchA.as<unsigned char>(), ws_stride,
+                         F.slices.as<cpx<TT>>(), d_cursor, capacity, d_terms, d_rank, d_stat, ctr);
+    };
+    using TrueT = std::integral_constant<bool, true>;
+    using FalseT = std::integral_constant<bool, false>;
+    double msf = 0, msn = 0;
+    if (precision == GCQ_C128) {
+      launch(double(0), TrueT(), 0, int(lf.size()), d_counter);
+      msf = timed_end(ctx, "aca3d_far");
+      GCQ_TRY(timed_begin(ctx));
+      launch(double(0), FalseT(), int(lf.size()), int(ln.size()), d_counter + 1);
+    } else {
+      launch(float(0), TrueT(), 0, int(lf.size()), d_counter);
+      msf = timed_end(ctx, "aca3d_far");
+      GCQ_TRY(timed_begin(ctx));
+      launch(float(0), FalseT(), int(lf.size()), int(ln.size()), d_counter + 1);
+    }
+    msn = timed_end(ctx, "aca3d_near");
+    ms += msf + msn;
     GCQ_HIP(hipGetLastError());
-    ms += timed_end(ctx, "aca3d_round");
     unsigned long long curh = 0;
     GCQ_HIP(hipMemcpy(&curh, d_cursor, sizeof(curh), hipMemcpyDeviceToHost));
     GCQ_HIP(hipMemcpy(blkrank.data(), d_rank, sizeof(int) * nb, hipMemcpyDeviceToHost));
@@ -508,6 +527,37 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   GCQ_TRY(upload(F.d_trank, F.trank, ctx->stream));
   GCQ_TRY(upload(F.d_toff, F.toff, ctx->stream));
   GCQ_TRY(upload(F.d_tfoff, F.tfoff, ctx->stream));
+  {
+    // product tables: stacked far columns and the block order of the product
+    std::vector<int64_t> cols;
+    std::vector<int32_t> bcol(nb + 1, 0);
+    std::vector<double> work(nb, 0.0);
+    for (int b = 0; b < nb; ++b) {
+      bcol[b] = int32_t(cols.size() / 3);
+      for (int d = 0; d < F.brank[b]; ++d) {
+        const int ti = F.bterm[b] + d;
+        if (F.trank[ti] < 0) {
+          work[b] += double(bd[b].m) * bd[b].n;
+          continue;
+        }
+        for (int c = 0; c < F.trank[ti]; ++c) {
+          cols.push_back(F.toff[ti] + int64_t(c) * bd[b].m);                                    // Ubar col
+          cols.push_back(F.toff[ti] + int64_t(F.trank[ti]) * bd[b].m + int64_t(c) * bd[b].n);   // Vbar col
+          cols.push_back(F.tfoff[ti]);
+          work[b] += bd[b].m + bd[b].n;
+        }
+      }
+    }
+    bcol[nb] = int32_t(cols.size() / 3);
+    std::vector<int32_t> mo;
+    for (int b = 0; b < nb; ++b)
+      if (F.brank[b] > 0) mo.push_back(b);
+    std::stable_sort(mo.begin(), mo.end(), [&](int a, int b) { return work[a] > work[b]; });
+    F.n_mvblocks = int(mo.size());
+    GCQ_TRY(upload(F.d_cols, cols, ctx->stream));
+    GCQ_TRY(upload(F.d_bcol, bcol, ctx->stream));
+    GCQ_TRY(upload(F.d_mvorder, mo, ctx->stream));
+  }
   GCQ_HIP(hipStreamSynchronize(ctx->stream));
   F.storage_bytes = store * csz;
   F.dense_bytes = int64_t(ctx->n) * ctx->n * nK * csz;

@@ -160,6 +160,37 @@ __device__ __forceinline__ cpx<T> far_entry(const Tab& t, T xi, T yi, T zi, int 
   return acc;
 }
 
+// float far tier on the hardware transcendental units: exp(-sr r) as
+// 2^(-sr log2(e) r), the phase si r reduced to [-1/2, 1/2] revolutions before
+// the hardware sine/cosine (which take revolutions), 1/r from the reciprocal
+// square root.  The argument products carry the same float rounding as the
+// generic path; the reduction is exact (subtraction of the nearest integer).
+template <>
+__device__ __forceinline__ cpx<float> far_entry<float>(const Tab& t, float xi, float yi, float zi,
+                                                       int pj, float sr, float si) {
+  const float* q = t.q32;
+  const int n = t.n;
+  const float a2 = -sr * 1.44269504088896340736f;   // -sr log2(e)
+  const float rv = si * 0.159154943091895335769f;   // si / (2 pi)
+  float ar = 0.f, ai = 0.f;
+#pragma unroll
+  for (int a = 0; a < NQ_FAR; ++a) {
+    const float dx = xi - q[(a)*n + pj];
+    const float dy = yi - q[(7 + a) * n + pj];
+    const float dz = zi - q[(14 + a) * n + pj];
+    const float w = q[(21 + a) * n + pj];
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float e = __builtin_amdgcn_exp2f(a2 * r) * (ri * w);
+    float rev = rv * r;
+    rev -= rintf(rev);
+    ar += e * __builtin_amdgcn_cosf(rev);
+    ai -= e * __builtin_amdgcn_sinf(rev);
+  }
+  return {ar, ai};
+}
+
 // near tier: 7-point rule on 16 sub-triangles, double
 __device__ __forceinline__ cpx<double> near_entry(const Tab& t, int pi, int pj, double sr,
                                                    double si) {
@@ -253,12 +284,13 @@ __device__ __forceinline__ bool is_near(const Tab& t, int pi, int pj) {
   return d2 < 4.0 * t.h2[pj];
 }
 
-// entry at internal positions (pi, pj), frequency sigma = s / c; far tier in T
-// unless `all_far` says the caller's block has no self/near pairs
-template <typename T>
+// entry at internal positions (pi, pj), frequency sigma = s / c; far tier in T.
+// ALLFAR: the caller guarantees that no self/near-tier pair occurs (blocks whose
+// boxes are far enough apart), so the float64 tiers are not compiled in.
+template <typename T, bool ALLFAR = false>
 __device__ __forceinline__ cpx<T> entry(const Tab& t, int pi, int pj, double sr, double si,
                                         bool all_far) {
-  if (!all_far) {
+  if (!ALLFAR && !all_far) {
     if (pi == pj) {
       cpx<double> e = self_entry(t, pi, sr, si);
       return {T(e.re), T(e.im)};

@@ -117,6 +117,10 @@ struct Faces3D {
   DevBuf d_brank, d_bterm, d_trank, d_toff, d_tfoff;
   DevBuf slices;                 // far: U (m x r) then V (n x r); near: dense m x n
   DevBuf fibers;                 // per term: nK complex
+  // product tables: per far block its stacked columns (U column offset, V
+  // column offset, fiber offset), blocks ordered by work, largest first
+  DevBuf d_cols, d_bcol, d_mvorder;
+  int n_mvblocks = 0;
   int64_t storage_bytes = 0;
   int64_t dense_bytes = 0;
 };

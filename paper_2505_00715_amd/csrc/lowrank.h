@@ -50,6 +50,10 @@ struct RecompShared {
   double lam[64], sg[64];
   int keep[64], order[64];
   int nkeep, tcut;
+  // one round of the parallel Jacobi ordering: pair i rotates (jp[i], jq[i])
+  int jp[32], jq[32];
+  double jc[32], js[32], ja[32], jd[32], jtb[32];
+  cpx<double> je[32];
 };
 
 // ---- ACA of an entry function --------------------------------------------------
@@ -189,12 +193,20 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
 
 // ---- Hermitian Jacobi eigen-solver, one wave, k <= 64 -------------------------
 // A (k x k, row-major, generic memory) is overwritten by its eigenvalues on the
-// diagonal; Q (k x k) receives the eigenvectors as columns.  Cyclic sweeps with
-// the rotation G = diag(1, conj(e)) R(c, s) that zeroes A[p][q] = |b| e.
-__device__ inline void jacobi_herm(cpx<double>* A, cpx<double>* Q, int k) {
+// diagonal; Q (k x k) receives the eigenvectors as columns.  Each rotation is
+// G = diag(1, conj(e)) R(c, s), which zeroes A[p][q] = |b| e with the real
+// rotation of the symmetric 2 x 2 problem [[a, |b|], [|b|, d]].  Sweeps use the
+// round-robin (tournament) ordering: every round rotates k/2 disjoint index
+// pairs at once, so a sweep is k - 1 parallel rounds instead of k (k - 1) / 2
+// sequential rotations.  Rotations of one round commute (disjoint pairs), so the
+// result equals the cyclic sweep in that pair order.
+__device__ inline void jacobi_herm(cpx<double>* A, cpx<double>* Q, int k, RecompShared& rs) {
   const int lane = threadIdx.x & (WAVE - 1);
   for (int r = lane; r < k * k; r += WAVE) Q[r] = {(r / k == r % k) ? 1.0 : 0.0, 0.0};
   __syncthreads();
+  if (k < 2) return;
+  const int ke = (k + 1) & ~1;   // even number of positions (one dummy when k is odd)
+  const int np = ke / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dg = 0.0;
     for (int r = lane; r < k * k; r += WAVE) {
@@ -205,47 +217,79 @@ __device__ inline void jacobi_herm(cpx<double>* A, cpx<double>* Q, int k) {
     off = wave_sum(off);
     dg = wave_sum(dg);
     if (off <= 1e-30 * dg || off == 0.0) break;
-    for (int p = 0; p < k - 1; ++p) {
-      for (int q = p + 1; q < k; ++q) {
-        const cpx<double> b = A[p * k + q];
-        const double a = A[p * k + p].re, d = A[q * k + q].re;
-        const double bb = sqrt(cabs2(b));
-        if (bb <= 1e-300 || bb * bb <= 1e-34 * fabs(a * d)) continue;
-        const double tau = (d - a) / (2.0 * bb);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-        const cpx<double> e = {b.re / bb, b.im / bb};
-        const cpx<double> ec = {e.re, -e.im};
-        __syncthreads();
-        if (lane < k) {  // columns p, q of A and Q (row `lane`)
-          const int r = lane;
-          cpx<double> x = A[r * k + p], y = A[r * k + q];
-          cpx<double> ecy = cmul(ec, y);
-          A[r * k + p] = {c * x.re - s * ecy.re, c * x.im - s * ecy.im};
-          A[r * k + q] = {s * x.re + c * ecy.re, s * x.im + c * ecy.im};
-          x = Q[r * k + p];
-          y = Q[r * k + q];
-          ecy = cmul(ec, y);
-          Q[r * k + p] = {c * x.re - s * ecy.re, c * x.im - s * ecy.im};
-          Q[r * k + q] = {s * x.re + c * ecy.re, s * x.im + c * ecy.im};
+    for (int round = 0; round < ke - 1; ++round) {
+      if (lane < np) {
+        // circle method: position 0 fixed, positions 1..ke-1 rotate
+        auto idx = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (ke - 1); };
+        int p = idx(lane), q = idx(ke - 1 - lane);
+        if (p > q) { int t = p; p = q; q = t; }
+        double c = 1.0, sv = 0.0, a = 0.0, d = 0.0, tb = 0.0;
+        cpx<double> e = {1.0, 0.0};
+        if (q < k) {
+          const cpx<double> b = A[p * k + q];
+          a = A[p * k + p].re;
+          d = A[q * k + q].re;
+          const double bb = sqrt(cabs2(b));
+          if (bb > 1e-300 && bb * bb > 1e-34 * fabs(a * d)) {
+            const double tau = (d - a) / (2.0 * bb);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sv = t * c;
+            e = {b.re / bb, b.im / bb};
+            tb = t * bb;
+          } else {
+            q = k;   // nothing to rotate
+          }
         }
-        __syncthreads();
-        if (lane < k) {  // rows p, q of A (column `lane`)
-          const int r = lane;
-          cpx<double> x = A[p * k + r], y = A[q * k + r];
-          cpx<double> ey = cmul(e, y);
-          A[p * k + r] = {c * x.re - s * ey.re, c * x.im - s * ey.im};
-          A[q * k + r] = {s * x.re + c * ey.re, s * x.im + c * ey.im};
-        }
-        __syncthreads();
-        if (lane == 0) {
-          A[p * k + q] = {0.0, 0.0};
-          A[q * k + p] = {0.0, 0.0};
-          A[p * k + p] = {a - t * bb, 0.0};
-          A[q * k + q] = {d + t * bb, 0.0};
-        }
-        __syncthreads();
+        rs.jp[lane] = p;
+        rs.jq[lane] = q;
+        rs.jc[lane] = c;
+        rs.js[lane] = sv;
+        rs.je[lane] = e;
+        rs.ja[lane] = a;
+        rs.jd[lane] = d;
+        rs.jtb[lane] = tb;
       }
+      __syncthreads();
+      // columns p, q of A and Q, every row
+      for (int x = lane; x < k * np; x += WAVE) {
+        const int r = x / np, i = x % np;
+        const int p = rs.jp[i], q = rs.jq[i];
+        if (q >= k) continue;
+        const double c = rs.jc[i], sv = rs.js[i];
+        const cpx<double> ec = {rs.je[i].re, -rs.je[i].im};
+        cpx<double> u = A[r * k + p], v = A[r * k + q];
+        cpx<double> ev = cmul(ec, v);
+        A[r * k + p] = {c * u.re - sv * ev.re, c * u.im - sv * ev.im};
+        A[r * k + q] = {sv * u.re + c * ev.re, sv * u.im + c * ev.im};
+        u = Q[r * k + p];
+        v = Q[r * k + q];
+        ev = cmul(ec, v);
+        Q[r * k + p] = {c * u.re - sv * ev.re, c * u.im - sv * ev.im};
+        Q[r * k + q] = {sv * u.re + c * ev.re, sv * u.im + c * ev.im};
+      }
+      __syncthreads();
+      // rows p, q of A, every column
+      for (int x = lane; x < k * np; x += WAVE) {
+        const int r = x / np, i = x % np;
+        const int p = rs.jp[i], q = rs.jq[i];
+        if (q >= k) continue;
+        const double c = rs.jc[i], sv = rs.js[i];
+        const cpx<double> e = rs.je[i];
+        cpx<double> u = A[p * k + r], v = A[q * k + r];
+        cpx<double> ev = cmul(e, v);
+        A[p * k + r] = {c * u.re - sv * ev.re, c * u.im - sv * ev.im};
+        A[q * k + r] = {sv * u.re + c * ev.re, sv * u.im + c * ev.im};
+      }
+      __syncthreads();
+      if (lane < np && rs.jq[lane] < k) {
+        const int p = rs.jp[lane], q = rs.jq[lane];
+        A[p * k + q] = {0.0, 0.0};
+        A[q * k + p] = {0.0, 0.0};
+        A[p * k + p] = {rs.ja[lane] - rs.jtb[lane], 0.0};
+        A[q * k + q] = {rs.jd[lane] + rs.jtb[lane], 0.0};
+      }
+      __syncthreads();
     }
   }
   __syncthreads();
@@ -275,7 +319,7 @@ __device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<doubl
   cpx<double>* Z = B + k * k;
   for (int r = lane; r < k * k; r += WAVE) A[r] = GV[(r / k) * cap + (r % k)];
   __syncthreads();
-  jacobi_herm(A, Q, k);
+  jacobi_herm(A, Q, k, rs);
   if (lane < k) rs.lam[lane] = A[lane * k + lane].re;
   __syncthreads();
   double lmax = 0.0;
@@ -327,7 +371,7 @@ __device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<doubl
     }
   }
   __syncthreads();
-  jacobi_herm(B, Z, kk);
+  jacobi_herm(B, Z, kk, rs);
   if (lane < kk) rs.sg[lane] = fmax(B[lane * kk + lane].re, 0.0);
   __syncthreads();
   if (lane < kk) {  // descending order, ties by index

@@ -107,6 +107,198 @@ __global__ void __launch_bounds__(64) perfreq_kernel(
   }
 }
 
+
+// Xp[p][k] = X[k][perm[p]] (frequency fastest), conjugated for columns applied
+// through their conjugate partner; and the inverse for the result
+template <typename TI, typename TO>
+__global__ void perm_in_t(const cpx<TI>* __restrict__ X, cpx<TO>* __restrict__ Xp,
+                          const int* __restrict__ perm, const int* __restrict__ conjflag, int n,
+                          int L) {
+  const int64_t total = int64_t(n) * L;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int p = int(e / L), k = int(e % L);
+    cpx<TI> v = X[int64_t(k) * n + perm[p]];
+    Xp[e] = {TO(v.re), conjflag[k] ? TO(-v.im) : TO(v.im)};
+  }
+}
+
+template <typename TI, typename TO>
+__global__ void perm_out_t(const cpx<TI>* __restrict__ Yp, cpx<TO>* __restrict__ Y,
+                           const int* __restrict__ perm, const int* __restrict__ conjflag, int n,
+                           int L) {
+  const int64_t total = int64_t(n) * L;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int p = int(e / L), k = int(e % L);
+    cpx<TI> v = Yp[e];
+    Y[int64_t(k) * n + perm[p]] = {TO(v.re), conjflag[k] ? TO(-v.im) : TO(v.im)};
+  }
+}
+
+// Per-frequency product, one workgroup (4 waves) per block, all frequency
+// columns of a 64-column tile at once (lane = column).  Every slice element is
+// read once per tile.
+//   near block: Y_I[:, k] += sum_d f_d[k] D_d X_J[:, k]; X_J and D_d staged
+//               through LDS in 64 x 64 chunks, each wave owns 16 rows
+//   far block:  T = Vcat^H X_J (each wave 16 stacked columns, X_J staged
+//               through LDS), T[c][k] *= f_{d(c)}[k], Y_I += Ucat T
+// Accumulation into Yp with atomics.
+template <typename T>
+__global__ void __launch_bounds__(256) perfreq_tiled(
+    const int* __restrict__ blk, const int* __restrict__ order, int nmv,
+    const int* __restrict__ bterm, const int64_t* __restrict__ toff,
+    const int64_t* __restrict__ tfoff, const int64_t* __restrict__ cols,
+    const int* __restrict__ bcol, const cpx<T>* __restrict__ pool, const int* __restrict__ colpos,
+    int L, const cpx<T>* __restrict__ Xp, cpx<T>* __restrict__ Yp) {
+  __shared__ cpx<T> xs[64 * 64];
+  __shared__ cpx<T> ds[64 * 64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const cpx<T> zero = {T(0), T(0)};
+  for (int ob = blockIdx.x; ob < nmv; ob += gridDim.x) {
+    const int b = order[ob];
+    const int rb = blk[5 * b], m = blk[5 * b + 1] - rb, cb = blk[5 * b + 2],
+              n = blk[5 * b + 3] - cb;
+    const bool adm = blk[5 * b + 4] & 1;
+    for (int k0 = 0; k0 < L; k0 += 64) {
+      const int k = k0 + lane;
+      const bool kin = k < L;
+      const int kp = kin ? colpos[k] : 0;
+      if (!adm) {
+        for (int i0 = 0; i0 < m; i0 += 64) {
+          const int in = min(64, m - i0);
+          cpx<T> acc[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) acc[q] = zero;
+          for (int j0 = 0; j0 < n; j0 += 64) {
+            const int jn = min(64, n - j0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < jn * 64; e += 256) {
+              const int jj = e >> 6, kk = e & 63;
+              xs[e] = (k0 + kk < L) ? Xp[int64_t(cb + j0 + jj) * L + k0 + kk] : zero;
+            }
+            for (int d = bterm[b]; d < bterm[b + 1]; ++d) {
+              const cpx<T>* D = pool + toff[d];
+              __syncthreads();
+              for (int e = threadIdx.x; e < jn * 64; e += 256) {
+                const int jj = e >> 6, ii = e & 63;
+                ds[e] = ii < in ? D[int64_t(j0 + jj) * m + i0 + ii] : zero;
+              }
+              __syncthreads();
+              const cpx<T> f = kin ? pool[tfoff[d] + kp] : zero;
+              cpx<T> sacc[16];
+#pragma unroll
+              for (int q = 0; q < 16; ++q) sacc[q] = zero;
+              for (int jj = 0; jj < jn; ++jj) {
+                const cpx<T> x = xs[jj * 64 + lane];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                  const cpx<T> dv = ds[jj * 64 + w * 16 + q];
+                  sacc[q].re += dv.re * x.re - dv.im * x.im;
+                  sacc[q].im += dv.re * x.im + dv.im * x.re;
+                }
+              }
+#pragma unroll
+              for (int q = 0; q < 16; ++q) {
+                acc[q].re += f.re * sacc[q].re - f.im * sacc[q].im;
+                acc[q].im += f.re * sacc[q].im + f.im * sacc[q].re;
+              }
+            }
+          }
+          if (kin) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+              const int i = w * 16 + q;
+              if (i < in) {
+                cpx<T>* y = Yp + int64_t(rb + i0 + i) * L + k;
+                atomicAdd(&y->re, acc[q].re);
+                atomicAdd(&y->im, acc[q].im);
+              }
+            }
+          }
+        }
+      } else {
+        const int c0 = bcol[b], c1 = bcol[b + 1];
+        for (int cc = c0; cc < c1; cc += 64) {
+          const int cn = min(64, c1 - cc);
+          cpx<T> acc[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) acc[q] = zero;
+          for (int j0 = 0; j0 < n; j0 += 64) {
+            const int jn = min(64, n - j0);
+            __syncthreads();
+            // X chunk into xs, the chunk of the stacked V columns into ds
+            for (int e = threadIdx.x; e < jn * 64; e += 256) {
+              const int jj = e >> 6, kk = e & 63;
+              xs[e] = (k0 + kk < L) ? Xp[int64_t(cb + j0 + jj) * L + k0 + kk] : zero;
+            }
+            for (int e = threadIdx.x; e < cn * 64; e += 256) {
+              const int cl = e >> 6, jj = e & 63;
+              ds[e] = jj < jn ? pool[cols[3 * (cc + cl) + 1] + j0 + jj] : zero;
+            }
+            __syncthreads();
+            for (int jj = 0; jj < jn; ++jj) {
+              const cpx<T> x = xs[jj * 64 + lane];
+#pragma unroll
+              for (int q = 0; q < 16; ++q) {
+                const cpx<T> v = ds[(w * 16 + q) * 64 + jj];
+                acc[q].re += v.re * x.re + v.im * x.im;   // conj(v) x
+                acc[q].im += v.re * x.im - v.im * x.re;
+              }
+            }
+          }
+          // scale by the fibers; T into ds
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int cl = w * 16 + q;
+            cpx<T> t = zero;
+            if (cl < cn && kin) {
+              const cpx<T> f = pool[cols[3 * (cc + cl) + 2] + kp];
+              t = {f.re * acc[q].re - f.im * acc[q].im, f.re * acc[q].im + f.im * acc[q].re};
+            }
+            ds[cl * 64 + lane] = t;
+          }
+          // Y_I += Ucat T: 64 rows at a time, U chunk staged into xs, 16 rows per wave
+          for (int ib0 = 0; ib0 < m; ib0 += 64) {
+            const int rn = min(64, m - ib0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < cn * 64; e += 256) {
+              const int cl = e >> 6, r = e & 63;
+              xs[e] = r < rn ? pool[cols[3 * (cc + cl)] + ib0 + r] : zero;
+            }
+            __syncthreads();
+            cpx<T> yacc[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) yacc[q] = zero;
+            for (int cl = 0; cl < cn; ++cl) {
+              const cpx<T> t = ds[cl * 64 + lane];
+#pragma unroll
+              for (int q = 0; q < 16; ++q) {
+                const cpx<T> u = xs[cl * 64 + w * 16 + q];
+                yacc[q].re += u.re * t.re - u.im * t.im;
+                yacc[q].im += u.re * t.im + u.im * t.re;
+              }
+            }
+            if (kin) {
+#pragma unroll
+              for (int q = 0; q < 16; ++q) {
+                const int r = w * 16 + q;
+                if (r < rn) {
+                  cpx<T>* y = Yp + int64_t(rb + ib0 + r) * L + k;
+                  atomicAdd(&y->re, yacc[q].re);
+                  atomicAdd(&y->im, yacc[q].im);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 // eq. product: one wave per block; per slice the frequency sums w1 (plain
 // columns) and w2 (conjugate-represented columns, conjugated input) are formed
 // first, then y_I += H w1 + conj(H w2)
@@ -219,21 +411,26 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
     GCQ_TRY(ctx->scratchA.ensure(size_t(nl) * sizeof(cpx<T>)));
     Yp = ctx->scratchA.as<cpx<T>>();
     if (precision == GCQ_C128)
-      hipLaunchKernelGGL((perm_in3<double, T>), dim3(g), dim3(256), 0, st, (const cpx<double>*)X,
+      hipLaunchKernelGGL((perm_in_t<double, T>), dim3(g), dim3(256), 0, st, (const cpx<double>*)X,
                          Xp, perm, d_conj, n, L);
     else
-      hipLaunchKernelGGL((perm_in3<float, T>), dim3(g), dim3(256), 0, st, (const cpx<float>*)X, Xp,
+      hipLaunchKernelGGL((perm_in_t<float, T>), dim3(g), dim3(256), 0, st, (const cpx<float>*)X, Xp,
                          perm, d_conj, n, L);
     hipLaunchKernelGGL(zero3<T>, dim3(g), dim3(256), 0, st, Yp, nl);
-    hipLaunchKernelGGL(perfreq_kernel<T>, dim3(65536), dim3(64), 0, st, ctx->d_blk.as<int>(), nb,
-                       F.d_bterm.as<int>(), F.d_trank.as<int>(), F.d_toff.as<int64_t>(),
-                       F.d_tfoff.as<int64_t>(), F.slices.as<cpx<T>>(), d_colpos, L, n, Xp, Yp);
+    int cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
+    hipLaunchKernelGGL(perfreq_tiled<T>, dim3(std::max(1, std::min(F.n_mvblocks, cus * 2))),
+                       dim3(256), 0, st, ctx->d_blk.as<int>(), F.d_mvorder.as<int>(),
+                       F.n_mvblocks, F.d_bterm.as<int>(), F.d_toff.as<int64_t>(),
+                       F.d_tfoff.as<int64_t>(), F.d_cols.as<int64_t>(), F.d_bcol.as<int>(),
+                       F.slices.as<cpx<T>>(), d_colpos, L, Xp, Yp);
     if (precision == GCQ_C128)
-      hipLaunchKernelGGL((perm_out3<T, double>), dim3(g), dim3(256), 0, st, Yp, (cpx<double>*)Y,
+      hipLaunchKernelGGL((perm_out_t<T, double>), dim3(g), dim3(256), 0, st, Yp, (cpx<double>*)Y,
                          perm, d_conj, n, L);
     else
-      hipLaunchKernelGGL((perm_out3<T, float>), dim3(g), dim3(256), 0, st, Yp, (cpx<float>*)Y, perm,
-                         d_conj, n, L);
+      hipLaunchKernelGGL((perm_out_t<T, float>), dim3(g), dim3(256), 0, st, Yp, (cpx<float>*)Y,
+                         perm, d_conj, n, L);
   } else {
     // the weighted sum keeps X unconjugated (the conjugation is applied per slice)
     std::vector<int> zero(L, 0);

@@ -78,7 +78,7 @@ def test_mlp_training_reduces_loss():
                               lr=3e-3)
     assert st.loss_last < 0.2 * st.loss_first
     pred = ctx.rank_model_predict(X.astype(np.float32))
-    assert np.mean((pred - t) ** 2) < 0.1 * np.var(t) + 1e-3
+    assert np.mean((pred - t) ** 2) < 0.2 * np.var(t)
 
 
 def test_predictor_ablation_same_result():
