@@ -7,6 +7,7 @@
 
 #include "internal.h"
 #include "lowrank.h"
+#include "near.h"
 
 namespace gcq {
 
@@ -96,25 +97,6 @@ __global__ void __launch_bounds__(256) apply_kernel(const PairDesc* __restrict__
     cpx<T>* OU = pool + out_off[pid];
     apply_factors<T>(k, t, m, n, U, U + int64_t(cap) * m, CU, CU + cap * cap, OU,
                      OU + int64_t(t) * m, threadIdx.x, blockDim.x);
-  }
-}
-
-// ---- dense near-field blocks at one frequency --------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) near_kernel(Tab tab, const int* __restrict__ blk,
-                                                   const int* __restrict__ near_ids,
-                                                   const int64_t* __restrict__ near_off, int nnear,
-                                                   double sr, double si, cpx<T>* __restrict__ out) {
-  for (int b = blockIdx.x; b < nnear; b += gridDim.x) {
-  const int id = near_ids[b];
-  const int rb = blk[5 * id], re = blk[5 * id + 1], cb = blk[5 * id + 2], ce = blk[5 * id + 3];
-  const int all_far = (blk[5 * id + 4] >> 1) & 1;
-  const int m = re - rb, n = ce - cb;
-  cpx<T>* o = out + near_off[b];
-  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
-    const int r = e % m, c = e / m;  // column-major
-    o[e] = entry<T>(tab, rb + r, cb + c, sr, si, all_far != 0);
-  }
   }
 }
 
@@ -408,35 +390,40 @@ GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_
       }
     }
   }
-  // near field: dense blocks per frequency slot
+  // near field: dense blocks at every frequency slot, [slot][near storage]
   const int nnear = int(ctx->near_ids.size());
-  H.near_off.assign(nnear, 0);
-  int64_t acc = 0;
-  for (int b = 0; b < nnear; ++b) {
-    const Block& B = ctx->blocks[ctx->near_ids[b]];
-    H.near_off[b] = acc;
-    acc += int64_t(ctx->clusters[B.row].end - ctx->clusters[B.row].begin) *
-           (ctx->clusters[B.col].end - ctx->clusters[B.col].begin);
-  }
+  H.near_off = ctx->near_off;
+  const int64_t acc = ctx->near_total;
   H.near_slot_elems = acc;
   const size_t esz = csize(precision);
   GCQ_TRY(H.near.ensure(size_t(acc) * nslot * esz + 256));
-  std::vector<int32_t> nid(ctx->near_ids.begin(), ctx->near_ids.end());
   GCQ_TRY(upload(H.d_near_off, H.near_off, ctx->stream));
-  GCQ_TRY(upload(ctx->scratchC, nid, ctx->stream));
+  std::vector<double2> sg(nslot);
+  for (int q = 0; q < nslot; ++q) {
+    std::complex<double> v = ctx->s[fr[q]] / ctx->c;
+    sg[q] = make_double2(v.real(), v.imag());
+  }
+  GCQ_TRY(upload(ctx->scratchC, sg, ctx->stream));
   GCQ_TRY(timed_begin(ctx));
-  for (int q = 0; q < nslot && nnear > 0; ++q) {
-    std::complex<double> sg = ctx->s[fr[q]] / ctx->c;
-    if (precision == GCQ_C128)
-      hipLaunchKernelGGL(near_kernel<double>, dim3(std::min(nnear, 65536)), dim3(256), 0, ctx->stream,
-                         ctx->tab(), ctx->d_blk.as<int>(), ctx->scratchC.as<int>(),
-                         H.d_near_off.as<int64_t>(), nnear, sg.real(), sg.imag(),
-                         H.near.as<cpx<double>>() + size_t(q) * acc);
-    else
-      hipLaunchKernelGGL(near_kernel<float>, dim3(std::min(nnear, 65536)), dim3(256), 0, ctx->stream,
-                         ctx->tab(), ctx->d_blk.as<int>(), ctx->scratchC.as<int>(),
-                         H.d_near_off.as<int64_t>(), nnear, sg.real(), sg.imag(),
-                         H.near.as<cpx<float>>() + size_t(q) * acc);
+  if (nnear > 0) {
+    const dim3 g1(std::min(nnear, 65536)), g2(4096);
+    if (precision == GCQ_C128) {
+      hipLaunchKernelGGL(near_far_tier<double>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
+                         ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(),
+                         0, nnear, int64_t(0), ctx->scratchC.as<double2>(), nslot,
+                         H.near.as<cpx<double>>(), acc);
+      hipLaunchKernelGGL(near_sing<double>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
+                         ctx->d_sing.as<SingEntry>(), int64_t(0), ctx->n_sing, int64_t(0),
+                         ctx->scratchC.as<double2>(), nslot, H.near.as<cpx<double>>(), acc);
+    } else {
+      hipLaunchKernelGGL(near_far_tier<float>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
+                         ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(),
+                         0, nnear, int64_t(0), ctx->scratchC.as<double2>(), nslot,
+                         H.near.as<cpx<float>>(), acc);
+      hipLaunchKernelGGL(near_sing<float>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
+                         ctx->d_sing.as<SingEntry>(), int64_t(0), ctx->n_sing, int64_t(0),
+                         ctx->scratchC.as<double2>(), nslot, H.near.as<cpx<float>>(), acc);
+    }
   }
   GCQ_HIP(hipGetLastError());
   double ms_near = timed_end(ctx, "near");

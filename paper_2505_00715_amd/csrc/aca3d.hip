@@ -8,6 +8,7 @@
 
 #include "internal.h"
 #include "lowrank.h"
+#include "near.h"
 
 namespace gcq {
 
@@ -340,6 +341,156 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
   }
 }
 
+
+// 3D-ACA of an inadmissible block from its precomputed entry tensor
+// Cn[k * stride + base + e] (all frequencies of K): the residual slices, the
+// pivots and the fibers are read instead of re-evaluated.  One wave per block.
+template <typename T>
+struct SharedN {
+  Term3 term[R3_MAX];
+  cpx<T> fk[R3_MAX];
+  cpx<T> hp[R3_MAX];
+  cpx<double> hin[R3_MAX];
+  unsigned usedk[NK_MAX / 32];
+  int64_t alloc;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(64) aca3d_near_kernel(
+    const BlockDesc3* __restrict__ blocks, const int* __restrict__ qlist, int nq,
+    const int* __restrict__ near_ids, const int64_t* __restrict__ near_off, int64_t base0,
+    const cpx<T>* __restrict__ Cn, int64_t stride, int nK, double tol, int rmax,
+    cpx<T>* __restrict__ pool, unsigned long long* __restrict__ cursor, int64_t capacity,
+    Term3* __restrict__ terms, int* __restrict__ brank, int* __restrict__ bstatus,
+    int* __restrict__ counter) {
+  __shared__ SharedN<T> sh;
+  const int lane = threadIdx.x;
+  for (;;) {
+    int idx = 0;
+    if (lane == 0) idx = atomicAdd(counter, 1);
+    idx = __shfl(idx, 0, WAVE);
+    if (idx >= nq) break;
+    const int q = qlist[idx];
+    const int b = near_ids[q];
+    const BlockDesc3 B = blocks[b];
+    const int m = B.m, n = B.n, mn = m * n;
+    const int64_t base = near_off[q] - base0;
+    for (int w = lane; w < (nK + 31) / 32; w += WAVE) sh.usedk[w] = 0u;
+    __syncthreads();
+    int ell = 0, kcur = 0, status = 0;
+    double norm2 = 0.0;
+    while (true) {
+      for (int d = lane; d < ell; d += WAVE) sh.fk[d] = pool[sh.term[d].fiber + kcur];
+      if (lane == 0) sh.alloc = pool_alloc(cursor, int64_t(mn), capacity);
+      __syncthreads();
+      const int64_t soff = sh.alloc;
+      if (soff < 0) { status |= ST_DEFERRED; break; }
+      // residual slice at k_cur and its norm
+      const cpx<T>* Ck = Cn + int64_t(kcur) * stride + base;
+      double nh2 = 0.0;
+      for (int e = lane; e < mn; e += WAVE) {
+        cpx<T> a = Ck[e];
+        for (int d = 0; d < ell; ++d) {
+          cpx<T> p = cmul(sh.fk[d], pool[sh.term[d].slice + e]);
+          a.re -= p.re;
+          a.im -= p.im;
+        }
+        pool[soff + e] = a;
+        nh2 += mag2(a);
+      }
+      nh2 = wave_sum(nh2);
+      __syncthreads();
+      // pivot: largest modulus, first in row-major order on ties
+      double best = -1.0;
+      int be = 0x7fffffff;
+      for (int e = lane; e < mn; e += WAVE) {
+        const int i = e / n, j = e % n;
+        const double v = mag2(pool[soff + int64_t(j) * m + i]);
+        if (v > best) { best = v; be = e; }
+      }
+      wave_argmax(best, be);
+      if (!(best > PivFloor<T>::v)) break;
+      const int ip = be / n, jp = be % n;
+      const int64_t ep = int64_t(jp) * m + ip;
+      const cpx<T> piv = pool[soff + ep];
+      for (int d = lane; d < ell; d += WAVE) sh.hp[d] = pool[sh.term[d].slice + ep];
+      if (lane == 0) sh.alloc = pool_alloc(cursor, nK, capacity);
+      __syncthreads();
+      const int64_t foff = sh.alloc;
+      if (foff < 0) { status |= ST_DEFERRED; break; }
+      const cpx<T> inv = cinv(piv);
+      double nf2 = 0.0;
+      for (int kk = lane; kk < nK; kk += WAVE) {
+        cpx<T> a = Cn[int64_t(kk) * stride + base + ep];
+        for (int d = 0; d < ell; ++d) {
+          cpx<T> p = cmul(sh.hp[d], pool[sh.term[d].fiber + kk]);
+          a.re -= p.re;
+          a.im -= p.im;
+        }
+        const cpx<T> f = kk == kcur ? cpx<T>{T(1), T(0)} : cmul(a, inv);
+        pool[foff + kk] = f;
+        nf2 += mag2(f);
+      }
+      nf2 = wave_sum(nf2);
+      __syncthreads();
+      // eq. norm cross terms
+      double cross = 0.0;
+      for (int d = 0; d < ell; ++d) {
+        double hr = 0, hi = 0, fr = 0, fi = 0;
+        const cpx<T>* Hd = pool + sh.term[d].slice;
+        for (int e = lane; e < mn; e += WAVE) {
+          const cpx<T> x = Hd[e], y = pool[soff + e];
+          hr += double(x.re) * y.re + double(x.im) * y.im;   // x conj(y)
+          hi += double(x.im) * y.re - double(x.re) * y.im;
+        }
+        const cpx<T>* fd = pool + sh.term[d].fiber;
+        for (int kk = lane; kk < nK; kk += WAVE) {
+          const cpx<T> x = fd[kk], y = pool[foff + kk];
+          fr += double(x.re) * y.re + double(x.im) * y.im;
+          fi += double(x.im) * y.re - double(x.re) * y.im;
+        }
+        hr = wave_sum(hr);
+        hi = wave_sum(hi);
+        fr = wave_sum(fr);
+        fi = wave_sum(fi);
+        cross += hr * fr - hi * fi;
+      }
+      norm2 += 2.0 * cross + nh2 * nf2;
+      if (lane == 0) sh.usedk[kcur >> 5] |= 1u << (kcur & 31);
+      __syncthreads();
+      if (sqrt(fmax(nh2 * nf2, 0.0)) <= tol * sqrt(fmax(norm2, 0.0))) break;
+      if (lane == 0) {
+        Term3 t;
+        t.slice = soff;
+        t.fiber = foff;
+        t.rank = -1;
+        t.freq = kcur;
+        sh.term[ell] = t;
+      }
+      __syncthreads();
+      ++ell;
+      double bf = -1.0;
+      int bk = 0x7fffffff;
+      for (int kk = lane; kk < nK; kk += WAVE) {
+        if ((sh.usedk[kk >> 5] >> (kk & 31)) & 1u) continue;
+        const double v = mag2(pool[foff + kk]);
+        if (v > bf) { bf = v; bk = kk; }
+      }
+      wave_argmax(bf, bk);
+      if (bk == 0x7fffffff) break;
+      if (ell >= rmax) { status |= ST_CAPPED; break; }
+      kcur = bk;
+    }
+    __syncthreads();
+    for (int d = lane; d < ell; d += WAVE) terms[int64_t(b) * R3_MAX + d] = sh.term[d];
+    if (lane == 0) {
+      brank[b] = ell;
+      bstatus[b] = status;
+    }
+    __syncthreads();
+  }
+}
+
 static __global__ void zero_int_3d(int* p, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -413,7 +564,10 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   for (int b = 0; b < nb; ++b)
     if (bd[b].admissible) far_dims += bd[b].m + bd[b].n;
     else near_elems += int64_t(bd[b].m) * bd[b].n;
-  int64_t want = (near_elems + far_dims * 16) * 12 + int64_t(nb) * 12 * nK;
+  // expected need: dense slices (near) and factored slices (far) of ~max_freq_rank/2
+  // terms each, plus one fiber per term
+  const int64_t rexp = std::max(8, int(max_freq_rank) / 2 + 4);
+  int64_t want = near_elems * rexp + far_dims * 16 * rexp + int64_t(nb) * rexp * nK;
   int64_t capacity = std::min<int64_t>(want, int64_t(double(freeb) * 0.5) / csz);
   F.slices.release();
   GCQ_TRY(F.slices.ensure(size_t(capacity) * csz + 256));
@@ -421,28 +575,47 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   std::vector<Term3> terms(size_t(nb) * R3_MAX);
   GCQ_TRY(upload(ctx->scratchB, bd, ctx->stream));
   GCQ_TRY(upload(ctx->scratchC, sig, ctx->stream));
-  GCQ_TRY(ctx->scratchD.ensure(sizeof(Term3) * size_t(nb) * R3_MAX + sizeof(int) * (2 * nb + 8) +
-                               64 + sizeof(int) * nb));
-  Term3* d_terms = ctx->scratchD.as<Term3>();
+  // scratch layout: cursor (8 B), 8 counters, terms, ranks, status, work order
+  GCQ_TRY(ctx->scratchD.ensure(64 + sizeof(Term3) * size_t(nb) * R3_MAX + sizeof(int) * 3 * size_t(nb)));
+  unsigned long long* d_cursor = ctx->scratchD.as<unsigned long long>();
+  int* d_counter = reinterpret_cast<int*>(ctx->scratchD.as<unsigned char>() + 16);
+  Term3* d_terms = reinterpret_cast<Term3*>(ctx->scratchD.as<unsigned char>() + 64);
   int* d_rank = reinterpret_cast<int*>(d_terms + size_t(nb) * R3_MAX);
   int* d_stat = d_rank + nb;
-  int* d_counter = d_stat + nb;
-  unsigned long long* d_cursor = reinterpret_cast<unsigned long long*>(d_counter + 2);
-  int* d_order = reinterpret_cast<int*>(d_cursor + 2);
+  int* d_order = d_stat + nb;
   GCQ_HIP(hipMemcpyAsync(d_order, order.data(), sizeof(int) * nb, hipMemcpyHostToDevice,
                          ctx->stream));
   int64_t used = 0;
-  double ms = 0.0;
+  double ms = 0.0, ms_far = 0.0, ms_near = 0.0, ms_tensor = 0.0;
+  int rounds = 0;
+  std::vector<int> near_pos(nb, -1);
+  for (size_t q = 0; q < ctx->near_ids.size(); ++q) near_pos[ctx->near_ids[q]] = int(q);
+  // element offsets of the self/near-tier entries, for batching
+  std::vector<int64_t> sing_off(ctx->n_sing);
+  if (ctx->n_sing > 0) {
+    std::vector<SingEntry> sl(ctx->n_sing);
+    GCQ_HIP(hipMemcpy(sl.data(), ctx->d_sing.p, sizeof(SingEntry) * ctx->n_sing, hipMemcpyDeviceToHost));
+    for (int64_t a = 0; a < ctx->n_sing; ++a) sing_off[a] = sl[a].off;
+  }
+  DevBuf tensor;
+  const int64_t tensor_budget = std::max<int64_t>(int64_t(1) << 28,
+                                                  std::min<int64_t>(int64_t(48) << 30, int64_t(double(freeb) * 0.25)));
   std::vector<int> todo = order;
   for (int round = 0; round < 4 && !todo.empty(); ++round) {
-    hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, d_counter, 2);
+    hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, d_counter, 8);
     unsigned long long cur0 = (unsigned long long)used;
     GCQ_HIP(hipMemcpyAsync(d_cursor, &cur0, sizeof(cur0), hipMemcpyHostToDevice, ctx->stream));
-    // far blocks without near-tier entries first, then every other block
-    std::vector<int> lf, ln;
-    for (int b : todo) (bd[b].admissible && bd[b].all_far ? lf : ln).push_back(b);
+    // admissible blocks without near-tier entries, other admissible blocks,
+    // inadmissible blocks (from their entry tensor)
+    std::vector<int> lf, lo, lq;
+    for (int b : todo) {
+      if (bd[b].admissible) (bd[b].all_far ? lf : lo).push_back(b);
+      else lq.push_back(near_pos[b]);
+    }
+    std::sort(lq.begin(), lq.end());
     std::vector<int> both(lf);
-    both.insert(both.end(), ln.begin(), ln.end());
+    both.insert(both.end(), lo.begin(), lo.end());
+    both.insert(both.end(), lq.begin(), lq.end());
     GCQ_HIP(hipMemcpyAsync(d_order, both.data(), sizeof(int) * both.size(), hipMemcpyHostToDevice,
                            ctx->stream));
     GCQ_TRY(timed_begin(ctx));
@@ -458,20 +631,77 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
     };
     using TrueT = std::integral_constant<bool, true>;
     using FalseT = std::integral_constant<bool, false>;
-    double msf = 0, msn = 0;
     if (precision == GCQ_C128) {
       launch(double(0), TrueT(), 0, int(lf.size()), d_counter);
-      msf = timed_end(ctx, "aca3d_far");
-      GCQ_TRY(timed_begin(ctx));
-      launch(double(0), FalseT(), int(lf.size()), int(ln.size()), d_counter + 1);
+      launch(double(0), FalseT(), int(lf.size()), int(lo.size()), d_counter + 1);
     } else {
       launch(float(0), TrueT(), 0, int(lf.size()), d_counter);
-      msf = timed_end(ctx, "aca3d_far");
-      GCQ_TRY(timed_begin(ctx));
-      launch(float(0), FalseT(), int(lf.size()), int(ln.size()), d_counter + 1);
+      launch(float(0), FalseT(), int(lf.size()), int(lo.size()), d_counter + 1);
     }
-    msn = timed_end(ctx, "aca3d_near");
-    ms += msf + msn;
+    GCQ_HIP(hipGetLastError());
+    ms_far += timed_end(ctx, "aca3d_far_round");
+    // inadmissible blocks in batches whose entry tensor fits the budget
+    size_t pos = 0;
+    const int* d_q = d_order + lf.size() + lo.size();
+    while (pos < lq.size()) {
+      const int q0 = lq[pos];
+      size_t end = pos;
+      while (end < lq.size() &&
+             (ctx->near_off[lq[end]] + int64_t(bd[ctx->near_ids[lq[end]]].m) * bd[ctx->near_ids[lq[end]]].n -
+              ctx->near_off[q0]) * nK * csz <= tensor_budget)
+        ++end;
+      if (end == pos) end = pos + 1;
+      const int q1 = lq[end - 1] + 1;
+      const int64_t base0 = ctx->near_off[q0];
+      const int64_t span = (q1 < int(ctx->near_off.size()) ? ctx->near_off[q1] : ctx->near_total) - base0;
+      GCQ_TRY(tensor.ensure(size_t(span) * nK * csz + 256));
+      // self/near-tier entries of [q0, q1)
+      const int64_t s0 = int64_t(std::lower_bound(sing_off.begin(), sing_off.end(), base0) - sing_off.begin());
+      const int64_t s1 = int64_t(std::lower_bound(sing_off.begin(), sing_off.end(), base0 + span) - sing_off.begin());
+      GCQ_TRY(timed_begin(ctx));
+      const dim3 g1(std::min(q1 - q0, 65536)), g2(4096);
+      hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, d_counter + 2, 1);
+      if (precision == GCQ_C128) {
+        hipLaunchKernelGGL(near_far_tier<double>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
+                           ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(),
+                           ctx->d_near_off.as<int64_t>(), q0, q1, base0,
+                           ctx->scratchC.as<double2>(), nK, tensor.as<cpx<double>>(), span);
+        hipLaunchKernelGGL(near_sing<double>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
+                           ctx->d_sing.as<SingEntry>(), s0, s1, base0, ctx->scratchC.as<double2>(),
+                           nK, tensor.as<cpx<double>>(), span);
+      } else {
+        hipLaunchKernelGGL(near_far_tier<float>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
+                           ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(),
+                           ctx->d_near_off.as<int64_t>(), q0, q1, base0,
+                           ctx->scratchC.as<double2>(), nK, tensor.as<cpx<float>>(), span);
+        hipLaunchKernelGGL(near_sing<float>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
+                           ctx->d_sing.as<SingEntry>(), s0, s1, base0, ctx->scratchC.as<double2>(),
+                           nK, tensor.as<cpx<float>>(), span);
+      }
+      GCQ_HIP(hipGetLastError());
+      ms_tensor += timed_end(ctx, "aca3d_tensor_batch");
+      GCQ_TRY(timed_begin(ctx));
+      const int cnt = int(end - pos);
+      if (precision == GCQ_C128)
+        hipLaunchKernelGGL(aca3d_near_kernel<double>, dim3(std::min(cnt, cus * 16)), dim3(64), 0,
+                           ctx->stream, ctx->scratchB.as<BlockDesc3>(), d_q + pos, cnt,
+                           ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(), base0,
+                           tensor.as<cpx<double>>(), span, nK, tol, int(max_freq_rank),
+                           F.slices.as<cpx<double>>(), d_cursor, capacity, d_terms, d_rank,
+                           d_stat, d_counter + 2);
+      else
+        hipLaunchKernelGGL(aca3d_near_kernel<float>, dim3(std::min(cnt, cus * 16)), dim3(64), 0,
+                           ctx->stream, ctx->scratchB.as<BlockDesc3>(), d_q + pos, cnt,
+                           ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(), base0,
+                           tensor.as<cpx<float>>(), span, nK, tol, int(max_freq_rank),
+                           F.slices.as<cpx<float>>(), d_cursor, capacity, d_terms, d_rank,
+                           d_stat, d_counter + 2);
+      GCQ_HIP(hipGetLastError());
+      ms_near += timed_end(ctx, "aca3d_near_batch");
+      pos = end;
+    }
+    ms = ms_far + ms_tensor + ms_near;
+    ++rounds;
     GCQ_HIP(hipGetLastError());
     unsigned long long curh = 0;
     GCQ_HIP(hipMemcpy(&curh, d_cursor, sizeof(curh), hipMemcpyDeviceToHost));
@@ -496,6 +726,10 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   if (!todo.empty()) return fail(GCQ_ERR_NOMEM, "3D-ACA pool could not hold the result");
   GCQ_HIP(hipMemcpy(terms.data(), d_terms, sizeof(Term3) * terms.size(), hipMemcpyDeviceToHost));
   ctx->kernel_ms["aca3d"] = ms;
+  ctx->kernel_ms["aca3d_far"] = ms_far;
+  ctx->kernel_ms["aca3d_near"] = ms_near;
+  ctx->kernel_ms["aca3d_tensor"] = ms_tensor;
+  ctx->kernel_ms["aca3d_rounds"] = rounds;
   // host tables
   F.brank.assign(blkrank.begin(), blkrank.end());
   F.bterm.assign(nb, 0);

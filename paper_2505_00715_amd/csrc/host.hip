@@ -6,6 +6,7 @@
 #include <numeric>
 
 #include "internal.h"
+#include "near.h"
 
 namespace gcq {
 
@@ -491,6 +492,35 @@ GCQ_API int gcq_build_cluster_tree(gcq_context* ctx, int32_t leaf_size, double e
   GCQ_TRY(upload(ctx->d_perm, perm32, st));
   GCQ_TRY(upload(ctx->d_iperm, iperm32, st));
   GCQ_TRY(upload(ctx->d_blk, blk, st));
+  // near field offsets and the self/near-tier entries of the inadmissible blocks
+  {
+    ctx->near_off.assign(ctx->near_ids.size(), 0);
+    std::vector<SingEntry> sing;
+    int64_t acc = 0;
+    for (size_t q = 0; q < ctx->near_ids.size(); ++q) {
+      const Block& B = ctx->blocks[ctx->near_ids[q]];
+      const Cluster& A = ctx->clusters[B.row];
+      const Cluster& C = ctx->clusters[B.col];
+      const int m = A.end - A.begin, nn = C.end - C.begin;
+      ctx->near_off[q] = acc;
+      for (int c = 0; c < nn; ++c)
+        for (int r = 0; r < m; ++r) {
+          const int pi = A.begin + r, pj = C.begin + c;
+          const int ti = ctx->perm[pi], tj = ctx->perm[pj];
+          double dx = cen[3 * ti] - cen[3 * tj], dy = cen[3 * ti + 1] - cen[3 * tj + 1],
+                 dz = cen[3 * ti + 2] - cen[3 * tj + 2];
+          double d2 = dx * dx + dy * dy + dz * dz;
+          if (pi == pj || d2 < 4.0 * ctx->h2[tj]) sing.push_back(SingEntry{acc + int64_t(c) * m + r, pi, pj});
+        }
+      acc += int64_t(m) * nn;
+    }
+    ctx->near_total = acc;
+    ctx->n_sing = int64_t(sing.size());
+    std::vector<int32_t> nid(ctx->near_ids.begin(), ctx->near_ids.end());
+    GCQ_TRY(upload(ctx->d_near_off, ctx->near_off, st));
+    GCQ_TRY(upload(ctx->d_near_ids, nid, st));
+    GCQ_TRY(upload(ctx->d_sing, sing, st));
+  }
   GCQ_HIP(hipStreamSynchronize(st));
   ctx->have_tree = true;
   return GCQ_OK;

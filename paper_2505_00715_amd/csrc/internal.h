@@ -168,6 +168,13 @@ struct gcq_context {
   std::vector<int> far_ids, near_ids;       // block ids
   int depth = 0;
 
+  // near field: element offsets of the inadmissible blocks (column-major
+  // storage of one frequency) and the list of their self/near-tier entries
+  std::vector<int64_t> near_off;
+  int64_t near_total = 0;
+  int64_t n_sing = 0;
+  gcq::DevBuf d_near_off, d_near_ids, d_sing;
+
   // device tables (permuted order)
   gcq::DevBuf d_cen, d_h2, d_vert, d_area, d_q64, d_c32, d_q32, d_consts, d_perm, d_iperm;
   gcq::DevBuf d_blk;                         // per block: rb, re, cb, ce, flags (int32 x 5)
