@@ -20,7 +20,9 @@ Readings of points Alg. 1 leaves open:
     term that met the test is dropped, as the algorithm's final line says;
   * a zero pivot (the residual slice vanishes) stops with rank l - 1;
   * the next frequency is chosen among unused ones (the literal argmax could
-    pick k_l again, where |f_l| = 1);
+    pick k_l again, where |f_l| = 1); when the fiber vanishes at every unused
+    frequency, the argmax is undefined and the approximation stops with the
+    current terms (the residual fiber through the last pivot is zero there);
   * when every frequency is used, or l reaches r_max, stop keeping term l.
 """
 from __future__ import annotations
@@ -133,6 +135,8 @@ def aca3d_block(entry_fn, m: int, n: int, nK: int, admissible: bool, tol_aca: fl
             break
         af = np.abs(fib)
         af[used] = -1.0
+        if af.max() <= 0.0:
+            break
         k_cur = int(np.argmax(af))
     B.norm2 = norm2
     return B
