@@ -327,9 +327,9 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
         if (v > bf) { bf = v; bk = kk; }
       }
       wave_argmax(bf, bk);
-      // every frequency used, or the fiber vanishes at all unused ones
-      if (bk == 0x7fffffff || !(bf > 0.0)) break;           // every frequency used
+      if (bk == 0x7fffffff) break;                       // every frequency used
       if (ell >= rmax) { status |= ST_CAPPED; break; }
+      if (!(bf > 0.0)) break;                            // fiber zero at all unused ones
       kcur = bk;
     }
     __syncthreads();
