@@ -130,6 +130,110 @@ __device__ inline cpx<T> slice_at(const Term3& t, const cpx<T>* pool, int m, int
   return acc;
 }
 
+
+// Pivot of a factored slice H = Ubar Vbar^H (m x n, rank t): largest |H[i, j]|,
+// first in row-major order on ties.  Each lane expands 4 x 4 tiles of the
+// product (the dense block is never stored).
+template <typename T>
+__device__ inline void lowrank_argmax(const cpx<T>* __restrict__ U, const cpx<T>* __restrict__ V,
+                                      int m, int n, int t, double& best, int& be) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int ti = (m + 3) >> 2, tj = (n + 3) >> 2;
+  best = -1.0;
+  be = 0x7fffffff;
+  for (int tile = lane; tile < ti * tj; tile += WAVE) {
+    const int i0 = (tile / tj) * 4, j0 = (tile % tj) * 4;
+    cpx<T> acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = {T(0), T(0)};
+    for (int c = 0; c < t; ++c) {
+      cpx<T> u[4], v[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        u[x] = i0 + x < m ? U[int64_t(c) * m + i0 + x] : cpx<T>{T(0), T(0)};
+        v[x] = j0 + x < n ? V[int64_t(c) * n + j0 + x] : cpx<T>{T(0), T(0)};
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {   // u conj(v)
+          acc[x][y].re += u[x].re * v[y].re + u[x].im * v[y].im;
+          acc[x][y].im += u[x].im * v[y].re - u[x].re * v[y].im;
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        if (i0 + x < m && j0 + y < n) {
+          const double val = mag2(acc[x][y]);
+          const int e = (i0 + x) * n + j0 + y;
+          if (val > best || (val == best && e < be)) { best = val; be = e; }
+        }
+      }
+  }
+  wave_argmax(best, be);
+}
+
+// <H_d, H_l>_F = sum_{a,b} (U_l^H U_d)[a][b] (V_d^H V_l)[b][a] for factored
+// slices; lanes own (a, b) pairs, rows are staged through LDS R at a time.
+// stage: LDS scratch of 16 KB (2 * 64 * R elements).
+template <typename T>
+__device__ inline cpx<double> lowrank_inner(const cpx<T>* __restrict__ Ul, const cpx<T>* __restrict__ Vl,
+                                            int tl, const cpx<T>* __restrict__ Ud,
+                                            const cpx<T>* __restrict__ Vd, int td, int m, int n,
+                                            cpx<T>* stage) {
+  constexpr int R = int(128 / sizeof(cpx<T>));   // 16 (float) or 8 (double)
+  const int lane = threadIdx.x & (WAVE - 1);
+  cpx<T>* sl = stage;           // [a][r]
+  cpx<T>* sd = stage + 64 * R;  // [b][r]
+  double re = 0.0, im = 0.0;
+  for (int p0 = 0; p0 < tl * td; p0 += WAVE) {
+    const int p = p0 + lane;
+    const bool act = p < tl * td;
+    const int a = act ? p / td : 0, b = act ? p % td : 0;
+    double pr = 0, pi = 0, qr = 0, qi = 0;
+    for (int side = 0; side < 2; ++side) {
+      const int len = side == 0 ? m : n;
+      const cpx<T>* X = side == 0 ? Ul : Vd;   // conjugated operand
+      const cpx<T>* Y = side == 0 ? Ud : Vl;
+      const int tx = side == 0 ? tl : td, ty = side == 0 ? td : tl;
+      const int ax = side == 0 ? a : b, ay = side == 0 ? b : a;
+      double sr = 0, si = 0;
+      for (int r0 = 0; r0 < len; r0 += R) {
+        const int rn = min(R, len - r0);
+        __syncthreads();
+        for (int e = lane; e < tx * R; e += WAVE) {
+          const int c = e / R, r = e % R;
+          sl[e] = r < rn ? X[int64_t(c) * len + r0 + r] : cpx<T>{T(0), T(0)};
+        }
+        for (int e = lane; e < ty * R; e += WAVE) {
+          const int c = e / R, r = e % R;
+          sd[e] = r < rn ? Y[int64_t(c) * len + r0 + r] : cpx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll 4
+          for (int r = 0; r < R; ++r) {
+            const cpx<T> x = sl[ax * R + r], y = sd[ay * R + r];
+            sr += double(x.re) * y.re + double(x.im) * y.im;   // conj(x) y
+            si += double(x.re) * y.im - double(x.im) * y.re;
+          }
+        }
+      }
+      if (side == 0) { pr = sr; pi = si; } else { qr = sr; qi = si; }
+    }
+    if (act) {
+      re += pr * qr - pi * qi;
+      im += pr * qi + pi * qr;
+    }
+  }
+  __syncthreads();
+  return {wave_sum(re), wave_sum(im)};
+}
+
 // ALLFAR = true: admissible blocks without self/near-tier entries (the float64
 // quadrature tiers are not compiled in); ALLFAR = false: every other block.
 template <typename T, bool ALLFAR>
@@ -209,13 +313,17 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
       double best = -1.0;
       int be = 0x7fffffff;
       const int mn = m * n;
-      for (int e = lane; e < mn; e += WAVE) {
-        const int i = e / n, j = e % n;  // row-major key
-        cpx<T> h = slice_at<T>(cur, pool, m, n, i, j);
-        double v = mag2(h);
-        if (v > best) { best = v; be = e; }
+      if (srank >= 0) {
+        lowrank_argmax<T>(pool + soff, pool + soff + int64_t(srank) * m, m, n, srank, best, be);
+      } else {
+        for (int e = lane; e < mn; e += WAVE) {
+          const int i = e / n, j = e % n;  // row-major key
+          cpx<T> h = slice_at<T>(cur, pool, m, n, i, j);
+          double v = mag2(h);
+          if (v > best) { best = v; be = e; }
+        }
+        wave_argmax(best, be);
       }
-      wave_argmax(best, be);
       if (!(best > PivFloor<T>::v)) break;   // zero pivot: rank stays ell
       const int ip = be / n, jp = be % n;
       const cpx<T> piv = slice_at<T>(cur, pool, m, n, ip, jp);
@@ -267,34 +375,16 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
         const int tl = srank;
         const cpx<T>* Ul = pool + soff;
         const cpx<T>* Vl = Ul + int64_t(tl) * m;
+        cpx<T>* stage = reinterpret_cast<cpx<T>*>(sh.mats);
         for (int d = 0; d <= ell; ++d) {
           const Term3 td = d < ell ? sh.term[d] : cur;
-          const int tdr = td.rank;
           const cpx<T>* Ud = pool + td.slice;
-          const cpx<T>* Vd = Ud + int64_t(tdr) * m;
-          double re = 0, im = 0;
-          for (int ab = lane; ab < tl * tdr; ab += WAVE) {
-            const int a = ab / tdr, bb = ab % tdr;
-            double ar = 0, ai = 0, br = 0, bi = 0;
-            for (int i = 0; i < m; ++i) {  // (U_l^H U_d)[a][bb]
-              cpx<T> x = Ul[int64_t(a) * m + i], y = Ud[int64_t(bb) * m + i];
-              ar += double(x.re) * y.re + double(x.im) * y.im;
-              ai += double(x.re) * y.im - double(x.im) * y.re;
-            }
-            for (int j = 0; j < n; ++j) {  // (V_d^H V_l)[bb][a]
-              cpx<T> x = Vd[int64_t(bb) * n + j], y = Vl[int64_t(a) * n + j];
-              br += double(x.re) * y.re + double(x.im) * y.im;
-              bi += double(x.re) * y.im - double(x.im) * y.re;
-            }
-            re += ar * br - ai * bi;
-            im += ar * bi + ai * br;
-          }
-          re = wave_sum(re);
-          im = wave_sum(im);
+          const cpx<T>* Vd = Ud + int64_t(td.rank) * m;
+          const cpx<double> h = lowrank_inner<T>(Ul, Vl, tl, Ud, Vd, td.rank, m, n, stage);
           if (d < ell) {
-            if (lane == 0) sh.hin[d] = {re, im};
+            if (lane == 0) sh.hin[d] = h;
           } else {
-            nh2 = re;
+            nh2 = h.re;
           }
         }
       }
