@@ -15,23 +15,29 @@ pivoting, as in the cited work):
                u_k = A[:, j] - sum_l w_l[j] u_l            (column residual)
                |S_k|^2 = |S_{k-1}|^2 + 2 Re sum_{l<k} (u_l^H u_k)(w_l^H w_k)
                          + |u_k|^2 |w_k|^2
-               stop (keeping term k) if |u_k| |w_k| <= eps |S_k|
+               stop (keeping term k) if |u_k| |w_k| <= eps max(|S_k|, nu)
                next i = argmax over unused rows of |u_k[i]| (lowest on ties)
   cap          at most min(m, n, max_rank) terms; hitting max_rank first is
                reported as capped.
 
 Recompression: U = Q_U R_U, V = Q_V R_V, R_U R_V^H = Uc S Vc^H (SVD); keep the
-smallest t with sqrt(sum_{i>t} s_i^2) <= eps sqrt(sum_i s_i^2);
+smallest t with sqrt(sum_{i>t} s_i^2) <= eps max(sqrt(sum_i s_i^2), nu);
 Ubar = Q_U Uc_t S_t, Vbar = Q_V Vc_t, so that U V^H ~ Ubar Vbar^H.
+
+nu is an absolute norm floor, 0 for an ordinary block: both tests are then
+relative to the block itself.  The 3D-ACA passes the norm of its current
+approximation at the slice's frequency when it compresses a residual slice
+(see aca3d).
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def aca(row_fn, col_fn, m: int, n: int, tol: float, max_rank: int):
+def aca(row_fn, col_fn, m: int, n: int, tol: float, max_rank: int, nu: float = 0.0):
     """row_fn(i) -> A[i, :] (n,), col_fn(j) -> A[:, j] (m,).
     Returns (U (m, k), V (n, k), info dict)."""
+    nu_floor = nu
     us, ws = [], []
     used = np.zeros(m, dtype=bool)
     norm2 = 0.0
@@ -62,11 +68,11 @@ def aca(row_fn, col_fn, m: int, n: int, tol: float, max_rank: int):
         cross = 0.0
         for ul, wl in zip(us, ws):
             cross += (np.vdot(ul, u) * np.vdot(wl, w)).real
-        nu, nw = np.linalg.norm(u), np.linalg.norm(w)
-        norm2 = norm2 + 2.0 * cross + (nu * nw) ** 2
+        n_u, n_w = np.linalg.norm(u), np.linalg.norm(w)
+        norm2 = norm2 + 2.0 * cross + (n_u * n_w) ** 2
         us.append(u)
         ws.append(w)
-        if nu * nw <= tol * np.sqrt(max(norm2, 0.0)):
+        if n_u * n_w <= tol * max(np.sqrt(max(norm2, 0.0)), nu_floor):
             break
         au = np.abs(u)
         au[used] = -1.0
@@ -79,7 +85,7 @@ def aca(row_fn, col_fn, m: int, n: int, tol: float, max_rank: int):
     return U, V, dict(rank=k, capped=capped, norm2=norm2, rows=rows_evaluated)
 
 
-def recompress(U, V, tol: float):
+def recompress(U, V, tol: float, nu: float = 0.0):
     """QR + SVD recompression; returns (Ubar, Vbar, sigma_kept, sigma_all)."""
     m, k = U.shape
     n = V.shape[0]
@@ -89,7 +95,7 @@ def recompress(U, V, tol: float):
     QV, RV = np.linalg.qr(V, mode="reduced")
     Uc, S, Vch = np.linalg.svd(RU @ RV.conj().T)
     tail = np.sqrt(np.concatenate([np.cumsum((S ** 2)[::-1])[::-1], [0.0]]))  # tail[t] = sqrt(sum_{i>=t} s_i^2)
-    total = tail[0]
+    total = max(tail[0], nu)
     t = int(np.nonzero(tail <= tol * total)[0][0])
     Ub = QU @ (Uc[:, :t] * S[:t][None, :])
     Vb = QV @ Vch.conj().T[:, :t]

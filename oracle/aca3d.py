@@ -6,7 +6,10 @@ frequencies K is approximated by sum_l H_l[i, j] f_l[k].  Term l:
 
   H_l  = V(s_{k_l})[I, J] - sum_{d<l} f_d[k_l] H_d   (residual slice)
          near block: dense; far block: ACA of the residual entry function,
-         then QR/SVD recompression (kept as Ubar Vbar^H)
+         then QR/SVD recompression (kept as Ubar Vbar^H), both with the
+         slice tolerance measured against max(|H_l|, nu_l), where
+         nu_l = |sum_{d<l} f_d[k_l] H_d|_F is the current approximation of
+         the block at k_l
   (i_l, j_l) = argmax |H_l|   (row-major first on ties; for a far block the
          slice is expanded densely from its factors, as the paper does)
   f_l[k] = (V(s_k)[i_l, j_l] - sum_{d<l} H_d[i_l, j_l] f_d[k]) / H_l[i_l, j_l]
@@ -23,7 +26,12 @@ Readings of points Alg. 1 leaves open:
     pick k_l again, where |f_l| = 1); when the fiber vanishes at every unused
     frequency, the argmax is undefined and the approximation stops with the
     current terms (the residual fiber through the last pivot is zero there);
-  * when every frequency is used, or l reaches r_max, stop keeping term l.
+  * when every frequency is used, or l reaches r_max, stop keeping term l;
+  * the slice tolerance eps_ACA of a residual slice is taken relative to the
+    block at that frequency, estimated by nu_l, not relative to the residual
+    alone: the residual only has to be resolved to the accuracy the face
+    itself is held to (a residual made of the earlier slices' own
+    approximation errors has no low-rank structure to find below that level).
 """
 from __future__ import annotations
 
@@ -84,6 +92,11 @@ def aca3d_block(entry_fn, m: int, n: int, nK: int, admissible: bool, tol_aca: fl
         ell = len(B.slices)
         fk = [f[k_cur] for f in B.fibers]
         if admissible:
+            approx = np.zeros((m, n), dtype=np.complex128)
+            for d in range(ell):
+                approx += fk[d] * Hd[d]
+            nu = float(np.linalg.norm(approx))
+
             def row_fn(i):
                 r = entry_fn(np.array([i]), allc, [k_cur])[0, 0, :]
                 for d in range(ell):
@@ -98,8 +111,8 @@ def aca3d_block(entry_fn, m: int, n: int, nK: int, admissible: bool, tol_aca: fl
                     col = col - fk[d] * (U @ V[j, :].conj())
                 return col
 
-            U, V, info = aca_mod.aca(row_fn, col_fn, m, n, tol_aca, aca_max_rank)
-            Ub, Vb, _, _ = aca_mod.recompress(U, V, tol_aca)
+            U, V, info = aca_mod.aca(row_fn, col_fn, m, n, tol_aca, aca_max_rank, nu=nu)
+            Ub, Vb, _, _ = aca_mod.recompress(U, V, tol_aca, nu=nu)
             H = Ub @ Vb.conj().T
             slice_store = (Ub, Vb)
         else:

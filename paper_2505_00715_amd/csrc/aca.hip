@@ -49,8 +49,8 @@ __global__ void __launch_bounds__(64) aca_kernel(Tab tab, const PairDesc* __rest
     cpx<double>* GU = reinterpret_cast<cpx<double>*>(ws + d.ws + ws_gram_off<T>(d.cap, d.m, d.n));
     PlainEntry<T, ALLFAR> ent{&tab, d.rb, d.cb, d.sr, d.si, d.all_far != 0};
     int status = 0;
-    const int k = aca_wave<T>(ent, d.m, d.n, d.cap, max_rank, tol, U, W, GU, GU + d.cap * d.cap,
-                              sm, status);
+    const int k = aca_wave<T>(ent, d.m, d.n, d.cap, max_rank, tol, 0.0, U, W, GU,
+                              GU + d.cap * d.cap, sm, status);
     if (lane == 0) {
       out_rank[pid] = k;
       out_status[pid] = status;
@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(64) recompress_kernel(const PairDesc* __restri
     cpx<double>* GU = reinterpret_cast<cpx<double>*>(ws + d.ws + ws_gram_off<T>(cap, d.m, d.n));
     cpx<double>* A = k <= 16 ? mats
                              : reinterpret_cast<cpx<double>*>(jws) + int64_t(blockIdx.x) * 4 * 64 * 64;
-    const int t = recompress_wave(k, cap, GU, GU + cap * cap, tol, do_recompress != 0, A, rs);
+    const int t = recompress_wave(k, cap, GU, GU + cap * cap, tol, 0.0, do_recompress != 0, A, rs);
     if (threadIdx.x == 0) out_t[pid] = t;
   }
 }

@@ -262,6 +262,8 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
     cpx<double>* GV = GU + cap * cap;
     cpx<double>* jmats = reinterpret_cast<cpx<double>*>(myws + ws_bytes<T>(cap, m, n));
     cpx<T>* coef = reinterpret_cast<cpx<T>*>(jmats + 4 * 64 * 64);
+    // Gram matrix <H_d, H_d'> of the accepted slices (R3_MAX x R3_MAX)
+    cpx<double>* G3 = reinterpret_cast<cpx<double>*>(coef + R3_MAX * 64);
     for (int w = lane; w < (nK + 31) / 32; w += WAVE) sh.usedk[w] = 0u;
     __syncthreads();
     int ell = 0, kcur = 0, status = 0;
@@ -291,11 +293,24 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
       } else {
         ResidualEntry<T, ALLFAR> ent{&tab, B.rb, B.cb, m, n, sg.x, sg.y, B.all_far != 0, ell, &sh,
                                      pool, coef, true};
+        // nu = |sum_d f_d[k] H_d|_F, the current approximation of the block at
+        // k: the slice tolerance is taken relative to max(|residual|, nu)
+        double nu2 = 0.0;
+        for (int e = lane; e < ell * ell; e += WAVE) {
+          const int d = e / ell, d2 = e % ell;
+          const cpx<T> a = sh.fk[d], b = sh.fk[d2];
+          const cpx<double> g = G3[d * R3_MAX + d2];
+          // a conj(b) <H_d, H_d2>
+          const double pr = double(a.re) * b.re + double(a.im) * b.im;
+          const double pi = double(a.im) * b.re - double(a.re) * b.im;
+          nu2 += pr * g.re - pi * g.im;
+        }
+        const double nu = sqrt(fmax(wave_sum(nu2), 0.0));
         int ast = 0;
-        const int k = aca_wave<T>(ent, m, n, cap, aca_cap, tol_aca, U, W, GU, GV, sh.aca, ast);
+        const int k = aca_wave<T>(ent, m, n, cap, aca_cap, tol_aca, nu, U, W, GU, GV, sh.aca, ast);
         if (ast & ST_CAPPED) status |= ST_CAPPED;
         cpx<double>* A = k <= 16 ? sh.mats : jmats;
-        const int t = recompress_wave(k, cap, GU, GV, tol_aca, true, A, sh.rs);
+        const int t = recompress_wave(k, cap, GU, GV, tol_aca, nu, true, A, sh.rs);
         if (lane == 0) sh.alloc = pool_alloc(cursor, int64_t(t) * (m + n), capacity);
         __syncthreads();
         soff = sh.alloc;
@@ -406,6 +421,12 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
       __syncthreads();
       if (sqrt(fmax(nh2 * nf2, 0.0)) <= tol * sqrt(fmax(norm2, 0.0))) break;  // drop term l
       if (lane == 0) sh.term[ell] = cur;
+      for (int d = lane; d <= ell; d += WAVE) {
+        // <H_d, H_l> (d < l) and |H_l|^2
+        const cpx<double> h = d < ell ? sh.hin[d] : cpx<double>{nh2, 0.0};
+        G3[d * R3_MAX + ell] = h;
+        G3[ell * R3_MAX + d] = {h.re, -h.im};
+      }
       __syncthreads();
       ++ell;
       // next frequency: largest |f_l[k]| among unused k (lowest k on ties)
@@ -643,7 +664,8 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   const int64_t csz = csize(precision);
   const int64_t ws_stride =
       ((precision == GCQ_C128 ? ws_bytes<double>(aca_cap, maxmn, 0) : ws_bytes<float>(aca_cap, maxmn, 0)) +
-       int64_t(4) * 64 * 64 * 16 + int64_t(R3_MAX) * 64 * csz + 4095) & ~int64_t(4095);
+       int64_t(4) * 64 * 64 * 16 + int64_t(R3_MAX) * 64 * csz + int64_t(R3_MAX) * R3_MAX * 16 +
+       4095) & ~int64_t(4095);
   int cus = 256;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;

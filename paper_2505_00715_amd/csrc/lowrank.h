@@ -66,8 +66,9 @@ struct RecompShared {
 // Vectors in T, norms and inner products in double; the inner products are
 // the Gram matrices GU = U^H U and GV = V^H V (V = conj(W)), stored for the
 // recompression.  Returns the rank; `status` receives ST_* bits.
+// nu: absolute norm floor of the stopping test (0: relative to the block itself)
 template <typename T, typename Ent>
-__device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double tol,
+__device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double tol, double nu,
                         cpx<T>* __restrict__ U, cpx<T>* __restrict__ W,
                         cpx<double>* __restrict__ GU, cpx<double>* __restrict__ GV,
                         AcaShared<T>& sm, int& status) {
@@ -177,7 +178,10 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
     }
     norm2 += 2.0 * cross + nu2 * nw2;
     ++k;
-    if (sqrt(nu2 * nw2) <= tol * sqrt(fmax(norm2, 0.0))) { status |= ST_CONVERGED; break; }
+    if (sqrt(nu2 * nw2) <= tol * fmax(sqrt(fmax(norm2, 0.0)), nu)) {
+      status |= ST_CONVERGED;
+      break;
+    }
     wave_argmax(bestu, bi);
     if (nused >= m || bi == 0x7fffffff) { status |= ST_EXACT; break; }
     i = bi;
@@ -298,11 +302,12 @@ __device__ inline void jacobi_herm(cpx<double>* A, cpx<double>* Q, int k, Recomp
 // ---- recompression of k ACA terms ------------------------------------------------
 // GU, GV: Gram matrices (leading dimension cap).  mats: 4 k^2 doubles-complex of
 // working memory (LDS or global).  Keeps the smallest t with
-// sqrt(sum_{i >= t} s_i^2) <= tol sqrt(sum s_i^2) and writes the coefficients
+// sqrt(sum_{i >= t} s_i^2) <= tol max(sqrt(sum s_i^2), nu) and writes the coefficients
 // CU = Q L^{1/2} Z_t and CV = Q L^{-1/2} Z_t (k x t, leading dimension t) over GU
 // and GV.  Without recompression CU = CV = I, t = k.  Returns t.
 __device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol,
-                                      bool do_recompress, cpx<double>* mats, RecompShared& rs) {
+                                      double nu, bool do_recompress, cpx<double>* mats,
+                                      RecompShared& rs) {
   const int lane = threadIdx.x & (WAVE - 1);
   if (k == 0 || !do_recompress) {
     __syncthreads();
@@ -386,9 +391,10 @@ __device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<doubl
     for (int a = 0; a < kk; ++a) total += rs.sg[a];
     double tail = 0.0;
     int t = kk;
+    const double ref = fmax(sqrt(total), nu);
     for (int a = kk - 1; a >= 0; --a) {
       tail += rs.sg[rs.order[a]];
-      if (sqrt(tail) <= tol * sqrt(total)) t = a;
+      if (sqrt(tail) <= tol * ref) t = a;
       else break;
     }
     rs.tcut = t;
