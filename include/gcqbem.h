@@ -93,6 +93,17 @@ enum {
   GCQ_FLAG_PER_FREQ_LAUNCH = 4u  /* one launch per frequency, no batching (baseline)  */
 };
 
+/* Launch configuration (gcq_set_tuning / gcq_get_tuning).
+ *   aca3d_waves[c]: wave64s that work together on one admissible block in
+ *     gcq_aca3d, for blocks with |I| + |J| <= 160, <= 320, <= 640 and > 640
+ *     (c = 0..3); each 1, 2, 4 or 8.  Default {1, 2, 4, 8}.  Blocks whose
+ *     accepted slices outgrow the group's on-chip storage are redone with
+ *     twice the waves; results do not depend on the setting beyond rounding
+ *     order. */
+typedef struct {
+  int32_t aca3d_waves[4];
+} gcq_tuning;
+
 typedef struct {
   int32_t n_clusters;
   int32_t n_leaves;
@@ -159,6 +170,12 @@ GCQ_API const char* gcq_last_error(void);
  * ("aca", "recompress", "aca3d", "matvec", ...) as measured with HIP events,
  * or -1 if none. */
 GCQ_API double gcq_kernel_ms(gcq_context* ctx, const char* name);
+
+/* gcq_set_tuning / gcq_get_tuning: replace / read the launch configuration
+ *   of the context (host struct, copied).  GCQ_ERR_ARG on values out of range;
+ *   the configuration is then unchanged. */
+GCQ_API int gcq_set_tuning(gcq_context* ctx, const gcq_tuning* tuning);
+GCQ_API int gcq_get_tuning(gcq_context* ctx, gcq_tuning* tuning);
 
 /* ---- geometry and frequencies (Sec. 3; Sec. 2) ------------------------------
  * gcq_upload_mesh: host xyz (n_vertices x 3 doubles, row-major) and tri

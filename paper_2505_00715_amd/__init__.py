@@ -49,6 +49,10 @@ class SolveStats(C.Structure):
                 ("resid_max", C.c_double), ("device_ms", C.c_double)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("aca3d_waves", C.c_int32 * 4)]
+
+
 class TrainCfg(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
@@ -78,6 +82,8 @@ def _load():
         "gcq_create": [C.c_int, P, C.POINTER(P)],
         "gcq_destroy": [P],
         "gcq_kernel_ms": [P, C.c_char_p],
+        "gcq_set_tuning": [P, P],
+        "gcq_get_tuning": [P, P],
         "gcq_upload_mesh": [P, P, I64, P, I64, D],
         "gcq_set_frequencies": [P, P, I32, I32],
         "gcq_build_cluster_tree": [P, I32, D, P],
@@ -167,6 +173,19 @@ class Context:
 
     def kernel_ms(self, name: str) -> float:
         return _lib.gcq_kernel_ms(self._h, name.encode())
+
+    def set_tuning(self, aca3d_waves=None):
+        """aca3d_waves: 4 group sizes (waves per block) of the 3D-ACA size classes."""
+        t = self.get_tuning()
+        if aca3d_waves is not None:
+            for c, w in enumerate(aca3d_waves):
+                t.aca3d_waves[c] = int(w)
+        _check(_lib.gcq_set_tuning(self._h, C.byref(t)))
+
+    def get_tuning(self) -> Tuning:
+        t = Tuning()
+        _check(_lib.gcq_get_tuning(self._h, C.byref(t)))
+        return t
 
     # ---- geometry, frequencies, tree
     def upload_mesh(self, xyz, tri, wave_speed: float):

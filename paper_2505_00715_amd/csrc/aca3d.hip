@@ -27,18 +27,45 @@ struct Term3 {
   int freq;        // position in K of the frequency the slice was taken at
 };
 
-template <typename T>
+// LDS capacities of the far kernel per group size NW (waves per block):
+// RES residual coefficients (sum of the accepted slices' ranks; a block whose
+// slices need more is handed to the next larger group), JK the largest ACA
+// rank whose recompression runs in LDS (larger ones use the global workspace).
+template <int NW>
+struct Cls;
+template <>
+struct Cls<1> {
+  static constexpr int RES = 512, JK = 16;
+};
+template <>
+struct Cls<2> {
+  static constexpr int RES = 1024, JK = 16;
+};
+template <>
+struct Cls<4> {
+  static constexpr int RES = 2048, JK = 24;
+};
+template <>
+struct Cls<8> {
+  static constexpr int RES = R3_MAX * 64, JK = 32;   // every possible stack
+};
+
+enum : int { ST_ESCALATE = 32 };   // residual stack exceeds the group's LDS capacity
+
+template <typename T, int NW>
 struct Shared3 {
+  cpx<T> coef[Cls<NW>::RES];   // residual coefficients of the current row / column
   AcaShared<T> aca;
   RecompShared rs;
-  cpx<double> mats[4 * 16 * 16];
+  cpx<double> mats[4 * Cls<NW>::JK * Cls<NW>::JK];
   Term3 term[R3_MAX];
-  cpx<T> fk[R3_MAX];          // f_d[k_cur]
-  cpx<T> hp[R3_MAX];          // H_d[i_l, j_l]
-  cpx<double> hin[R3_MAX];    // <H_d, H_l>
+  int tbase[R3_MAX];           // first coefficient of each slice
+  cpx<T> fk[R3_MAX];           // f_d[k_cur]
+  cpx<T> hp[R3_MAX];           // H_d[i_l, j_l]
+  cpx<double> hin[R3_MAX];     // <H_d, H_l>
   unsigned usedk[NK_MAX / 32];
   int64_t alloc;
-  int flag;
+  int idx;
 };
 
 // pool allocation by one lane; returns -1 when the pool is exhausted
@@ -50,74 +77,76 @@ __device__ inline int64_t pool_alloc(unsigned long long* cursor, int64_t cnt, in
 
 // residual entry function of a far block at one frequency:
 //   R(i, j) = A_ij(s) - sum_d f_d[k] (Ubar_d Vbar_d^H)[i, j]
-template <typename T, bool ALLFAR>
+// A row (column) evaluation first forms the coefficients f_d[k] Ubar_d[i][c]
+// (f_d[k] conj(Vbar_d[j][c])) of all slices in LDS; each thread then subtracts
+// sum_{d,c} coef conj(Vbar_d[j][c]) (sum_{d,c} Ubar_d[i][c] coef) from its entry.
+template <typename T, bool ALLFAR, int NW>
 struct ResidualEntry {
   const Tab* tab;
   int rb, cb, m, n;
   double sr, si;
   bool all_far;
   int nterm;
-  Shared3<T>* sh;
+  Shared3<T, NW>* sh;
   const cpx<T>* pool;
-  cpx<T>* coef;   // per-wave scratch: sum_d rank_d coefficients
   bool rowmode;
   __device__ void prep_row(int i) {
-    // coef[d][c] = f_d[k] Ubar_d[i][c]
-    const int lane = threadIdx.x & (WAVE - 1);
-    int base = 0;
     for (int d = 0; d < nterm; ++d) {
       const Term3 t = sh->term[d];
       const cpx<T>* Ud = pool + t.slice;
-      for (int c = lane; c < t.rank; c += WAVE) coef[base + c] = cmul(sh->fk[d], Ud[int64_t(c) * m + i]);
-      base += t.rank;
+      const cpx<T> f = sh->fk[d];
+      for (int c = threadIdx.x; c < t.rank; c += NW * WAVE)
+        sh->coef[sh->tbase[d] + c] = cmul(f, Ud[int64_t(c) * m + i]);
     }
     rowmode = true;
     __syncthreads();
   }
   __device__ void prep_col(int j) {
-    // coef[d][c] = f_d[k] conj(Vbar_d[j][c])
-    const int lane = threadIdx.x & (WAVE - 1);
-    int base = 0;
     for (int d = 0; d < nterm; ++d) {
       const Term3 t = sh->term[d];
       const cpx<T>* Vd = pool + t.slice + int64_t(t.rank) * m;
-      for (int c = lane; c < t.rank; c += WAVE) {
-        cpx<T> v = Vd[int64_t(c) * n + j];
-        coef[base + c] = cmul(sh->fk[d], cpx<T>{v.re, -v.im});
+      const cpx<T> f = sh->fk[d];
+      for (int c = threadIdx.x; c < t.rank; c += NW * WAVE) {
+        const cpx<T> v = Vd[int64_t(c) * n + j];
+        sh->coef[sh->tbase[d] + c] = cmul(f, cpx<T>{v.re, -v.im});
       }
-      base += t.rank;
     }
     rowmode = false;
     __syncthreads();
   }
   __device__ cpx<T> operator()(int i, int j) const {
     cpx<T> a = entry<T, ALLFAR>(*tab, rb + i, cb + j, sr, si, all_far);
-    int base = 0;
+    T ar = 0, ai = 0;
     for (int d = 0; d < nterm; ++d) {
       const Term3 t = sh->term[d];
-      const cpx<T>* Ud = pool + t.slice;
-      const cpx<T>* Vd = Ud + int64_t(t.rank) * m;
-      for (int c = 0; c < t.rank; ++c) {
-        cpx<T> p;
-        if (rowmode) {
-          cpx<T> v = Vd[int64_t(c) * n + j];
-          p = cmul(coef[base + c], cpx<T>{v.re, -v.im});
-        } else {
-          p = cmul(Ud[int64_t(c) * m + i], coef[base + c]);
+      const cpx<T>* q = sh->coef + sh->tbase[d];
+      if (rowmode) {
+        const cpx<T>* Vd = pool + t.slice + int64_t(t.rank) * m + j;
+#pragma unroll 4
+        for (int c = 0; c < t.rank; ++c) {
+          const cpx<T> v = Vd[int64_t(c) * n], x = q[c];
+          ar += x.re * v.re + x.im * v.im;   // x conj(v)
+          ai += x.im * v.re - x.re * v.im;
         }
-        a.re -= p.re;
-        a.im -= p.im;
+      } else {
+        const cpx<T>* Ud = pool + t.slice + i;
+#pragma unroll 4
+        for (int c = 0; c < t.rank; ++c) {
+          const cpx<T> u = Ud[int64_t(c) * m], x = q[c];
+          ar += u.re * x.re - u.im * x.im;
+          ai += u.re * x.im + u.im * x.re;
+        }
       }
-      base += t.rank;
     }
+    a.re -= ar;
+    a.im -= ai;
     return a;
   }
 };
 
-// entry of slice d at (i, j): dense or sum_c Ubar[i][c] conj(Vbar[j][c]) (one lane)
+// entry (i, j) of a factored slice, sum_c Ubar[i][c] conj(Vbar[j][c]) (one thread)
 template <typename T>
 __device__ inline cpx<T> slice_at(const Term3& t, const cpx<T>* pool, int m, int n, int i, int j) {
-  if (t.rank < 0) return pool[t.slice + int64_t(j) * m + i];
   const cpx<T>* U = pool + t.slice;
   const cpx<T>* V = U + int64_t(t.rank) * m;
   cpx<T> acc = {T(0), T(0)};
@@ -130,18 +159,16 @@ __device__ inline cpx<T> slice_at(const Term3& t, const cpx<T>* pool, int m, int
   return acc;
 }
 
-
 // Pivot of a factored slice H = Ubar Vbar^H (m x n, rank t): largest |H[i, j]|,
-// first in row-major order on ties.  Each lane expands 4 x 4 tiles of the
+// first in row-major order on ties.  Each thread expands 4 x 4 tiles of the
 // product (the dense block is never stored).
-template <typename T>
+template <typename T, int NW>
 __device__ inline void lowrank_argmax(const cpx<T>* __restrict__ U, const cpx<T>* __restrict__ V,
                                       int m, int n, int t, double& best, int& be) {
-  const int lane = threadIdx.x & (WAVE - 1);
   const int ti = (m + 3) >> 2, tj = (n + 3) >> 2;
   best = -1.0;
   be = 0x7fffffff;
-  for (int tile = lane; tile < ti * tj; tile += WAVE) {
+  for (int tile = threadIdx.x; tile < ti * tj; tile += NW * WAVE) {
     const int i0 = (tile / tj) * 4, j0 = (tile % tj) * 4;
     cpx<T> acc[4][4];
 #pragma unroll
@@ -174,83 +201,98 @@ __device__ inline void lowrank_argmax(const cpx<T>* __restrict__ U, const cpx<T>
         }
       }
   }
-  wave_argmax(best, be);
+  grp_argmax<NW>(best, be);
 }
 
 // <H_d, H_l>_F = sum_{a,b} (U_l^H U_d)[a][b] (V_d^H V_l)[b][a] for factored
-// slices; lanes own (a, b) pairs, rows are staged through LDS R at a time.
+// slices.  Each thread owns up to PP (a, b) pairs per pass and accumulates both
+// factors over the rows, which are staged through LDS R at a time.
 // stage: LDS scratch of 16 KB (2 * 64 * R elements).
-template <typename T>
+template <typename T, int NW>
 __device__ inline cpx<double> lowrank_inner(const cpx<T>* __restrict__ Ul, const cpx<T>* __restrict__ Vl,
                                             int tl, const cpx<T>* __restrict__ Ud,
                                             const cpx<T>* __restrict__ Vd, int td, int m, int n,
                                             cpx<T>* stage) {
+  constexpr int NT = NW * WAVE;
   constexpr int R = int(128 / sizeof(cpx<T>));   // 16 (float) or 8 (double)
-  const int lane = threadIdx.x & (WAVE - 1);
+  constexpr int PP = 4;
+  const int tid = threadIdx.x;
   cpx<T>* sl = stage;           // [a][r]
   cpx<T>* sd = stage + 64 * R;  // [b][r]
   double re = 0.0, im = 0.0;
-  for (int p0 = 0; p0 < tl * td; p0 += WAVE) {
-    const int p = p0 + lane;
-    const bool act = p < tl * td;
-    const int a = act ? p / td : 0, b = act ? p % td : 0;
-    double pr = 0, pi = 0, qr = 0, qi = 0;
+  const int npair = tl * td;
+  for (int p0 = 0; p0 < npair; p0 += PP * NT) {
+    double pr[PP], pi[PP], qr[PP], qi[PP];
+#pragma unroll
+    for (int q = 0; q < PP; ++q) pr[q] = pi[q] = qr[q] = qi[q] = 0.0;
     for (int side = 0; side < 2; ++side) {
       const int len = side == 0 ? m : n;
       const cpx<T>* X = side == 0 ? Ul : Vd;   // conjugated operand
       const cpx<T>* Y = side == 0 ? Ud : Vl;
       const int tx = side == 0 ? tl : td, ty = side == 0 ? td : tl;
-      const int ax = side == 0 ? a : b, ay = side == 0 ? b : a;
-      double sr = 0, si = 0;
       for (int r0 = 0; r0 < len; r0 += R) {
         const int rn = min(R, len - r0);
         __syncthreads();
-        for (int e = lane; e < tx * R; e += WAVE) {
+        for (int e = tid; e < tx * R; e += NT) {
           const int c = e / R, r = e % R;
           sl[e] = r < rn ? X[int64_t(c) * len + r0 + r] : cpx<T>{T(0), T(0)};
         }
-        for (int e = lane; e < ty * R; e += WAVE) {
+        for (int e = tid; e < ty * R; e += NT) {
           const int c = e / R, r = e % R;
           sd[e] = r < rn ? Y[int64_t(c) * len + r0 + r] : cpx<T>{T(0), T(0)};
         }
         __syncthreads();
-        if (act) {
+#pragma unroll
+        for (int q = 0; q < PP; ++q) {
+          const int p = p0 + q * NT + tid;
+          if (p < npair) {
+            const int a = p / td, b = p % td;
+            const int ax = side == 0 ? a : b, ay = side == 0 ? b : a;
+            double sr = 0.0, si = 0.0;
 #pragma unroll 4
-          for (int r = 0; r < R; ++r) {
-            const cpx<T> x = sl[ax * R + r], y = sd[ay * R + r];
-            sr += double(x.re) * y.re + double(x.im) * y.im;   // conj(x) y
-            si += double(x.re) * y.im - double(x.im) * y.re;
+            for (int r = 0; r < R; ++r) {
+              const cpx<T> x = sl[ax * R + r], y = sd[ay * R + r];
+              sr += double(x.re) * y.re + double(x.im) * y.im;   // conj(x) y
+              si += double(x.re) * y.im - double(x.im) * y.re;
+            }
+            if (side == 0) { pr[q] += sr; pi[q] += si; } else { qr[q] += sr; qi[q] += si; }
           }
         }
       }
-      if (side == 0) { pr = sr; pi = si; } else { qr = sr; qi = si; }
     }
-    if (act) {
-      re += pr * qr - pi * qi;
-      im += pr * qi + pi * qr;
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+      re += pr[q] * qr[q] - pi[q] * qi[q];
+      im += pr[q] * qi[q] + pi[q] * qr[q];
     }
   }
   __syncthreads();
-  return {wave_sum(re), wave_sum(im)};
+  grp_sum2<NW>(re, im);
+  return {re, im};
 }
 
-// ALLFAR = true: admissible blocks without self/near-tier entries (the float64
-// quadrature tiers are not compiled in); ALLFAR = false: every other block.
-template <typename T, bool ALLFAR>
-__global__ void __launch_bounds__(64) aca3d_kernel(
+// 3D-ACA of admissible blocks, NW waves per block.  ALLFAR = true: blocks
+// without self/near-tier entries (the float64 quadrature tiers are not
+// compiled in); ALLFAR = false: admissible blocks that contain some.
+template <typename T, bool ALLFAR, int NW>
+__global__ void __launch_bounds__(NW * 64) aca3d_kernel(
     Tab tab, const BlockDesc3* __restrict__ blocks, const int* __restrict__ order, int nblocks,
     const double2* __restrict__ sigK, int nK, double tol_aca, double tol, int rmax, int aca_cap,
     unsigned char* __restrict__ ws, int64_t ws_stride, cpx<T>* __restrict__ pool,
     unsigned long long* __restrict__ cursor, int64_t capacity, Term3* __restrict__ terms,
     int* __restrict__ brank, int* __restrict__ bstatus, int* __restrict__ counter) {
-  __shared__ Shared3<T> sh;
-  const int lane = threadIdx.x;
+  constexpr int NT = NW * WAVE;
+  constexpr int JK = Cls<NW>::JK;
+  __shared__ Shared3<T, NW> sh;
+  const int tid = threadIdx.x;
+  const int lane = tid & (WAVE - 1), wid = tid / WAVE;
+  // per-group workspace: ACA factors and Gram matrices, Jacobi matrices of
+  // ranks above JK, Gram matrix <H_d, H_d'> of the accepted slices
   unsigned char* myws = ws + int64_t(blockIdx.x) * ws_stride;
-  // per-wave scratch layout: ACA workspace, Jacobi matrices, residual coefficients
   for (;;) {
-    int idx = 0;
-    if (lane == 0) idx = atomicAdd(counter, 1);
-    idx = __shfl(idx, 0, WAVE);
+    if (tid == 0) sh.idx = atomicAdd(counter, 1);
+    __syncthreads();
+    const int idx = sh.idx;
     if (idx >= nblocks) break;
     const int b = order[idx];
     const BlockDesc3 B = blocks[b];
@@ -261,89 +303,55 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
     cpx<double>* GU = reinterpret_cast<cpx<double>*>(myws + ws_gram_off<T>(cap, m, n));
     cpx<double>* GV = GU + cap * cap;
     cpx<double>* jmats = reinterpret_cast<cpx<double>*>(myws + ws_bytes<T>(cap, m, n));
-    cpx<T>* coef = reinterpret_cast<cpx<T>*>(jmats + 4 * 64 * 64);
-    // Gram matrix <H_d, H_d'> of the accepted slices (R3_MAX x R3_MAX)
-    cpx<double>* G3 = reinterpret_cast<cpx<double>*>(coef + R3_MAX * 64);
-    for (int w = lane; w < (nK + 31) / 32; w += WAVE) sh.usedk[w] = 0u;
+    cpx<double>* G3 = jmats + 4 * 64 * 64;
+    for (int w = tid; w < (nK + 31) / 32; w += NT) sh.usedk[w] = 0u;
     __syncthreads();
-    int ell = 0, kcur = 0, status = 0;
+    int ell = 0, kcur = 0, status = 0, nres = 0;
     double norm2 = 0.0;
     while (true) {
-      for (int d = lane; d < ell; d += WAVE) sh.fk[d] = pool[sh.term[d].fiber + kcur];
+      for (int d = tid; d < ell; d += NT) sh.fk[d] = pool[sh.term[d].fiber + kcur];
       __syncthreads();
       const double2 sg = sigK[kcur];
-      int64_t soff = -1;
-      int srank = -1;
-      // ---- residual slice at k_cur
-      if (!ALLFAR && !B.admissible) {
-        if (lane == 0) sh.alloc = pool_alloc(cursor, int64_t(m) * n, capacity);
-        __syncthreads();
-        soff = sh.alloc;
-        if (soff < 0) { status |= ST_DEFERRED; break; }
-        for (int e = lane; e < m * n; e += WAVE) {
-          const int r = e % m, c = e / m;
-          cpx<T> a = entry<T, ALLFAR>(tab, B.rb + r, B.cb + c, sg.x, sg.y, B.all_far != 0);
-          for (int d = 0; d < ell; ++d) {
-            cpx<T> p = cmul(sh.fk[d], pool[sh.term[d].slice + e]);
-            a.re -= p.re;
-            a.im -= p.im;
-          }
-          pool[soff + e] = a;
-        }
-      } else {
-        ResidualEntry<T, ALLFAR> ent{&tab, B.rb, B.cb, m, n, sg.x, sg.y, B.all_far != 0, ell, &sh,
-                                     pool, coef, true};
-        // nu = |sum_d f_d[k] H_d|_F, the current approximation of the block at
-        // k: the slice tolerance is taken relative to max(|residual|, nu)
-        double nu2 = 0.0;
-        for (int e = lane; e < ell * ell; e += WAVE) {
-          const int d = e / ell, d2 = e % ell;
-          const cpx<T> a = sh.fk[d], b = sh.fk[d2];
-          const cpx<double> g = G3[d * R3_MAX + d2];
-          // a conj(b) <H_d, H_d2>
-          const double pr = double(a.re) * b.re + double(a.im) * b.im;
-          const double pi = double(a.im) * b.re - double(a.re) * b.im;
-          nu2 += pr * g.re - pi * g.im;
-        }
-        const double nu = sqrt(fmax(wave_sum(nu2), 0.0));
-        int ast = 0;
-        const int k = aca_wave<T>(ent, m, n, cap, aca_cap, tol_aca, nu, U, W, GU, GV, sh.aca, ast);
-        if (ast & ST_CAPPED) status |= ST_CAPPED;
-        cpx<double>* A = k <= 16 ? sh.mats : jmats;
-        const int t = recompress_wave(k, cap, GU, GV, tol_aca, nu, true, A, sh.rs);
-        if (lane == 0) sh.alloc = pool_alloc(cursor, int64_t(t) * (m + n), capacity);
-        __syncthreads();
-        soff = sh.alloc;
-        if (soff < 0) { status |= ST_DEFERRED; break; }
-        apply_factors<T>(k, t, m, n, U, W, GU, GV, pool + soff, pool + soff + int64_t(t) * m, lane,
-                         WAVE);
-        srank = t;
+      // nu = |sum_d f_d[k] H_d|_F, the current approximation of the block at
+      // k: the slice tolerance is taken relative to max(|residual|, nu)
+      double nu2 = 0.0;
+      for (int e = tid; e < ell * ell; e += NT) {
+        const int d = e / ell, d2 = e % ell;
+        const cpx<T> a = sh.fk[d], bb = sh.fk[d2];
+        const cpx<double> g = G3[d * R3_MAX + d2];
+        // a conj(b) <H_d, H_d2>
+        const double pr = double(a.re) * bb.re + double(a.im) * bb.im;
+        const double pi = double(a.im) * bb.re - double(a.re) * bb.im;
+        nu2 += pr * g.re - pi * g.im;
       }
+      const double nu = sqrt(fmax(grp_sum<NW>(nu2), 0.0));
+      // ---- residual slice at k_cur: ACA, then recompression
+      ResidualEntry<T, ALLFAR, NW> ent{&tab, B.rb, B.cb, m, n, sg.x, sg.y, B.all_far != 0, ell, &sh,
+                                       pool, true};
+      int ast = 0;
+      const int k = aca_grp<NW, T>(ent, m, n, cap, aca_cap, tol_aca, nu, U, W, GU, GV, sh.aca, ast);
+      if (ast & ST_CAPPED) status |= ST_CAPPED;
+      cpx<double>* A = k <= JK ? sh.mats : jmats;
+      const int t = recompress_grp<NW>(k, cap, GU, GV, tol_aca, nu, true, A, sh.rs);
+      if (tid == 0) sh.alloc = pool_alloc(cursor, int64_t(t) * (m + n), capacity);
+      __syncthreads();
+      const int64_t soff = sh.alloc;
+      if (soff < 0) { status |= ST_DEFERRED; break; }
+      apply_factors<T>(k, t, m, n, U, W, GU, GV, pool + soff, pool + soff + int64_t(t) * m, tid, NT);
       __syncthreads();
       Term3 cur;
       cur.slice = soff;
-      cur.rank = srank;
+      cur.rank = t;
       cur.freq = kcur;
       // ---- pivot: largest modulus, first in row-major order on ties
-      double best = -1.0;
-      int be = 0x7fffffff;
-      const int mn = m * n;
-      if (srank >= 0) {
-        lowrank_argmax<T>(pool + soff, pool + soff + int64_t(srank) * m, m, n, srank, best, be);
-      } else {
-        for (int e = lane; e < mn; e += WAVE) {
-          const int i = e / n, j = e % n;  // row-major key
-          cpx<T> h = slice_at<T>(cur, pool, m, n, i, j);
-          double v = mag2(h);
-          if (v > best) { best = v; be = e; }
-        }
-        wave_argmax(best, be);
-      }
+      double best;
+      int be;
+      lowrank_argmax<T, NW>(pool + soff, pool + soff + int64_t(t) * m, m, n, t, best, be);
       if (!(best > PivFloor<T>::v)) break;   // zero pivot: rank stays ell
       const int ip = be / n, jp = be % n;
       const cpx<T> piv = slice_at<T>(cur, pool, m, n, ip, jp);
-      for (int d = lane; d < ell; d += WAVE) sh.hp[d] = slice_at<T>(sh.term[d], pool, m, n, ip, jp);
-      if (lane == 0) sh.alloc = pool_alloc(cursor, nK, capacity);
+      for (int d = tid; d < ell; d += NT) sh.hp[d] = slice_at<T>(sh.term[d], pool, m, n, ip, jp);
+      if (tid == 0) sh.alloc = pool_alloc(cursor, nK, capacity);
       __syncthreads();
       const int64_t foff = sh.alloc;
       if (foff < 0) { status |= ST_DEFERRED; break; }
@@ -351,7 +359,7 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
       // ---- fiber over K
       const cpx<T> inv = cinv(piv);
       double nf2 = 0.0;
-      for (int kk = lane; kk < nK; kk += WAVE) {
+      for (int kk = tid; kk < nK; kk += NT) {
         const double2 s2 = sigK[kk];
         cpx<T> a = entry<T, ALLFAR>(tab, B.rb + ip, B.cb + jp, s2.x, s2.y, B.all_far != 0);
         for (int d = 0; d < ell; ++d) {
@@ -359,54 +367,35 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
           a.re -= p.re;
           a.im -= p.im;
         }
-        cpx<T> f = (kk == kcur && B.admissible == 0) ? cpx<T>{T(1), T(0)} : cmul(a, inv);
+        cpx<T> f = cmul(a, inv);
         pool[foff + kk] = f;
         nf2 += double(f.re) * double(f.re) + double(f.im) * double(f.im);
       }
       __syncthreads();
-      nf2 = wave_sum(nf2);
-      // ---- eq. norm: <H_d, H_l> <f_d, f_l> cross terms and |H_l|^2 |f_l|^2
+      nf2 = grp_sum<NW>(nf2);
+      // ---- eq. norm: <H_d, H_l> = tr((U_l^H U_d)(V_d^H V_l)), |H_l|^2 with d = l
       double nh2 = 0.0;
-      if (!ALLFAR && !B.admissible) {
-        for (int e = lane; e < mn; e += WAVE) {
-          cpx<T> h = pool[soff + e];
-          nh2 += double(h.re) * double(h.re) + double(h.im) * double(h.im);
-        }
-        nh2 = wave_sum(nh2);
-        for (int d = 0; d < ell; ++d) {
-          double re = 0, im = 0;
-          const cpx<T>* Hd = pool + sh.term[d].slice;
-          for (int e = lane; e < mn; e += WAVE) {
-            cpx<T> x = Hd[e], y = pool[soff + e];
-            re += double(x.re) * y.re + double(x.im) * y.im;   // x conj(y)
-            im += double(x.im) * y.re - double(x.re) * y.im;
-          }
-          re = wave_sum(re);
-          im = wave_sum(im);
-          if (lane == 0) sh.hin[d] = {re, im};
-        }
-      } else {
-        // <H_d, H_l> = tr((U_l^H U_d)(V_d^H V_l)); |H_l|^2 likewise with d = l
-        const int tl = srank;
+      {
         const cpx<T>* Ul = pool + soff;
-        const cpx<T>* Vl = Ul + int64_t(tl) * m;
+        const cpx<T>* Vl = Ul + int64_t(t) * m;
         cpx<T>* stage = reinterpret_cast<cpx<T>*>(sh.mats);
         for (int d = 0; d <= ell; ++d) {
           const Term3 td = d < ell ? sh.term[d] : cur;
           const cpx<T>* Ud = pool + td.slice;
           const cpx<T>* Vd = Ud + int64_t(td.rank) * m;
-          const cpx<double> h = lowrank_inner<T>(Ul, Vl, tl, Ud, Vd, td.rank, m, n, stage);
+          const cpx<double> h = lowrank_inner<T, NW>(Ul, Vl, t, Ud, Vd, td.rank, m, n, stage);
           if (d < ell) {
-            if (lane == 0) sh.hin[d] = h;
+            if (tid == 0) sh.hin[d] = h;
           } else {
             nh2 = h.re;
           }
         }
       }
       __syncthreads();
-      double cross = 0.0;
-      for (int d = 0; d < ell; ++d) {
-        double fr = 0, fi = 0;  // <f_d, f_l> = sum f_d conj(f_l)
+      // <f_d, f_l> = sum f_d conj(f_l), slice d by wave d mod NW
+      double crossw = 0.0;
+      for (int d = wid; d < ell; d += NW) {
+        double fr = 0, fi = 0;
         for (int kk = lane; kk < nK; kk += WAVE) {
           cpx<T> x = pool[sh.term[d].fiber + kk], y = pool[foff + kk];
           fr += double(x.re) * y.re + double(x.im) * y.im;
@@ -414,14 +403,20 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
         }
         fr = wave_sum(fr);
         fi = wave_sum(fi);
-        cross += sh.hin[d].re * fr - sh.hin[d].im * fi;
+        crossw += sh.hin[d].re * fr - sh.hin[d].im * fi;
       }
+      const double cross = grp_sum<NW>(lane == 0 ? crossw : 0.0);
       norm2 += 2.0 * cross + nh2 * nf2;
-      if (lane == 0) sh.usedk[kcur >> 5] |= 1u << (kcur & 31);
+      if (tid == 0) sh.usedk[kcur >> 5] |= 1u << (kcur & 31);
       __syncthreads();
       if (sqrt(fmax(nh2 * nf2, 0.0)) <= tol * sqrt(fmax(norm2, 0.0))) break;  // drop term l
-      if (lane == 0) sh.term[ell] = cur;
-      for (int d = lane; d <= ell; d += WAVE) {
+      if (nres + t > Cls<NW>::RES) { status |= ST_ESCALATE; break; }         // needs a larger group
+      if (tid == 0) {
+        sh.term[ell] = cur;
+        sh.tbase[ell] = nres;
+      }
+      nres += t;
+      for (int d = tid; d <= ell; d += NT) {
         // <H_d, H_l> (d < l) and |H_l|^2
         const cpx<double> h = d < ell ? sh.hin[d] : cpx<double>{nh2, 0.0};
         G3[d * R3_MAX + ell] = h;
@@ -432,20 +427,20 @@ __global__ void __launch_bounds__(64) aca3d_kernel(
       // next frequency: largest |f_l[k]| among unused k (lowest k on ties)
       double bf = -1.0;
       int bk = 0x7fffffff;
-      for (int kk = lane; kk < nK; kk += WAVE) {
+      for (int kk = tid; kk < nK; kk += NT) {
         if ((sh.usedk[kk >> 5] >> (kk & 31)) & 1u) continue;
         double v = mag2(pool[foff + kk]);
         if (v > bf) { bf = v; bk = kk; }
       }
-      wave_argmax(bf, bk);
+      grp_argmax<NW>(bf, bk);
       if (bk == 0x7fffffff) break;                       // every frequency used
       if (ell >= rmax) { status |= ST_CAPPED; break; }
       if (!(bf > 0.0)) break;                            // fiber zero at all unused ones
       kcur = bk;
     }
     __syncthreads();
-    for (int d = lane; d < ell; d += WAVE) terms[int64_t(b) * R3_MAX + d] = sh.term[d];
-    if (lane == 0) {
+    for (int d = tid; d < ell; d += NT) terms[int64_t(b) * R3_MAX + d] = sh.term[d];
+    if (tid == 0) {
       brank[b] = ell;
       bstatus[b] = status;
     }
@@ -609,6 +604,27 @@ static __global__ void zero_int_3d(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// launch of the far kernel with NW waves per block
+template <typename T, bool AF, typename... Args>
+static void launch_far(int nw, int grid, hipStream_t st, Args... args) {
+  switch (nw) {
+    case 1: hipLaunchKernelGGL((aca3d_kernel<T, AF, 1>), dim3(grid), dim3(64), 0, st, args...); break;
+    case 2: hipLaunchKernelGGL((aca3d_kernel<T, AF, 2>), dim3(grid), dim3(128), 0, st, args...); break;
+    case 4: hipLaunchKernelGGL((aca3d_kernel<T, AF, 4>), dim3(grid), dim3(256), 0, st, args...); break;
+    default: hipLaunchKernelGGL((aca3d_kernel<T, AF, 8>), dim3(grid), dim3(512), 0, st, args...); break;
+  }
+}
+
+// side streams and fork/join events of the context, created on first use
+static int ensure_side_streams(gcq_context* ctx) {
+  if (!ctx->evfork) GCQ_HIP(hipEventCreateWithFlags(&ctx->evfork, hipEventDisableTiming));
+  for (int i = 0; i < 3; ++i) {
+    if (!ctx->side[i]) GCQ_HIP(hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking));
+    if (!ctx->evjoin[i]) GCQ_HIP(hipEventCreateWithFlags(&ctx->evjoin[i], hipEventDisableTiming));
+  }
+  return GCQ_OK;
+}
+
 }  // namespace gcq
 
 using namespace gcq;
@@ -662,15 +678,24 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   }
   const int aca_cap = 64;
   const int64_t csz = csize(precision);
-  const int64_t ws_stride =
-      ((precision == GCQ_C128 ? ws_bytes<double>(aca_cap, maxmn, 0) : ws_bytes<float>(aca_cap, maxmn, 0)) +
-       int64_t(4) * 64 * 64 * 16 + int64_t(R3_MAX) * 64 * csz + int64_t(R3_MAX) * R3_MAX * 16 +
-       4095) & ~int64_t(4095);
+  // per-group workspace: ACA factors + Gram matrices, Jacobi matrices, <H_d, H_d'>
+  auto ws_stride_for = [&](int mn) -> int64_t {
+    return ((precision == GCQ_C128 ? ws_bytes<double>(aca_cap, mn, 0) : ws_bytes<float>(aca_cap, mn, 0)) +
+            int64_t(4) * 64 * 64 * 16 + int64_t(R3_MAX) * R3_MAX * 16 + 4095) & ~int64_t(4095);
+  };
   int cus = 256;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
-  const int grid = std::min(nb, cus * 8);
-  GCQ_TRY(ctx->scratchA.ensure(size_t(ws_stride) * grid));
+  GCQ_TRY(ensure_side_streams(ctx));
+  // waves per admissible block, by size class (tuning table); doubled for a
+  // block whose residual stack outgrows its group
+  std::vector<int> bnw(nb, 1);
+  for (int b = 0; b < nb; ++b) {
+    if (!bd[b].admissible) continue;
+    const int sz = bd[b].m + bd[b].n;
+    const int c = sz <= 160 ? 0 : sz <= 320 ? 1 : sz <= 640 ? 2 : 3;
+    bnw[b] = ctx->tune.aca3d_waves[c];
+  }
   // pool: dense near slices and factored far slices, bump-allocated
   size_t freeb = 0, totalb = 0;
   GCQ_HIP(hipMemGetInfo(&freeb, &totalb));
@@ -689,11 +714,12 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   std::vector<Term3> terms(size_t(nb) * R3_MAX);
   GCQ_TRY(upload(ctx->scratchB, bd, ctx->stream));
   GCQ_TRY(upload(ctx->scratchC, sig, ctx->stream));
-  // scratch layout: cursor (8 B), 8 counters, terms, ranks, status, work order
-  GCQ_TRY(ctx->scratchD.ensure(64 + sizeof(Term3) * size_t(nb) * R3_MAX + sizeof(int) * 3 * size_t(nb)));
+  // scratch layout: cursor (8 B), 16 work counters, terms, ranks, status, work order
+  GCQ_TRY(ctx->scratchD.ensure(128 + sizeof(Term3) * size_t(nb) * R3_MAX + sizeof(int) * 3 * size_t(nb)));
   unsigned long long* d_cursor = ctx->scratchD.as<unsigned long long>();
   int* d_counter = reinterpret_cast<int*>(ctx->scratchD.as<unsigned char>() + 16);
-  Term3* d_terms = reinterpret_cast<Term3*>(ctx->scratchD.as<unsigned char>() + 64);
+  int* d_near_counter = d_counter + 8;
+  Term3* d_terms = reinterpret_cast<Term3*>(ctx->scratchD.as<unsigned char>() + 128);
   int* d_rank = reinterpret_cast<int*>(d_terms + size_t(nb) * R3_MAX);
   int* d_stat = d_rank + nb;
   int* d_order = d_stat + nb;
@@ -714,49 +740,86 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   DevBuf tensor;
   const int64_t tensor_budget = std::max<int64_t>(int64_t(1) << 28,
                                                   std::min<int64_t>(int64_t(48) << 30, int64_t(double(freeb) * 0.25)));
+  std::vector<int> opos(nb);
+  for (int i = 0; i < nb; ++i) opos[order[i]] = i;
   std::vector<int> todo = order;
-  for (int round = 0; round < 4 && !todo.empty(); ++round) {
-    hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, d_counter, 8);
+  for (int round = 0; round < 8 && !todo.empty(); ++round) {
+    hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, d_counter, 16);
     unsigned long long cur0 = (unsigned long long)used;
     GCQ_HIP(hipMemcpyAsync(d_cursor, &cur0, sizeof(cur0), hipMemcpyHostToDevice, ctx->stream));
-    // admissible blocks without near-tier entries, other admissible blocks,
-    // inadmissible blocks (from their entry tensor)
-    std::vector<int> lf, lo, lq;
+    // admissible blocks by group size (8, 4, 2, 1 waves) and kind (no
+    // near-tier entries / some), then inadmissible blocks (from their entry
+    // tensor); each list keeps the cost order
+    std::vector<int> lists[8], lq;
+    auto slot_of = [](int nw, bool allfar) {
+      const int c = nw == 8 ? 0 : nw == 4 ? 1 : nw == 2 ? 2 : 3;
+      return 2 * c + (allfar ? 0 : 1);
+    };
     for (int b : todo) {
-      if (bd[b].admissible) (bd[b].all_far ? lf : lo).push_back(b);
+      if (bd[b].admissible) lists[slot_of(bnw[b], bd[b].all_far != 0)].push_back(b);
       else lq.push_back(near_pos[b]);
     }
     std::sort(lq.begin(), lq.end());
-    std::vector<int> both(lf);
-    both.insert(both.end(), lo.begin(), lo.end());
+    std::vector<int> both;
+    int loff[8], lgrid[8];
+    int64_t lws[8], lstride[8], ws_total = 0;
+    for (int l = 0; l < 8; ++l) {
+      loff[l] = int(both.size());
+      both.insert(both.end(), lists[l].begin(), lists[l].end());
+      const int nw = 8 >> (l / 2);
+      int mn = 0;
+      for (int b : lists[l]) mn = std::max(mn, bd[b].m + bd[b].n);
+      lgrid[l] = std::min<int>(int(lists[l].size()), cus * std::max(1, 8 / nw));
+      lstride[l] = ws_stride_for(std::max(mn, 1));
+      lws[l] = ws_total;
+      ws_total += lstride[l] * lgrid[l];
+    }
+    const int nfar = int(both.size());
     both.insert(both.end(), lq.begin(), lq.end());
+    GCQ_TRY(ctx->scratchA.ensure(size_t(std::max<int64_t>(ws_total, 1))));
     GCQ_HIP(hipMemcpyAsync(d_order, both.data(), sizeof(int) * both.size(), hipMemcpyHostToDevice,
                            ctx->stream));
     GCQ_TRY(timed_begin(ctx));
-    auto launch = [&](auto tag_t, auto tag_a, int off, int cnt, int* ctr) {
-      using TT = decltype(tag_t);
-      constexpr bool AA = decltype(tag_a)::value;
-      if (cnt == 0) return;
-      hipLaunchKernelGGL((aca3d_kernel<TT, AA>), dim3(std::min(grid, cnt)), dim3(64), 0,
-                         ctx->stream, ctx->tab(), ctx->scratchB.as<BlockDesc3>(), d_order + off,
-                         cnt, ctx->scratchC.as<double2>(), nK, tol_aca, tol, int(max_freq_rank),
-                         aca_cap, ctx->scratchA.as<unsigned char>(), ws_stride,
-                         F.slices.as<cpx<TT>>(), d_cursor, capacity, d_terms, d_rank, d_stat, ctr);
-    };
-    using TrueT = std::integral_constant<bool, true>;
-    using FalseT = std::integral_constant<bool, false>;
-    if (precision == GCQ_C128) {
-      launch(double(0), TrueT(), 0, int(lf.size()), d_counter);
-      launch(double(0), FalseT(), int(lf.size()), int(lo.size()), d_counter + 1);
-    } else {
-      launch(float(0), TrueT(), 0, int(lf.size()), d_counter);
-      launch(float(0), FalseT(), int(lf.size()), int(lo.size()), d_counter + 1);
+    // group sizes 8, 4, 2 on the side streams, 1 on the context stream, all
+    // at once: the large blocks start together with the many small ones
+    GCQ_HIP(hipEventRecord(ctx->evfork, ctx->stream));
+    for (int i = 0; i < 3; ++i) GCQ_HIP(hipStreamWaitEvent(ctx->side[i], ctx->evfork, 0));
+    for (int l = 0; l < 8; ++l) {
+      const int cnt = int(lists[l].size());
+      if (cnt == 0) continue;
+      const int nw = 8 >> (l / 2);
+      hipStream_t st = l / 2 < 3 ? ctx->side[l / 2] : ctx->stream;
+      unsigned char* wsp = ctx->scratchA.as<unsigned char>() + lws[l];
+      const bool af = (l % 2) == 0;
+      if (precision == GCQ_C128) {
+        auto go = [&](auto tag) {
+          launch_far<double, decltype(tag)::value>(
+              nw, lgrid[l], st, ctx->tab(), (const BlockDesc3*)ctx->scratchB.as<BlockDesc3>(),
+              (const int*)(d_order + loff[l]), cnt, (const double2*)ctx->scratchC.as<double2>(), nK,
+              tol_aca, tol, int(max_freq_rank), aca_cap, wsp, lstride[l], F.slices.as<cpx<double>>(),
+              d_cursor, capacity, d_terms, d_rank, d_stat, d_counter + l);
+        };
+        if (af) go(std::true_type()); else go(std::false_type());
+      } else {
+        auto go = [&](auto tag) {
+          launch_far<float, decltype(tag)::value>(
+              nw, lgrid[l], st, ctx->tab(), (const BlockDesc3*)ctx->scratchB.as<BlockDesc3>(),
+              (const int*)(d_order + loff[l]), cnt, (const double2*)ctx->scratchC.as<double2>(), nK,
+              tol_aca, tol, int(max_freq_rank), aca_cap, wsp, lstride[l], F.slices.as<cpx<float>>(),
+              d_cursor, capacity, d_terms, d_rank, d_stat, d_counter + l);
+        };
+        if (af) go(std::true_type()); else go(std::false_type());
+      }
+      GCQ_HIP(hipGetLastError());
     }
-    GCQ_HIP(hipGetLastError());
+    for (int i = 0; i < 3; ++i) {
+      GCQ_HIP(hipEventRecord(ctx->evjoin[i], ctx->side[i]));
+      GCQ_HIP(hipStreamWaitEvent(ctx->stream, ctx->evjoin[i], 0));
+    }
     ms_far += timed_end(ctx, "aca3d_far_round");
     // inadmissible blocks in batches whose entry tensor fits the budget
     size_t pos = 0;
-    const int* d_q = d_order + lf.size() + lo.size();
+    const int* d_q = d_order + nfar;
     while (pos < lq.size()) {
       const int q0 = lq[pos];
       size_t end = pos;
@@ -774,7 +837,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
       const int64_t s1 = int64_t(std::lower_bound(sing_off.begin(), sing_off.end(), base0 + span) - sing_off.begin());
       GCQ_TRY(timed_begin(ctx));
       const dim3 g1(std::min(q1 - q0, 65536)), g2(4096);
-      hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, d_counter + 2, 1);
+      hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, d_near_counter, 1);
       if (precision == GCQ_C128) {
         hipLaunchKernelGGL(near_far_tier<double>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
                            ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(),
@@ -802,14 +865,14 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
                            ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(), base0,
                            tensor.as<cpx<double>>(), span, nK, tol, int(max_freq_rank),
                            F.slices.as<cpx<double>>(), d_cursor, capacity, d_terms, d_rank,
-                           d_stat, d_counter + 2);
+                           d_stat, d_near_counter);
       else
         hipLaunchKernelGGL(aca3d_near_kernel<float>, dim3(std::min(cnt, cus * 16)), dim3(64), 0,
                            ctx->stream, ctx->scratchB.as<BlockDesc3>(), d_q + pos, cnt,
                            ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(), base0,
                            tensor.as<cpx<float>>(), span, nK, tol, int(max_freq_rank),
                            F.slices.as<cpx<float>>(), d_cursor, capacity, d_terms, d_rank,
-                           d_stat, d_counter + 2);
+                           d_stat, d_near_counter);
       GCQ_HIP(hipGetLastError());
       ms_near += timed_end(ctx, "aca3d_near_batch");
       pos = end;
@@ -823,9 +886,18 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
     GCQ_HIP(hipMemcpy(blkstat.data(), d_stat, sizeof(int) * nb, hipMemcpyDeviceToHost));
     used = std::min<int64_t>(int64_t(curh), capacity);
     std::vector<int> again;
-    for (int b : todo)
-      if (blkstat[b] & ST_DEFERRED) again.push_back(b);
-    if (!again.empty()) {
+    bool grow = false;
+    for (int b : todo) {
+      if (blkstat[b] & ST_DEFERRED) {
+        again.push_back(b);
+        grow = true;
+      } else if (blkstat[b] & ST_ESCALATE) {
+        again.push_back(b);
+        bnw[b] = std::min(8, 2 * bnw[b]);
+      }
+    }
+    std::sort(again.begin(), again.end(), [&](int x, int y) { return opos[x] < opos[y]; });  // cost order
+    if (grow) {
       // grow the pool (keeping what is stored) and redo the deferred blocks
       int64_t newcap = capacity * 2;
       DevBuf bigger;

@@ -88,6 +88,84 @@ __device__ __forceinline__ void wave_argmax(T& val, int& idx) {
   }
 }
 
+// ---- group reductions: NW wave64s of one workgroup -------------------------
+// Every thread of the workgroup receives the result.  The waves' partial
+// results are combined in wave order, so the result does not depend on timing.
+// Each call starts with a barrier, which protects the exchange slots from the
+// previous call's readers.
+template <int NW>
+__device__ __forceinline__ double grp_sum(double v) {
+  v = wave_sum(v);
+  if constexpr (NW > 1) {
+    __shared__ double red[NW];
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    v = red[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += red[w];
+  }
+  return v;
+}
+template <int NW>
+__device__ __forceinline__ void grp_sum2(double& a, double& b) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if constexpr (NW > 1) {
+    __shared__ double red[2 * NW];
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+      red[2 * (threadIdx.x / WAVE)] = a;
+      red[2 * (threadIdx.x / WAVE) + 1] = b;
+    }
+    __syncthreads();
+    a = red[0];
+    b = red[1];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      a += red[2 * w];
+      b += red[2 * w + 1];
+    }
+  }
+}
+template <int NW>
+__device__ __forceinline__ int grp_min_int(int v) {
+  v = wave_min_int(v);
+  if constexpr (NW > 1) {
+    __shared__ int red[NW];
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    v = red[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v = min(v, red[w]);
+  }
+  return v;
+}
+// argmax over the group: largest val, lowest idx among equal vals
+template <int NW>
+__device__ __forceinline__ void grp_argmax(double& val, int& idx) {
+  wave_argmax(val, idx);
+  if constexpr (NW > 1) {
+    __shared__ double rv[NW];
+    __shared__ int ri[NW];
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+      rv[threadIdx.x / WAVE] = val;
+      ri[threadIdx.x / WAVE] = idx;
+    }
+    __syncthreads();
+    val = rv[0];
+    idx = ri[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+      if (rv[w] > val || (rv[w] == val && ri[w] < idx)) {
+        val = rv[w];
+        idx = ri[w];
+      }
+  }
+}
+
 // ---- constant tables (filled by the host at context creation) --------------
 struct Consts {
   double gl_x[NGL], gl_w[NGL];        // Gauss-Legendre on [0, 1]

@@ -204,7 +204,32 @@ GCQ_API int gcq_destroy(gcq_context* ctx) {
   else (void)hipDeviceSynchronize();
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->evfork) (void)hipEventDestroy(ctx->evfork);
+  for (int i = 0; i < 3; ++i) {
+    if (ctx->side[i]) {
+      (void)hipStreamSynchronize(ctx->side[i]);
+      (void)hipStreamDestroy(ctx->side[i]);
+    }
+    if (ctx->evjoin[i]) (void)hipEventDestroy(ctx->evjoin[i]);
+  }
   delete ctx;  // DevBuf destructors free device memory
+  return GCQ_OK;
+}
+
+GCQ_API int gcq_set_tuning(gcq_context* ctx, const gcq_tuning* tuning) {
+  if (!ctx || !tuning) return fail(GCQ_ERR_ARG, "ctx or tuning is NULL");
+  for (int c = 0; c < 4; ++c) {
+    const int w = tuning->aca3d_waves[c];
+    if (w != 1 && w != 2 && w != 4 && w != 8)
+      return fail(GCQ_ERR_ARG, "aca3d_waves[%d] = %d is not 1, 2, 4 or 8", c, w);
+  }
+  ctx->tune = *tuning;
+  return GCQ_OK;
+}
+
+GCQ_API int gcq_get_tuning(gcq_context* ctx, gcq_tuning* tuning) {
+  if (!ctx || !tuning) return fail(GCQ_ERR_ARG, "ctx or tuning is NULL");
+  *tuning = ctx->tune;
   return GCQ_OK;
 }
 

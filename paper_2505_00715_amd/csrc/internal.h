@@ -140,6 +140,12 @@ struct gcq_context {
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::map<std::string, double> kernel_ms;
+  // side streams (default priority) for concurrent work classes, created on
+  // first use, and the events that fork from / join into `stream`
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t evfork = nullptr, evjoin[3] = {nullptr, nullptr, nullptr};
+  // launch configuration
+  gcq_tuning tune = {{1, 2, 4, 8}};
 
   // mesh
   bool have_mesh = false;

@@ -57,7 +57,7 @@ struct RecompShared {
 };
 
 // ---- ACA of an entry function --------------------------------------------------
-// Ent: prep_row(i) / prep_col(j) (wave-collective, may be empty) and
+// Ent: prep_row(i) / prep_col(j) (group-collective, may be empty) and
 // operator()(i, j) -> cpx<T>.  Partial pivoting: row residual -> pivot column
 // (largest modulus, lowest index on ties) -> column residual -> Frobenius norm
 // of the approximant updated with the cross terms (u_l^H u_k)(w_l^H w_k) ->
@@ -67,13 +67,17 @@ struct RecompShared {
 // the Gram matrices GU = U^H U and GV = V^H V (V = conj(W)), stored for the
 // recompression.  Returns the rank; `status` receives ST_* bits.
 // nu: absolute norm floor of the stopping test (0: relative to the block itself)
-template <typename T, typename Ent>
-__device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double tol, double nu,
-                        cpx<T>* __restrict__ U, cpx<T>* __restrict__ W,
-                        cpx<double>* __restrict__ GU, cpx<double>* __restrict__ GV,
-                        AcaShared<T>& sm, int& status) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  for (int w = lane; w < (m + 31) / 32; w += WAVE) sm.used[w] = 0u;
+// NW wave64s of the workgroup run the approximation together: rows and
+// columns are split over all threads, each Gram entry is summed by one wave.
+template <int NW, typename T, typename Ent>
+__device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol, double nu,
+                       cpx<T>* __restrict__ U, cpx<T>* __restrict__ W,
+                       cpx<double>* __restrict__ GU, cpx<double>* __restrict__ GV,
+                       AcaShared<T>& sm, int& status) {
+  constexpr int NT = NW * WAVE;
+  const int tid = threadIdx.x;
+  const int lane = tid & (WAVE - 1), wid = tid / WAVE;
+  for (int w = tid; w < (m + 31) / 32; w += NT) sm.used[w] = 0u;
   __syncthreads();
   const int kmax = min(min(m, n), cap);
   int k = 0, i = 0, nused = 0;
@@ -82,11 +86,11 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
   while (k < kmax) {
     // row residual of row i into W[k]
     ent.prep_row(i);
-    for (int l = lane; l < k; l += WAVE) sm.ubuf[l] = U[int64_t(l) * m + i];
+    for (int l = tid; l < k; l += NT) sm.ubuf[l] = U[int64_t(l) * m + i];
     __syncthreads();
     double best = -1.0;
     int bj = 0x7fffffff;
-    for (int j = lane; j < n; j += WAVE) {
+    for (int j = tid; j < n; j += NT) {
       cpx<T> a = ent(i, j);
       for (int l = 0; l < k; ++l) {
         cpx<T> p = cmul(sm.ubuf[l], W[int64_t(l) * n + j]);
@@ -97,39 +101,40 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
       double v = mag2(a);
       if (v > best) { best = v; bj = j; }
     }
-    if (lane == 0) sm.used[i >> 5] |= 1u << (i & 31);
+    if (tid == 0) sm.used[i >> 5] |= 1u << (i & 31);
     ++nused;
-    wave_argmax(best, bj);
+    grp_argmax<NW>(best, bj);
     __syncthreads();
     if (!(best > PivFloor<T>::v)) {
       int cand = 0x7fffffff;
-      for (int w = lane; w < (m + 31) / 32; w += WAVE) {
+      for (int w = tid; w < (m + 31) / 32; w += NT) {
         unsigned free_bits = ~sm.used[w];
         if (w == (m - 1) / 32 && (m & 31)) free_bits &= (1u << (m & 31)) - 1u;
         if (free_bits) cand = min(cand, w * 32 + __ffs(free_bits) - 1);
       }
-      cand = wave_min_int(cand);
+      cand = grp_min_int<NW>(cand);
       if (cand == 0x7fffffff || nused >= m) { status |= ST_EXACT; break; }
       i = cand;
       continue;
     }
     const int jstar = bj;
     const cpx<T> inv = cinv(W[int64_t(k) * n + jstar]);
+    __syncthreads();   // every thread has read the pivot before it is overwritten
     double nw2 = 0.0;
-    for (int j = lane; j < n; j += WAVE) {
+    for (int j = tid; j < n; j += NT) {
       cpx<T> w = (j == jstar) ? cpx<T>{T(1), T(0)} : cmul(W[int64_t(k) * n + j], inv);
       W[int64_t(k) * n + j] = w;
       nw2 += double(w.re) * double(w.re) + double(w.im) * double(w.im);
     }
     __syncthreads();
     ent.prep_col(jstar);
-    for (int l = lane; l < k; l += WAVE) sm.ubuf[l] = W[int64_t(l) * n + jstar];
+    for (int l = tid; l < k; l += NT) sm.ubuf[l] = W[int64_t(l) * n + jstar];
     __syncthreads();
     // column residual of column jstar into U[k]; candidate next row
     double nu2 = 0.0;
     double bestu = -1.0;
     int bi = 0x7fffffff;
-    for (int r = lane; r < m; r += WAVE) {
+    for (int r = tid; r < m; r += NT) {
       cpx<T> a = ent(r, jstar);
       for (int l = 0; l < k; ++l) {
         cpx<T> p = cmul(sm.ubuf[l], U[int64_t(l) * m + r]);
@@ -144,10 +149,10 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
       }
     }
     __syncthreads();
-    nw2 = wave_sum(nw2);
-    nu2 = wave_sum(nu2);
-    double cross = 0.0;
-    for (int l = 0; l < k; ++l) {
+    grp_sum2<NW>(nw2, nu2);
+    // Gram entries of the new term: entry l by wave l mod NW
+    double crossw = 0.0;
+    for (int l = wid; l < k; l += NW) {
       double gur = 0, gui = 0, gwr = 0, gwi = 0;
       for (int r = lane; r < m; r += WAVE) {
         cpx<T> a = U[int64_t(l) * m + r], b = U[int64_t(k) * m + r];
@@ -163,7 +168,7 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
       gui = wave_sum(gui);
       gwr = wave_sum(gwr);
       gwi = wave_sum(gwi);
-      cross += gur * gwr - gui * gwi;  // Re((u_l^H u_k)(w_l^H w_k))
+      crossw += gur * gwr - gui * gwi;  // Re((u_l^H u_k)(w_l^H w_k))
       if (lane == 0) {
         GU[l * cap + k] = {gur, gui};
         GU[k * cap + l] = {gur, -gui};
@@ -172,7 +177,8 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
         GV[k * cap + l] = {gwr, gwi};
       }
     }
-    if (lane == 0) {
+    const double cross = grp_sum<NW>(lane == 0 ? crossw : 0.0);
+    if (tid == 0) {
       GU[k * cap + k] = {nu2, 0.0};
       GV[k * cap + k] = {nw2, 0.0};
     }
@@ -182,7 +188,7 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
       status |= ST_CONVERGED;
       break;
     }
-    wave_argmax(bestu, bi);
+    grp_argmax<NW>(bestu, bi);
     if (nused >= m || bi == 0x7fffffff) { status |= ST_EXACT; break; }
     i = bi;
   }
@@ -195,7 +201,15 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
   return k;
 }
 
-// ---- Hermitian Jacobi eigen-solver, one wave, k <= 64 -------------------------
+template <typename T, typename Ent>
+__device__ inline int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double tol, double nu,
+                               cpx<T>* __restrict__ U, cpx<T>* __restrict__ W,
+                               cpx<double>* __restrict__ GU, cpx<double>* __restrict__ GV,
+                               AcaShared<T>& sm, int& status) {
+  return aca_grp<1, T, Ent>(ent, m, n, cap, max_rank, tol, nu, U, W, GU, GV, sm, status);
+}
+
+// ---- Hermitian Jacobi eigen-solver, one group, k <= 64 ------------------------
 // A (k x k, row-major, generic memory) is overwritten by its eigenvalues on the
 // diagonal; Q (k x k) receives the eigenvectors as columns.  Each rotation is
 // G = diag(1, conj(e)) R(c, s), which zeroes A[p][q] = |b| e with the real
@@ -204,28 +218,29 @@ __device__ int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, double to
 // pairs at once, so a sweep is k - 1 parallel rounds instead of k (k - 1) / 2
 // sequential rotations.  Rotations of one round commute (disjoint pairs), so the
 // result equals the cyclic sweep in that pair order.
-__device__ inline void jacobi_herm(cpx<double>* A, cpx<double>* Q, int k, RecompShared& rs) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  for (int r = lane; r < k * k; r += WAVE) Q[r] = {(r / k == r % k) ? 1.0 : 0.0, 0.0};
+template <int NW>
+__device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompShared& rs) {
+  constexpr int NT = NW * WAVE;
+  const int tid = threadIdx.x;
+  for (int r = tid; r < k * k; r += NT) Q[r] = {(r / k == r % k) ? 1.0 : 0.0, 0.0};
   __syncthreads();
   if (k < 2) return;
   const int ke = (k + 1) & ~1;   // even number of positions (one dummy when k is odd)
   const int np = ke / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dg = 0.0;
-    for (int r = lane; r < k * k; r += WAVE) {
+    for (int r = tid; r < k * k; r += NT) {
       double v = cabs2(A[r]);
       if (r / k == r % k) dg += v;
       else off += v;
     }
-    off = wave_sum(off);
-    dg = wave_sum(dg);
+    grp_sum2<NW>(off, dg);
     if (off <= 1e-30 * dg || off == 0.0) break;
     for (int round = 0; round < ke - 1; ++round) {
-      if (lane < np) {
+      if (tid < np) {
         // circle method: position 0 fixed, positions 1..ke-1 rotate
         auto idx = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (ke - 1); };
-        int p = idx(lane), q = idx(ke - 1 - lane);
+        int p = idx(tid), q = idx(ke - 1 - tid);
         if (p > q) { int t = p; p = q; q = t; }
         double c = 1.0, sv = 0.0, a = 0.0, d = 0.0, tb = 0.0;
         cpx<double> e = {1.0, 0.0};
@@ -245,18 +260,18 @@ __device__ inline void jacobi_herm(cpx<double>* A, cpx<double>* Q, int k, Recomp
             q = k;   // nothing to rotate
           }
         }
-        rs.jp[lane] = p;
-        rs.jq[lane] = q;
-        rs.jc[lane] = c;
-        rs.js[lane] = sv;
-        rs.je[lane] = e;
-        rs.ja[lane] = a;
-        rs.jd[lane] = d;
-        rs.jtb[lane] = tb;
+        rs.jp[tid] = p;
+        rs.jq[tid] = q;
+        rs.jc[tid] = c;
+        rs.js[tid] = sv;
+        rs.je[tid] = e;
+        rs.ja[tid] = a;
+        rs.jd[tid] = d;
+        rs.jtb[tid] = tb;
       }
       __syncthreads();
       // columns p, q of A and Q, every row
-      for (int x = lane; x < k * np; x += WAVE) {
+      for (int x = tid; x < k * np; x += NT) {
         const int r = x / np, i = x % np;
         const int p = rs.jp[i], q = rs.jq[i];
         if (q >= k) continue;
@@ -274,7 +289,7 @@ __device__ inline void jacobi_herm(cpx<double>* A, cpx<double>* Q, int k, Recomp
       }
       __syncthreads();
       // rows p, q of A, every column
-      for (int x = lane; x < k * np; x += WAVE) {
+      for (int x = tid; x < k * np; x += NT) {
         const int r = x / np, i = x % np;
         const int p = rs.jp[i], q = rs.jq[i];
         if (q >= k) continue;
@@ -286,12 +301,12 @@ __device__ inline void jacobi_herm(cpx<double>* A, cpx<double>* Q, int k, Recomp
         A[q * k + r] = {sv * u.re + c * ev.re, sv * u.im + c * ev.im};
       }
       __syncthreads();
-      if (lane < np && rs.jq[lane] < k) {
-        const int p = rs.jp[lane], q = rs.jq[lane];
+      if (tid < np && rs.jq[tid] < k) {
+        const int p = rs.jp[tid], q = rs.jq[tid];
         A[p * k + q] = {0.0, 0.0};
         A[q * k + p] = {0.0, 0.0};
-        A[p * k + p] = {rs.ja[lane] - rs.jtb[lane], 0.0};
-        A[q * k + q] = {rs.jd[lane] + rs.jtb[lane], 0.0};
+        A[p * k + p] = {rs.ja[tid] - rs.jtb[tid], 0.0};
+        A[q * k + q] = {rs.jd[tid] + rs.jtb[tid], 0.0};
       }
       __syncthreads();
     }
@@ -305,13 +320,15 @@ __device__ inline void jacobi_herm(cpx<double>* A, cpx<double>* Q, int k, Recomp
 // sqrt(sum_{i >= t} s_i^2) <= tol max(sqrt(sum s_i^2), nu) and writes the coefficients
 // CU = Q L^{1/2} Z_t and CV = Q L^{-1/2} Z_t (k x t, leading dimension t) over GU
 // and GV.  Without recompression CU = CV = I, t = k.  Returns t.
-__device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol,
-                                      double nu, bool do_recompress, cpx<double>* mats,
-                                      RecompShared& rs) {
-  const int lane = threadIdx.x & (WAVE - 1);
+template <int NW>
+__device__ inline int recompress_grp(int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol,
+                                     double nu, bool do_recompress, cpx<double>* mats,
+                                     RecompShared& rs) {
+  constexpr int NT = NW * WAVE;
+  const int tid = threadIdx.x;
   if (k == 0 || !do_recompress) {
     __syncthreads();
-    for (int r = lane; r < k * k; r += WAVE) {
+    for (int r = tid; r < k * k; r += NT) {
       GU[r] = {(r / k == r % k) ? 1.0 : 0.0, 0.0};
       GV[r] = GU[r];
     }
@@ -322,14 +339,14 @@ __device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<doubl
   cpx<double>* Q = A + k * k;
   cpx<double>* B = Q + k * k;
   cpx<double>* Z = B + k * k;
-  for (int r = lane; r < k * k; r += WAVE) A[r] = GV[(r / k) * cap + (r % k)];
+  for (int r = tid; r < k * k; r += NT) A[r] = GV[(r / k) * cap + (r % k)];
   __syncthreads();
-  jacobi_herm(A, Q, k, rs);
-  if (lane < k) rs.lam[lane] = A[lane * k + lane].re;
+  jacobi_grp<NW>(A, Q, k, rs);
+  if (tid < k) rs.lam[tid] = A[tid * k + tid].re;
   __syncthreads();
   double lmax = 0.0;
   for (int a = 0; a < k; ++a) lmax = fmax(lmax, rs.lam[a]);
-  if (lane == 0) {
+  if (tid == 0) {
     int c = 0;
     for (int a = 0; a < k; ++a)
       if (rs.lam[a] > 1e-14 * lmax && rs.lam[a] > 0.0) rs.keep[c++] = a;
@@ -339,7 +356,7 @@ __device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<doubl
   const int kk = rs.nkeep;
   if (kk == 0) return 0;
   // T1 = GU Q_S (k x kk) into Z, then B = L^1/2 Q_S^H T1 L^1/2
-  for (int e = lane; e < k * kk; e += WAVE) {
+  for (int e = tid; e < k * kk; e += NT) {
     const int x = e / kk, b = e % kk;
     const int qb = rs.keep[b];
     cpx<double> acc = {0, 0};
@@ -351,7 +368,7 @@ __device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<doubl
     Z[x * kk + b] = acc;
   }
   __syncthreads();
-  for (int e = lane; e < kk * kk; e += WAVE) {
+  for (int e = tid; e < kk * kk; e += NT) {
     const int a = e / kk, b = e % kk;
     const int qa = rs.keep[a];
     cpx<double> acc = {0, 0};
@@ -364,7 +381,7 @@ __device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<doubl
     B[a * kk + b] = {acc.re * sc, acc.im * sc};
   }
   __syncthreads();
-  for (int e = lane; e < kk * kk; e += WAVE) {  // Hermitian part
+  for (int e = tid; e < kk * kk; e += NT) {  // Hermitian part
     const int a = e / kk, b = e % kk;
     if (a < b) {
       cpx<double> x = B[a * kk + b], y = B[b * kk + a];
@@ -376,17 +393,17 @@ __device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<doubl
     }
   }
   __syncthreads();
-  jacobi_herm(B, Z, kk, rs);
-  if (lane < kk) rs.sg[lane] = fmax(B[lane * kk + lane].re, 0.0);
+  jacobi_grp<NW>(B, Z, kk, rs);
+  if (tid < kk) rs.sg[tid] = fmax(B[tid * kk + tid].re, 0.0);
   __syncthreads();
-  if (lane < kk) {  // descending order, ties by index
+  if (tid < kk) {  // descending order, ties by index
     int pos = 0;
     for (int b = 0; b < kk; ++b)
-      if (rs.sg[b] > rs.sg[lane] || (rs.sg[b] == rs.sg[lane] && b < lane)) ++pos;
-    rs.order[pos] = lane;
+      if (rs.sg[b] > rs.sg[tid] || (rs.sg[b] == rs.sg[tid] && b < tid)) ++pos;
+    rs.order[pos] = tid;
   }
   __syncthreads();
-  if (lane == 0) {
+  if (tid == 0) {
     double total = 0.0;
     for (int a = 0; a < kk; ++a) total += rs.sg[a];
     double tail = 0.0;
@@ -401,7 +418,7 @@ __device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<doubl
   }
   __syncthreads();
   const int t = rs.tcut;
-  for (int e = lane; e < k * t; e += WAVE) {
+  for (int e = tid; e < k * t; e += NT) {
     const int x = e / t, c = e % t;
     const int zc = rs.order[c];
     cpx<double> au = {0, 0}, av = {0, 0};
@@ -418,12 +435,18 @@ __device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<doubl
     B[e] = av;
   }
   __syncthreads();
-  for (int e = lane; e < k * t; e += WAVE) {
+  for (int e = tid; e < k * t; e += NT) {
     GU[e] = A[e];
     GV[e] = B[e];
   }
   __syncthreads();
   return t;
+}
+
+__device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol,
+                                      double nu, bool do_recompress, cpx<double>* mats,
+                                      RecompShared& rs) {
+  return recompress_grp<1>(k, cap, GU, GV, tol, nu, do_recompress, mats, rs);
 }
 
 // ---- Ubar = U CU (m x t), Vbar = conj(W) CV (n x t), column-major outputs ----------

@@ -84,3 +84,13 @@ def test_argument_and_state_errors():
     assert rc < 0
     assert g.lib.gcq_destroy(None) == 0
     ctx.destroy()
+
+
+def test_tuning_roundtrip_and_rejection():
+    ctx = g.Context(-1)
+    assert list(ctx.get_tuning().aca3d_waves) == [1, 2, 4, 8]
+    ctx.set_tuning(aca3d_waves=(1, 1, 2, 4))
+    assert list(ctx.get_tuning().aca3d_waves) == [1, 1, 2, 4]
+    with pytest.raises(g.GcqError):
+        ctx.set_tuning(aca3d_waves=(1, 3, 4, 8))
+    assert list(ctx.get_tuning().aca3d_waves) == [1, 1, 2, 4]

@@ -95,3 +95,31 @@ def test_products_without_conjugate_symmetry(setup):
     Yg = from_dev(Y).reshape(len(s), P.n)
     Yt = matvec.dense(entries.dense(P, s, 1.0), X)
     assert rel(Yg, Yt) <= 1e-4
+
+
+@pytest.mark.parametrize("waves", [(1, 1, 1, 1), (2, 2, 2, 2), (4, 4, 4, 4), (8, 8, 8, 8)])
+def test_aca3d_group_sizes(setup, waves):
+    """Every group size (waves per block) gives the oracle's 3D-ACA."""
+    xyz, tri, s, P, T, B, rep, conj, K, kpos, b3 = setup
+    ctx = make_ctx(xyz, tri, 1.0, s, 32, 1.0)
+    ctx.set_tuning(aca3d_waves=waves)
+    assert list(ctx.get_tuning().aca3d_waves) == list(waves)
+    ctx.aca3d(TOLA, TOLF, 40, g.C128)
+    num = den = 0.0
+    same = 0
+    nfar = 0
+    for b, Bo in enumerate(b3):
+        if not Bo.admissible:
+            continue
+        nfar += 1
+        freqs, fib, sl = ctx.get_aca3d_block(b, len(K))
+        Tg = np.einsum("dk,dij->kij", fib, sl) if len(freqs) else 0.0
+        To = Bo.tensor() if Bo.rank else 0.0
+        num += np.linalg.norm(Tg - To) ** 2
+        den += np.linalg.norm(To) ** 2
+        same += len(freqs) == Bo.rank
+    assert nfar > 0
+    err = np.sqrt(num / den)
+    assert err <= 1e-5, err
+    assert same >= 0.9 * nfar
+
