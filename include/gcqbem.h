@@ -96,12 +96,16 @@ enum {
 /* Launch configuration (gcq_set_tuning / gcq_get_tuning).
  *   aca3d_waves[c]: wave64s that work together on one admissible block in
  *     gcq_aca3d, for blocks with |I| + |J| <= 160, <= 320, <= 640 and > 640
- *     (c = 0..3); each 1, 2, 4 or 8.  Default {1, 2, 4, 8}.  Blocks whose
+ *     (c = 0..3); each 1, 2, 4 or 8.  Default {4, 4, 4, 4}.  Blocks whose
  *     accepted slices outgrow the group's on-chip storage are redone with
- *     twice the waves; results do not depend on the setting beyond rounding
- *     order. */
+ *     twice the waves.
+ *   aca3d_stack_slices: initial reservation of an admissible block's stacked
+ *     slice factors, in slices of full ACA rank (1..64, default 8); a block
+ *     that needs more moves its stack to a reservation twice as large.
+ * Results do not depend on the configuration beyond rounding order. */
 typedef struct {
   int32_t aca3d_waves[4];
+  int32_t aca3d_stack_slices;
 } gcq_tuning;
 
 typedef struct {

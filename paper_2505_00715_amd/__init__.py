@@ -50,7 +50,7 @@ class SolveStats(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("aca3d_waves", C.c_int32 * 4)]
+    _fields_ = [("aca3d_waves", C.c_int32 * 4), ("aca3d_stack_slices", C.c_int32)]
 
 
 class TrainCfg(C.Structure):
@@ -174,12 +174,15 @@ class Context:
     def kernel_ms(self, name: str) -> float:
         return _lib.gcq_kernel_ms(self._h, name.encode())
 
-    def set_tuning(self, aca3d_waves=None):
-        """aca3d_waves: 4 group sizes (waves per block) of the 3D-ACA size classes."""
+    def set_tuning(self, aca3d_waves=None, aca3d_stack_slices=None):
+        """aca3d_waves: 4 group sizes (waves per block) of the 3D-ACA size classes;
+        aca3d_stack_slices: initial stack reservation of a far block (slices)."""
         t = self.get_tuning()
         if aca3d_waves is not None:
             for c, w in enumerate(aca3d_waves):
                 t.aca3d_waves[c] = int(w)
+        if aca3d_stack_slices is not None:
+            t.aca3d_stack_slices = int(aca3d_stack_slices)
         _check(_lib.gcq_set_tuning(self._h, C.byref(t)))
 
     def get_tuning(self) -> Tuning:

@@ -20,8 +20,8 @@ struct PlainEntry {
   bool all_far;
   __device__ void prep_row(int) {}
   __device__ void prep_col(int) {}
-  __device__ cpx<T> operator()(int i, int j) const {
-    return entry<T, ALLFAR>(*tab, rb + i, cb + j, sr, si, all_far);
+  __device__ cpx<T> part(int i, int j, int p, int P) const {
+    return entry_part<T, ALLFAR>(*tab, rb + i, cb + j, sr, si, all_far, p, P);
   }
 };
 
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(64) recompress_kernel(const PairDesc* __restri
     const PairDesc d = pairs[pid];
     const int k = rank_in[pid], cap = d.cap;
     cpx<double>* GU = reinterpret_cast<cpx<double>*>(ws + d.ws + ws_gram_off<T>(cap, d.m, d.n));
-    cpx<double>* A = k <= 16 ? mats
+    cpx<double>* A = recompress_mats(k) <= 4 * 16 * 16 ? mats
                              : reinterpret_cast<cpx<double>*>(jws) + int64_t(blockIdx.x) * 4 * 64 * 64;
     const int t = recompress_wave(k, cap, GU, GU + cap * cap, tol, 0.0, do_recompress != 0, A, rs);
     if (threadIdx.x == 0) out_t[pid] = t;

@@ -18,48 +18,68 @@ constexpr int NK_MAX = 2048;    // frequencies in K
 struct BlockDesc3 {
   int rb, m, cb, n;
   int admissible, all_far;
+  int sres;        // admissible: columns reserved for the block's stacked slice factors
+  int pad;
 };
 
+// A term of a block.  Far blocks keep their slices' factors stacked: the
+// block reserves U columns (m x sres) and V columns (n x sres) in the pool,
+// and slice d owns columns [c_d, c_d + rank_d) of both.
 struct Term3 {
-  int64_t slice;   // pool offset (elements) of the slice: dense m x n, or Ubar then Vbar
+  int64_t slice;   // pool offset (elements) of the slice: dense m x n, or its first Ubar column
+  int64_t vslice;  // far: pool offset of its first Vbar column
   int64_t fiber;   // pool offset of the fiber (nK elements)
   int rank;        // slice rank (far) or -1 (dense)
   int freq;        // position in K of the frequency the slice was taken at
 };
 
-// LDS capacities of the far kernel per group size NW (waves per block):
-// RES residual coefficients (sum of the accepted slices' ranks; a block whose
-// slices need more is handed to the next larger group), JK the largest ACA
-// rank whose recompression runs in LDS (larger ones use the global workspace).
+// LDS of the far kernel per group size NW (waves per block).  One area serves
+// three uses that never overlap in time: the residual coefficients of the
+// slice ACA (RES of them: the sum of the accepted slices' ranks; a block whose
+// slices need more is redone by the next larger group), the recompression
+// matrices (ranks up to JK in LDS, larger ones in the global workspace), and
+// the 16 KB row staging of the slice inner products.
 template <int NW>
 struct Cls;
 template <>
 struct Cls<1> {
-  static constexpr int RES = 512, JK = 16;
+  static constexpr int JK = 19;
 };
 template <>
 struct Cls<2> {
-  static constexpr int RES = 1024, JK = 16;
+  static constexpr int JK = 20;
 };
 template <>
 struct Cls<4> {
-  static constexpr int RES = 2048, JK = 24;
+  static constexpr int JK = 28;
 };
 template <>
 struct Cls<8> {
-  static constexpr int RES = R3_MAX * 64, JK = 32;   // every possible stack
+  static constexpr int JK = 28;
 };
 
-enum : int { ST_ESCALATE = 32 };   // residual stack exceeds the group's LDS capacity
+enum : int {
+  ST_ESCALATE = 32    // residual coefficients exceed the group's LDS capacity
+};
 
 template <typename T, int NW>
 struct Shared3 {
-  cpx<T> coef[Cls<NW>::RES];   // residual coefficients of the current row / column
+  static constexpr int A0 = 3 * Cls<NW>::JK * Cls<NW>::JK * 16;
+  static constexpr int A1 = A0 > 16384 ? A0 : 16384;
+  // the largest group holds every possible stack (R3_MAX slices of rank <= 64)
+  static constexpr int A2 = NW == 8 ? R3_MAX * 64 * int(sizeof(cpx<T>)) : 0;
+  static constexpr int BYTES = A1 > A2 ? A1 : A2;
+  static constexpr int RES0 = BYTES / int(sizeof(cpx<T>));
+  static constexpr int RES = RES0 < R3_MAX * 64 ? RES0 : R3_MAX * 64;
+  static constexpr int JK = Cls<NW>::JK;
+  union {
+    cpx<T> coef[RES0];          // residual coefficients of the current row / column
+    cpx<double> mats[BYTES / 16];
+  };
   AcaShared<T> aca;
   RecompShared rs;
-  cpx<double> mats[4 * Cls<NW>::JK * Cls<NW>::JK];
   Term3 term[R3_MAX];
-  int tbase[R3_MAX];           // first coefficient of each slice
+  unsigned char cterm[RES];    // slice of each stacked column
   cpx<T> fk[R3_MAX];           // f_d[k_cur]
   cpx<T> hp[R3_MAX];           // H_d[i_l, j_l]
   cpx<double> hin[R3_MAX];     // <H_d, H_l>
@@ -77,65 +97,56 @@ __device__ inline int64_t pool_alloc(unsigned long long* cursor, int64_t cnt, in
 
 // residual entry function of a far block at one frequency:
 //   R(i, j) = A_ij(s) - sum_d f_d[k] (Ubar_d Vbar_d^H)[i, j]
-// A row (column) evaluation first forms the coefficients f_d[k] Ubar_d[i][c]
-// (f_d[k] conj(Vbar_d[j][c])) of all slices in LDS; each thread then subtracts
-// sum_{d,c} coef conj(Vbar_d[j][c]) (sum_{d,c} Ubar_d[i][c] coef) from its entry.
+// over the nres stacked columns x of the accepted slices (x of slice cterm[x]).
+// A row (column) evaluation first forms the coefficients f_d[k] Ubar[i][x]
+// (f_d[k] conj(Vbar[j][x])) in LDS; each entry then subtracts
+// sum_x coef[x] conj(Vbar[j][x]) (sum_x Ubar[i][x] coef[x]).
 template <typename T, bool ALLFAR, int NW>
 struct ResidualEntry {
   const Tab* tab;
   int rb, cb, m, n;
   double sr, si;
   bool all_far;
-  int nterm;
+  int nres;
   Shared3<T, NW>* sh;
-  const cpx<T>* pool;
+  const cpx<T>* Us;   // stacked Ubar columns (m apart)
+  const cpx<T>* Vs;   // stacked Vbar columns (n apart)
   bool rowmode;
   __device__ void prep_row(int i) {
-    for (int d = 0; d < nterm; ++d) {
-      const Term3 t = sh->term[d];
-      const cpx<T>* Ud = pool + t.slice;
-      const cpx<T> f = sh->fk[d];
-      for (int c = threadIdx.x; c < t.rank; c += NW * WAVE)
-        sh->coef[sh->tbase[d] + c] = cmul(f, Ud[int64_t(c) * m + i]);
-    }
+    for (int x = threadIdx.x; x < nres; x += NW * WAVE)
+      sh->coef[x] = cmul(sh->fk[sh->cterm[x]], Us[int64_t(x) * m + i]);
     rowmode = true;
     __syncthreads();
   }
   __device__ void prep_col(int j) {
-    for (int d = 0; d < nterm; ++d) {
-      const Term3 t = sh->term[d];
-      const cpx<T>* Vd = pool + t.slice + int64_t(t.rank) * m;
-      const cpx<T> f = sh->fk[d];
-      for (int c = threadIdx.x; c < t.rank; c += NW * WAVE) {
-        const cpx<T> v = Vd[int64_t(c) * n + j];
-        sh->coef[sh->tbase[d] + c] = cmul(f, cpx<T>{v.re, -v.im});
-      }
+    for (int x = threadIdx.x; x < nres; x += NW * WAVE) {
+      const cpx<T> v = Vs[int64_t(x) * n + j];
+      sh->coef[x] = cmul(sh->fk[sh->cterm[x]], cpx<T>{v.re, -v.im});
     }
     rowmode = false;
     __syncthreads();
   }
-  __device__ cpx<T> operator()(int i, int j) const {
-    cpx<T> a = entry<T, ALLFAR>(*tab, rb + i, cb + j, sr, si, all_far);
+  // part p of P of the residual entry (i, j): quadrature points and stacked
+  // columns x = p, p + P, ...
+  __device__ cpx<T> part(int i, int j, int p, int P) const {
+    cpx<T> a = entry_part<T, ALLFAR>(*tab, rb + i, cb + j, sr, si, all_far, p, P);
     T ar = 0, ai = 0;
-    for (int d = 0; d < nterm; ++d) {
-      const Term3 t = sh->term[d];
-      const cpx<T>* q = sh->coef + sh->tbase[d];
-      if (rowmode) {
-        const cpx<T>* Vd = pool + t.slice + int64_t(t.rank) * m + j;
-#pragma unroll 4
-        for (int c = 0; c < t.rank; ++c) {
-          const cpx<T> v = Vd[int64_t(c) * n], x = q[c];
-          ar += x.re * v.re + x.im * v.im;   // x conj(v)
-          ai += x.im * v.re - x.re * v.im;
-        }
-      } else {
-        const cpx<T>* Ud = pool + t.slice + i;
-#pragma unroll 4
-        for (int c = 0; c < t.rank; ++c) {
-          const cpx<T> u = Ud[int64_t(c) * m], x = q[c];
-          ar += u.re * x.re - u.im * x.im;
-          ai += u.re * x.im + u.im * x.re;
-        }
+    const cpx<T>* q = sh->coef;
+    if (rowmode) {
+      const cpx<T>* V = Vs + j;
+#pragma unroll 8
+      for (int x = p; x < nres; x += P) {
+        const cpx<T> v = V[int64_t(x) * n], c = q[x];
+        ar += c.re * v.re + c.im * v.im;   // c conj(v)
+        ai += c.im * v.re - c.re * v.im;
+      }
+    } else {
+      const cpx<T>* U = Us + i;
+#pragma unroll 8
+      for (int x = p; x < nres; x += P) {
+        const cpx<T> u = U[int64_t(x) * m], c = q[x];
+        ar += u.re * c.re - u.im * c.im;
+        ai += u.re * c.im + u.im * c.re;
       }
     }
     a.re -= ar;
@@ -148,7 +159,7 @@ struct ResidualEntry {
 template <typename T>
 __device__ inline cpx<T> slice_at(const Term3& t, const cpx<T>* pool, int m, int n, int i, int j) {
   const cpx<T>* U = pool + t.slice;
-  const cpx<T>* V = U + int64_t(t.rank) * m;
+  const cpx<T>* V = pool + t.vslice;
   cpx<T> acc = {T(0), T(0)};
   for (int c = 0; c < t.rank; ++c) {
     cpx<T> v = V[int64_t(c) * n + j];
@@ -282,8 +293,9 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
     unsigned long long* __restrict__ cursor, int64_t capacity, Term3* __restrict__ terms,
     int* __restrict__ brank, int* __restrict__ bstatus, int* __restrict__ counter) {
   constexpr int NT = NW * WAVE;
-  constexpr int JK = Cls<NW>::JK;
-  __shared__ Shared3<T, NW> sh;
+  using SH = Shared3<T, NW>;
+  constexpr int JK = SH::JK;
+  __shared__ SH sh;
   const int tid = threadIdx.x;
   const int lane = tid & (WAVE - 1), wid = tid / WAVE;
   // per-group workspace: ACA factors and Gram matrices, Jacobi matrices of
@@ -305,10 +317,17 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
     cpx<double>* jmats = reinterpret_cast<cpx<double>*>(myws + ws_bytes<T>(cap, m, n));
     cpx<double>* G3 = jmats + 4 * 64 * 64;
     for (int w = tid; w < (nK + 31) / 32; w += NT) sh.usedk[w] = 0u;
+    // the block's stacked slice factors: U (m x S) then V (n x S)
+    int S = B.sres;
+    if (tid == 0) sh.alloc = pool_alloc(cursor, int64_t(m + n) * S, capacity);
     __syncthreads();
+    int64_t sbase = sh.alloc;
     int ell = 0, kcur = 0, status = 0, nres = 0;
     double norm2 = 0.0;
-    while (true) {
+    if (sbase < 0) status |= ST_DEFERRED;
+    cpx<T>* Us = pool + (sbase < 0 ? 0 : sbase);
+    cpx<T>* Vs = Us + int64_t(S) * m;
+    while (sbase >= 0) {
       for (int d = tid; d < ell; d += NT) sh.fk[d] = pool[sh.term[d].fiber + kcur];
       __syncthreads();
       const double2 sg = sigK[kcur];
@@ -326,27 +345,51 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       }
       const double nu = sqrt(fmax(grp_sum<NW>(nu2), 0.0));
       // ---- residual slice at k_cur: ACA, then recompression
-      ResidualEntry<T, ALLFAR, NW> ent{&tab, B.rb, B.cb, m, n, sg.x, sg.y, B.all_far != 0, ell, &sh,
-                                       pool, true};
+      ResidualEntry<T, ALLFAR, NW> ent{&tab, B.rb, B.cb, m, n, sg.x, sg.y, B.all_far != 0, nres, &sh,
+                                       Us, Vs, true};
       int ast = 0;
       const int k = aca_grp<NW, T>(ent, m, n, cap, aca_cap, tol_aca, nu, U, W, GU, GV, sh.aca, ast);
       if (ast & ST_CAPPED) status |= ST_CAPPED;
-      cpx<double>* A = k <= JK ? sh.mats : jmats;
+      cpx<double>* A = recompress_mats(k) <= recompress_mats(JK) ? sh.mats : jmats;
       const int t = recompress_grp<NW>(k, cap, GU, GV, tol_aca, nu, true, A, sh.rs);
-      if (tid == 0) sh.alloc = pool_alloc(cursor, int64_t(t) * (m + n), capacity);
-      __syncthreads();
-      const int64_t soff = sh.alloc;
-      if (soff < 0) { status |= ST_DEFERRED; break; }
-      apply_factors<T>(k, t, m, n, U, W, GU, GV, pool + soff, pool + soff + int64_t(t) * m, tid, NT);
+      // the candidate slice goes to the next free stacked columns
+      if (nres + t > SH::RES) { status |= ST_ESCALATE; break; }   // needs a larger group
+      if (nres + t > S) {
+        // move the stack to a reservation twice as large (the old one is left unused)
+        const int S2 = min(R3_MAX * 64, max(2 * S, ((nres + t + 15) / 16) * 16));
+        if (tid == 0) sh.alloc = pool_alloc(cursor, int64_t(m + n) * S2, capacity);
+        __syncthreads();
+        const int64_t nbase = sh.alloc;
+        if (nbase < 0) { status |= ST_DEFERRED; break; }
+        cpx<T>* nUs = pool + nbase;
+        cpx<T>* nVs = nUs + int64_t(S2) * m;
+        for (int64_t e = tid; e < int64_t(nres) * m; e += NT) nUs[e] = Us[e];
+        for (int64_t e = tid; e < int64_t(nres) * n; e += NT) nVs[e] = Vs[e];
+        if (tid == 0) {
+          for (int d = 0; d < ell; ++d) {
+            const int64_t c0 = (sh.term[d].slice - sbase) / m;
+            sh.term[d].slice = nbase + c0 * m;
+            sh.term[d].vslice = nbase + int64_t(S2) * m + c0 * n;
+          }
+        }
+        __syncthreads();
+        sbase = nbase;
+        S = S2;
+        Us = nUs;
+        Vs = nVs;
+      }
+      apply_factors<T>(k, t, m, n, U, W, GU, GV, Us + int64_t(nres) * m, Vs + int64_t(nres) * n, tid,
+                       NT);
       __syncthreads();
       Term3 cur;
-      cur.slice = soff;
+      cur.slice = sbase + int64_t(nres) * m;
+      cur.vslice = sbase + int64_t(S) * m + int64_t(nres) * n;
       cur.rank = t;
       cur.freq = kcur;
       // ---- pivot: largest modulus, first in row-major order on ties
       double best;
       int be;
-      lowrank_argmax<T, NW>(pool + soff, pool + soff + int64_t(t) * m, m, n, t, best, be);
+      lowrank_argmax<T, NW>(pool + cur.slice, pool + cur.vslice, m, n, t, best, be);
       if (!(best > PivFloor<T>::v)) break;   // zero pivot: rank stays ell
       const int ip = be / n, jp = be % n;
       const cpx<T> piv = slice_at<T>(cur, pool, m, n, ip, jp);
@@ -376,14 +419,13 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       // ---- eq. norm: <H_d, H_l> = tr((U_l^H U_d)(V_d^H V_l)), |H_l|^2 with d = l
       double nh2 = 0.0;
       {
-        const cpx<T>* Ul = pool + soff;
-        const cpx<T>* Vl = Ul + int64_t(t) * m;
+        const cpx<T>* Ul = pool + cur.slice;
+        const cpx<T>* Vl = pool + cur.vslice;
         cpx<T>* stage = reinterpret_cast<cpx<T>*>(sh.mats);
         for (int d = 0; d <= ell; ++d) {
           const Term3 td = d < ell ? sh.term[d] : cur;
-          const cpx<T>* Ud = pool + td.slice;
-          const cpx<T>* Vd = Ud + int64_t(td.rank) * m;
-          const cpx<double> h = lowrank_inner<T, NW>(Ul, Vl, t, Ud, Vd, td.rank, m, n, stage);
+          const cpx<double> h =
+              lowrank_inner<T, NW>(Ul, Vl, t, pool + td.slice, pool + td.vslice, td.rank, m, n, stage);
           if (d < ell) {
             if (tid == 0) sh.hin[d] = h;
           } else {
@@ -410,11 +452,8 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       if (tid == 0) sh.usedk[kcur >> 5] |= 1u << (kcur & 31);
       __syncthreads();
       if (sqrt(fmax(nh2 * nf2, 0.0)) <= tol * sqrt(fmax(norm2, 0.0))) break;  // drop term l
-      if (nres + t > Cls<NW>::RES) { status |= ST_ESCALATE; break; }         // needs a larger group
-      if (tid == 0) {
-        sh.term[ell] = cur;
-        sh.tbase[ell] = nres;
-      }
+      if (tid == 0) sh.term[ell] = cur;
+      for (int x = tid; x < t; x += NT) sh.cterm[nres + x] = (unsigned char)ell;
       nres += t;
       for (int d = tid; d <= ell; d += NT) {
         // <H_d, H_l> (d < l) and |H_l|^2
@@ -569,6 +608,7 @@ __global__ void __launch_bounds__(64) aca3d_near_kernel(
       if (lane == 0) {
         Term3 t;
         t.slice = soff;
+        t.vslice = -1;
         t.fiber = foff;
         t.rank = -1;
         t.freq = kcur;
@@ -657,7 +697,12 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
     const Cluster& A = ctx->clusters[B.row];
     const Cluster& C = ctx->clusters[B.col];
     bd[b] = {A.begin, A.end - A.begin, C.begin, C.end - C.begin, B.admissible ? 1 : 0,
-             B.all_far ? 1 : 0};
+             B.all_far ? 1 : 0, 0, 0};
+    if (B.admissible) {
+      // stacked slice columns: room for a few slices of full ACA rank to start with
+      const int r0 = std::min(std::min(bd[b].m, bd[b].n), 64);
+      bd[b].sres = std::min(R3_MAX * 64, ((ctx->tune.aca3d_stack_slices * r0 + 15) / 16) * 16);
+    }
     if (bd[b].m > ACA_MAXM) return fail(GCQ_ERR_UNSUPPORTED, "block too large");
     if (B.admissible) maxmn = std::max(maxmn, bd[b].m + bd[b].n);
     maxm = std::max(maxm, bd[b].m);
@@ -699,14 +744,14 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   // pool: dense near slices and factored far slices, bump-allocated
   size_t freeb = 0, totalb = 0;
   GCQ_HIP(hipMemGetInfo(&freeb, &totalb));
-  int64_t near_elems = 0, far_dims = 0;
+  int64_t near_elems = 0, far_stack = 0;
   for (int b = 0; b < nb; ++b)
-    if (bd[b].admissible) far_dims += bd[b].m + bd[b].n;
+    if (bd[b].admissible) far_stack += int64_t(bd[b].m + bd[b].n) * bd[b].sres;
     else near_elems += int64_t(bd[b].m) * bd[b].n;
-  // expected need: dense slices (near) and factored slices (far) of ~max_freq_rank/2
-  // terms each, plus one fiber per term
+  // expected need: dense slices (near) of ~max_freq_rank/2 terms each, the far
+  // blocks' stack reservations, plus one fiber per term
   const int64_t rexp = std::max(8, int(max_freq_rank) / 2 + 4);
-  int64_t want = near_elems * rexp + far_dims * 16 * rexp + int64_t(nb) * rexp * nK;
+  int64_t want = near_elems * rexp + far_stack + int64_t(nb) * rexp * nK;
   int64_t capacity = std::min<int64_t>(want, int64_t(double(freeb) * 0.5) / csz);
   F.slices.release();
   GCQ_TRY(F.slices.ensure(size_t(capacity) * csz + 256));
@@ -922,6 +967,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   F.tfreq.clear();
   F.trank.clear();
   F.toff.clear();
+  F.tvoff.clear();
   std::vector<int64_t> foff;
   int nt = 0;
   int ncap = 0;
@@ -934,6 +980,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
       F.tfreq.push_back(t.freq);
       F.trank.push_back(t.rank);
       F.toff.push_back(t.slice);
+      F.tvoff.push_back(t.vslice);
       foff.push_back(t.fiber);
       store += (t.rank < 0 ? int64_t(bd[b].m) * bd[b].n : int64_t(t.rank) * (bd[b].m + bd[b].n)) + nK;
       if (t.rank >= 0) slice_rank_sum += t.rank;
@@ -946,6 +993,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   GCQ_TRY(upload(F.d_bterm, F.bterm, ctx->stream));
   GCQ_TRY(upload(F.d_trank, F.trank, ctx->stream));
   GCQ_TRY(upload(F.d_toff, F.toff, ctx->stream));
+  GCQ_TRY(upload(F.d_tvoff, F.tvoff, ctx->stream));
   GCQ_TRY(upload(F.d_tfoff, F.tfoff, ctx->stream));
   {
     // product tables: stacked far columns and the block order of the product
@@ -962,7 +1010,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
         }
         for (int c = 0; c < F.trank[ti]; ++c) {
           cols.push_back(F.toff[ti] + int64_t(c) * bd[b].m);                                    // Ubar col
-          cols.push_back(F.toff[ti] + int64_t(F.trank[ti]) * bd[b].m + int64_t(c) * bd[b].n);   // Vbar col
+          cols.push_back(F.tvoff[ti] + int64_t(c) * bd[b].n);                                   // Vbar col
           cols.push_back(F.tfoff[ti]);
           work[b] += bd[b].m + bd[b].n;
         }
@@ -1046,12 +1094,14 @@ extern "C" GCQ_API int gcq_get_aca3d_block(gcq_context* ctx, int32_t block, int3
         std::memcpy(out, buf.data(), sizeof(gcq_c128) * m * n);
       } else {
         const int t = F.trank[ti];
-        GCQ_TRY(fetch(F.toff[ti], int64_t(t) * (m + n), buf));
+        std::vector<std::complex<double>> vbuf;
+        GCQ_TRY(fetch(F.toff[ti], int64_t(t) * m, buf));
+        GCQ_TRY(fetch(F.tvoff[ti], int64_t(t) * n, vbuf));
         for (int j = 0; j < n; ++j)
           for (int i = 0; i < m; ++i) {
             std::complex<double> acc = 0;
             for (int c = 0; c < t; ++c)
-              acc += buf[int64_t(c) * m + i] * std::conj(buf[int64_t(t) * m + int64_t(c) * n + j]);
+              acc += buf[int64_t(c) * m + i] * std::conj(vbuf[int64_t(c) * n + j]);
             out[int64_t(j) * m + i] = {acc.real(), acc.imag()};
           }
       }

@@ -383,4 +383,85 @@ __device__ __forceinline__ cpx<T> entry(const Tab& t, int pi, int pj, double sr,
   return far_entry<T>(t, c[pi], c[n + pi], c[2 * n + pi], pj, T(sr), T(si));
 }
 
+// Part p of P of an entry: the far tier's quadrature points a = p, p + P, ...
+// (the lanes p = 0..P-1 of an aligned group add their parts); a self or
+// near-tier entry is evaluated whole by part 0.
+template <typename T>
+__device__ __forceinline__ cpx<T> far_entry_part(const Tab& t, T xi, T yi, T zi, int pj, T sr, T si,
+                                                 int p, int P) {
+  const T* q = FarData<T>::q(t);
+  const int n = t.n;
+  cpx<T> acc = {T(0), T(0)};
+  for (int a = p; a < NQ_FAR; a += P) {
+    T dx = xi - q[(a)*n + pj];
+    T dy = yi - q[(7 + a) * n + pj];
+    T dz = zi - q[(14 + a) * n + pj];
+    T w = q[(21 + a) * n + pj];
+    T r = sqrt(dx * dx + dy * dy + dz * dz);
+    cpx<T> g = green(r, sr, si);
+    acc.re += w * g.re;
+    acc.im += w * g.im;
+  }
+  return acc;
+}
+template <>
+__device__ __forceinline__ cpx<float> far_entry_part<float>(const Tab& t, float xi, float yi, float zi,
+                                                            int pj, float sr, float si, int p, int P) {
+  const float* q = t.q32;
+  const int n = t.n;
+  const float a2 = -sr * 1.44269504088896340736f;   // -sr log2(e)
+  const float rv = si * 0.159154943091895335769f;   // si / (2 pi)
+  float ar = 0.f, ai = 0.f;
+  for (int a = p; a < NQ_FAR; a += P) {
+    const float dx = xi - q[(a)*n + pj];
+    const float dy = yi - q[(7 + a) * n + pj];
+    const float dz = zi - q[(14 + a) * n + pj];
+    const float w = q[(21 + a) * n + pj];
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float e = __builtin_amdgcn_exp2f(a2 * r) * (ri * w);
+    float rev = rv * r;
+    rev -= rintf(rev);
+    ar += e * __builtin_amdgcn_cosf(rev);
+    ai -= e * __builtin_amdgcn_sinf(rev);
+  }
+  return {ar, ai};
+}
+
+template <typename T, bool ALLFAR = false>
+__device__ __forceinline__ cpx<T> entry_part(const Tab& t, int pi, int pj, double sr, double si,
+                                             bool all_far, int p, int P) {
+  if (P == 1) return entry<T, ALLFAR>(t, pi, pj, sr, si, all_far);
+  if (!ALLFAR && !all_far) {
+    if (pi == pj || is_near(t, pi, pj)) {
+      if (p != 0) return {T(0), T(0)};
+      const cpx<double> e = pi == pj ? self_entry(t, pi, sr, si) : near_entry(t, pi, pj, sr, si);
+      return {T(e.re), T(e.im)};
+    }
+  }
+  const T* c = FarData<T>::c(t);
+  const int n = t.n;
+  return far_entry_part<T>(t, c[pi], c[n + pi], c[2 * n + pi], pj, T(sr), T(si), p, P);
+}
+
+// lanes per entry when a row of len entries is spread over nt threads: the
+// largest power of two <= 8 that still gives every entry its own lanes
+__device__ __forceinline__ int split_lanes(int nt, int len) {
+  int P = 1;
+  while (P < 8 && nt / (2 * P) >= len) P *= 2;
+  return P;
+}
+
+// sum over the aligned group of P lanes (P a power of two <= 64); every lane of
+// the group receives it
+template <typename T>
+__device__ __forceinline__ cpx<T> lanes_sum(cpx<T> v, int P) {
+  for (int o = 1; o < P; o <<= 1) {
+    v.re += __shfl_xor(v.re, o, WAVE);
+    v.im += __shfl_xor(v.im, o, WAVE);
+  }
+  return v;
+}
+
 }  // namespace gcq

@@ -223,6 +223,8 @@ GCQ_API int gcq_set_tuning(gcq_context* ctx, const gcq_tuning* tuning) {
     if (w != 1 && w != 2 && w != 4 && w != 8)
       return fail(GCQ_ERR_ARG, "aca3d_waves[%d] = %d is not 1, 2, 4 or 8", c, w);
   }
+  if (tuning->aca3d_stack_slices < 1 || tuning->aca3d_stack_slices > 64)
+    return fail(GCQ_ERR_ARG, "aca3d_stack_slices = %d is not in 1..64", tuning->aca3d_stack_slices);
   ctx->tune = *tuning;
   return GCQ_OK;
 }

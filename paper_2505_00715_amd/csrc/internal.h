@@ -113,8 +113,8 @@ struct Faces3D {
   // per term: frequency position, slice rank (far) or -1 (near), offset of the
   // slice data (complex elements), offset of the fiber (complex elements)
   std::vector<int> tfreq, trank;
-  std::vector<int64_t> toff, tfoff;
-  DevBuf d_brank, d_bterm, d_trank, d_toff, d_tfoff;
+  std::vector<int64_t> toff, tvoff, tfoff;   // slice (dense or Ubar), Vbar, fiber offsets
+  DevBuf d_brank, d_bterm, d_trank, d_toff, d_tvoff, d_tfoff;
   DevBuf slices;                 // far: U (m x r) then V (n x r); near: dense m x n
   DevBuf fibers;                 // per term: nK complex
   // product tables: per far block its stacked columns (U column offset, V
@@ -145,7 +145,7 @@ struct gcq_context {
   hipStream_t side[3] = {nullptr, nullptr, nullptr};
   hipEvent_t evfork = nullptr, evjoin[3] = {nullptr, nullptr, nullptr};
   // launch configuration
-  gcq_tuning tune = {{1, 2, 4, 8}};
+  gcq_tuning tune = {{4, 4, 4, 4}, 8};
 
   // mesh
   bool have_mesh = false;

@@ -51,14 +51,20 @@ struct RecompShared {
   int keep[64], order[64];
   int nkeep, tcut;
   // one round of the parallel Jacobi ordering: pair i rotates (jp[i], jq[i])
-  int jp[32], jq[32];
+  // when jact[i] is set
+  int jp[32], jq[32], jact[32];
   double jc[32], js[32], ja[32], jd[32], jtb[32];
   cpx<double> je[32];
+  double dmax;
 };
+
+// working memory of the recompression of k terms (complex doubles)
+__host__ __device__ inline int recompress_mats(int k) { return 3 * k * k; }
 
 // ---- ACA of an entry function --------------------------------------------------
 // Ent: prep_row(i) / prep_col(j) (group-collective, may be empty) and
-// operator()(i, j) -> cpx<T>.  Partial pivoting: row residual -> pivot column
+// part(i, j, p, P) -> cpx<T>, part p of P of the entry (i, j), the parts of
+// the P lanes adding up to the entry.  Partial pivoting: row residual -> pivot column
 // (largest modulus, lowest index on ties) -> column residual -> Frobenius norm
 // of the approximant updated with the cross terms (u_l^H u_k)(w_l^H w_k) ->
 // stop when |u_k||w_k| <= tol |S_k| (term kept) -> next row = largest |u_k|
@@ -90,16 +96,29 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
     __syncthreads();
     double best = -1.0;
     int bj = 0x7fffffff;
-    for (int j = tid; j < n; j += NT) {
-      cpx<T> a = ent(i, j);
-      for (int l = 0; l < k; ++l) {
-        cpx<T> p = cmul(sm.ubuf[l], W[int64_t(l) * n + j]);
-        a.re -= p.re;
-        a.im -= p.im;
+    {
+      // P lanes per entry when the row is short: they split the quadrature
+      // points and the residual sums
+      const int P = split_lanes(NT, n), E = NT / P, p = tid % P;
+      for (int j0 = 0; j0 < n; j0 += E) {
+        const int j = j0 + tid / P;
+        const bool ok = j < n;
+        cpx<T> a = {T(0), T(0)};
+        if (ok) {
+          a = ent.part(i, j, p, P);
+          for (int l = p; l < k; l += P) {
+            cpx<T> q = cmul(sm.ubuf[l], W[int64_t(l) * n + j]);
+            a.re -= q.re;
+            a.im -= q.im;
+          }
+        }
+        a = lanes_sum(a, P);
+        if (ok && p == 0) {
+          W[int64_t(k) * n + j] = a;
+          double v = mag2(a);
+          if (v > best) { best = v; bj = j; }
+        }
       }
-      W[int64_t(k) * n + j] = a;
-      double v = mag2(a);
-      if (v > best) { best = v; bj = j; }
     }
     if (tid == 0) sm.used[i >> 5] |= 1u << (i & 31);
     ++nused;
@@ -134,18 +153,29 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
     double nu2 = 0.0;
     double bestu = -1.0;
     int bi = 0x7fffffff;
-    for (int r = tid; r < m; r += NT) {
-      cpx<T> a = ent(r, jstar);
-      for (int l = 0; l < k; ++l) {
-        cpx<T> p = cmul(sm.ubuf[l], U[int64_t(l) * m + r]);
-        a.re -= p.re;
-        a.im -= p.im;
-      }
-      U[int64_t(k) * m + r] = a;
-      nu2 += double(a.re) * double(a.re) + double(a.im) * double(a.im);
-      if (!((sm.used[r >> 5] >> (r & 31)) & 1u)) {
-        double v = mag2(a);
-        if (v > bestu) { bestu = v; bi = r; }
+    {
+      const int P = split_lanes(NT, m), E = NT / P, p = tid % P;
+      for (int r0 = 0; r0 < m; r0 += E) {
+        const int r = r0 + tid / P;
+        const bool ok = r < m;
+        cpx<T> a = {T(0), T(0)};
+        if (ok) {
+          a = ent.part(r, jstar, p, P);
+          for (int l = p; l < k; l += P) {
+            cpx<T> q = cmul(sm.ubuf[l], U[int64_t(l) * m + r]);
+            a.re -= q.re;
+            a.im -= q.im;
+          }
+        }
+        a = lanes_sum(a, P);
+        if (ok && p == 0) {
+          U[int64_t(k) * m + r] = a;
+          nu2 += double(a.re) * double(a.re) + double(a.im) * double(a.im);
+          if (!((sm.used[r >> 5] >> (r & 31)) & 1u)) {
+            double v = mag2(a);
+            if (v > bestu) { bestu = v; bi = r; }
+          }
+        }
       }
     }
     __syncthreads();
@@ -217,7 +247,9 @@ __device__ inline int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, do
 // round-robin (tournament) ordering: every round rotates k/2 disjoint index
 // pairs at once, so a sweep is k - 1 parallel rounds instead of k (k - 1) / 2
 // sequential rotations.  Rotations of one round commute (disjoint pairs), so the
-// result equals the cyclic sweep in that pair order.
+// result equals the cyclic sweep in that pair order.  A round is two phases:
+// the rotation parameters, then G^H A G by 2 x 2 blocks (rows of pair i,
+// columns of pair j) together with Q G.
 template <int NW>
 __device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompShared& rs) {
   constexpr int NT = NW * WAVE;
@@ -244,6 +276,7 @@ __device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompS
         if (p > q) { int t = p; p = q; q = t; }
         double c = 1.0, sv = 0.0, a = 0.0, d = 0.0, tb = 0.0;
         cpx<double> e = {1.0, 0.0};
+        int act = 0;
         if (q < k) {
           const cpx<double> b = A[p * k + q];
           a = A[p * k + p].re;
@@ -256,12 +289,12 @@ __device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompS
             sv = t * c;
             e = {b.re / bb, b.im / bb};
             tb = t * bb;
-          } else {
-            q = k;   // nothing to rotate
+            act = 1;
           }
         }
         rs.jp[tid] = p;
         rs.jq[tid] = q;
+        rs.jact[tid] = act;
         rs.jc[tid] = c;
         rs.js[tid] = sv;
         rs.je[tid] = e;
@@ -270,43 +303,64 @@ __device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompS
         rs.jtb[tid] = tb;
       }
       __syncthreads();
-      // columns p, q of A and Q, every row
-      for (int x = tid; x < k * np; x += NT) {
-        const int r = x / np, i = x % np;
-        const int p = rs.jp[i], q = rs.jq[i];
-        if (q >= k) continue;
-        const double c = rs.jc[i], sv = rs.js[i];
-        const cpx<double> ec = {rs.je[i].re, -rs.je[i].im};
-        cpx<double> u = A[r * k + p], v = A[r * k + q];
-        cpx<double> ev = cmul(ec, v);
-        A[r * k + p] = {c * u.re - sv * ev.re, c * u.im - sv * ev.im};
-        A[r * k + q] = {sv * u.re + c * ev.re, sv * u.im + c * ev.im};
-        u = Q[r * k + p];
-        v = Q[r * k + q];
-        ev = cmul(ec, v);
-        Q[r * k + p] = {c * u.re - sv * ev.re, c * u.im - sv * ev.im};
-        Q[r * k + q] = {sv * u.re + c * ev.re, sv * u.im + c * ev.im};
-      }
-      __syncthreads();
-      // rows p, q of A, every column
-      for (int x = tid; x < k * np; x += NT) {
-        const int r = x / np, i = x % np;
-        const int p = rs.jp[i], q = rs.jq[i];
-        if (q >= k) continue;
-        const double c = rs.jc[i], sv = rs.js[i];
-        const cpx<double> e = rs.je[i];
-        cpx<double> u = A[p * k + r], v = A[q * k + r];
-        cpx<double> ev = cmul(e, v);
-        A[p * k + r] = {c * u.re - sv * ev.re, c * u.im - sv * ev.im};
-        A[q * k + r] = {sv * u.re + c * ev.re, sv * u.im + c * ev.im};
-      }
-      __syncthreads();
-      if (tid < np && rs.jq[tid] < k) {
-        const int p = rs.jp[tid], q = rs.jq[tid];
-        A[p * k + q] = {0.0, 0.0};
-        A[q * k + p] = {0.0, 0.0};
-        A[p * k + p] = {rs.ja[tid] - rs.jtb[tid], 0.0};
-        A[q * k + q] = {rs.jd[tid] + rs.jtb[tid], 0.0};
+      for (int x = tid; x < np * np + k * np; x += NT) {
+        if (x < np * np) {
+          // block (rows of pair i, columns of pair j) of G^H A G
+          const int i = x / np, j = x % np;
+          const int pi = rs.jp[i], qi = rs.jq[i], pj = rs.jp[j], qj = rs.jq[j];
+          const bool ai = rs.jact[i] != 0, aj = rs.jact[j] != 0;
+          if (!ai && !aj) continue;
+          if (i == j) {   // rotated pair: its 2 x 2 block becomes diagonal
+            A[pi * k + qi] = {0.0, 0.0};
+            A[qi * k + pi] = {0.0, 0.0};
+            A[pi * k + pi] = {rs.ja[i] - rs.jtb[i], 0.0};
+            A[qi * k + qi] = {rs.jd[i] + rs.jtb[i], 0.0};
+            continue;
+          }
+          const bool qiv = qi < k, qjv = qj < k;
+          cpx<double> app = A[pi * k + pj];
+          cpx<double> apq = qjv ? A[pi * k + qj] : cpx<double>{0.0, 0.0};
+          cpx<double> aqp = qiv ? A[qi * k + pj] : cpx<double>{0.0, 0.0};
+          cpx<double> aqq = qiv && qjv ? A[qi * k + qj] : cpx<double>{0.0, 0.0};
+          if (aj) {   // columns: [u, v] -> [c u - s conj(e) v, s u + c conj(e) v]
+            const double c = rs.jc[j], sv = rs.js[j];
+            const cpx<double> ec = {rs.je[j].re, -rs.je[j].im};
+            cpx<double> ev = cmul(ec, apq);
+            const cpx<double> n0 = {c * app.re - sv * ev.re, c * app.im - sv * ev.im};
+            const cpx<double> n1 = {sv * app.re + c * ev.re, sv * app.im + c * ev.im};
+            ev = cmul(ec, aqq);
+            const cpx<double> n2 = {c * aqp.re - sv * ev.re, c * aqp.im - sv * ev.im};
+            const cpx<double> n3 = {sv * aqp.re + c * ev.re, sv * aqp.im + c * ev.im};
+            app = n0; apq = n1; aqp = n2; aqq = n3;
+          }
+          if (ai) {   // rows: [u; v] -> [c u - s e v; s u + c e v]
+            const double c = rs.jc[i], sv = rs.js[i];
+            const cpx<double> e = rs.je[i];
+            cpx<double> ev = cmul(e, aqp);
+            const cpx<double> n0 = {c * app.re - sv * ev.re, c * app.im - sv * ev.im};
+            const cpx<double> n2 = {sv * app.re + c * ev.re, sv * app.im + c * ev.im};
+            ev = cmul(e, aqq);
+            const cpx<double> n1 = {c * apq.re - sv * ev.re, c * apq.im - sv * ev.im};
+            const cpx<double> n3 = {sv * apq.re + c * ev.re, sv * apq.im + c * ev.im};
+            app = n0; apq = n1; aqp = n2; aqq = n3;
+          }
+          A[pi * k + pj] = app;
+          if (qjv) A[pi * k + qj] = apq;
+          if (qiv) A[qi * k + pj] = aqp;
+          if (qiv && qjv) A[qi * k + qj] = aqq;
+        } else {
+          // Q G: row r, columns of pair j
+          const int y = x - np * np;
+          const int r = y / np, j = y % np;
+          if (!rs.jact[j]) continue;
+          const int p = rs.jp[j], q = rs.jq[j];
+          const double c = rs.jc[j], sv = rs.js[j];
+          const cpx<double> ec = {rs.je[j].re, -rs.je[j].im};
+          const cpx<double> u = Q[r * k + p], v = Q[r * k + q];
+          const cpx<double> ev = cmul(ec, v);
+          Q[r * k + p] = {c * u.re - sv * ev.re, c * u.im - sv * ev.im};
+          Q[r * k + q] = {sv * u.re + c * ev.re, sv * u.im + c * ev.im};
+        }
       }
       __syncthreads();
     }
@@ -315,11 +369,17 @@ __device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompS
 }
 
 // ---- recompression of k ACA terms ------------------------------------------------
-// GU, GV: Gram matrices (leading dimension cap).  mats: 4 k^2 doubles-complex of
-// working memory (LDS or global).  Keeps the smallest t with
-// sqrt(sum_{i >= t} s_i^2) <= tol max(sqrt(sum s_i^2), nu) and writes the coefficients
-// CU = Q L^{1/2} Z_t and CV = Q L^{-1/2} Z_t (k x t, leading dimension t) over GU
-// and GV.  Without recompression CU = CV = I, t = k.  Returns t.
+// GU, GV: Gram matrices (leading dimension cap).  mats: recompress_mats(k)
+// complex doubles of working memory (LDS or global).
+//   1. G_V = R^H R by Cholesky with diagonal pivoting (rows of R in pivot
+//      order; a remaining diagonal below 1e-14 of the largest ends it at rank
+//      r): R plays the role of the triangular factor of V = Q_V R.
+//   2. B = R G_U R^H = Z S^2 Z^H (Jacobi), the core M = R_U R^H having B = M^H M.
+//   3. Keep the smallest t with sqrt(sum_{i >= t} s_i^2) <= tol max(sqrt(sum s_i^2), nu):
+//      Ubar = U CU, CU = R^H Z_t;  Vbar = V CV, CV = R^+ Z_t, R^+ the right
+//      inverse of R supported on the pivot rows (triangular solve).
+// CU and CV (k x t, leading dimension t) are written over GU and GV.  Without
+// recompression CU = CV = I, t = k.  Returns t.
 template <int NW>
 __device__ inline int recompress_grp(int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol,
                                      double nu, bool do_recompress, cpx<double>* mats,
@@ -335,82 +395,116 @@ __device__ inline int recompress_grp(int k, int cap, cpx<double>* GU, cpx<double
     __syncthreads();
     return k;
   }
-  cpx<double>* A = mats;
-  cpx<double>* Q = A + k * k;
-  cpx<double>* B = Q + k * k;
-  cpx<double>* Z = B + k * k;
-  for (int r = tid; r < k * k; r += NT) A[r] = GV[(r / k) * cap + (r % k)];
+  cpx<double>* S = mats;           // k x k Schur complement of G_V, then R (rows in pivot order)
+  cpx<double>* B = S + k * k;      // r x r
+  cpx<double>* Z = B + k * k;      // r x r
+  cpx<double>* R = Z;              // rows of R are built in Z first (B, Z are free until step 2)
+  for (int e = tid; e < k * k; e += NT) {
+    S[e] = GV[(e / k) * cap + (e % k)];
+    R[e] = {0.0, 0.0};
+  }
+  if (tid < k) rs.keep[tid] = 0;   // eliminated flags
   __syncthreads();
-  jacobi_grp<NW>(A, Q, k, rs);
-  if (tid < k) rs.lam[tid] = A[tid * k + tid].re;
-  __syncthreads();
-  double lmax = 0.0;
-  for (int a = 0; a < k; ++a) lmax = fmax(lmax, rs.lam[a]);
   if (tid == 0) {
-    int c = 0;
-    for (int a = 0; a < k; ++a)
-      if (rs.lam[a] > 1e-14 * lmax && rs.lam[a] > 0.0) rs.keep[c++] = a;
-    rs.nkeep = c;
+    double d0 = 0.0;
+    for (int a = 0; a < k; ++a) d0 = fmax(d0, S[a * k + a].re);
+    rs.dmax = d0;
   }
   __syncthreads();
-  const int kk = rs.nkeep;
-  if (kk == 0) return 0;
-  // T1 = GU Q_S (k x kk) into Z, then B = L^1/2 Q_S^H T1 L^1/2
-  for (int e = tid; e < k * kk; e += NT) {
-    const int x = e / kk, b = e % kk;
-    const int qb = rs.keep[b];
+  const double dlim = 1e-14 * rs.dmax;
+  int r = 0;
+  for (; r < k; ++r) {
+    // pivot: largest remaining diagonal (lowest index on ties)
+    if (tid == 0) {
+      int p = -1;
+      double best = 0.0;
+      for (int a = 0; a < k; ++a)
+        if (!rs.keep[a] && S[a * k + a].re > best) { best = S[a * k + a].re; p = a; }
+      if (p >= 0 && best > dlim && best > 0.0) {
+        rs.nkeep = p;
+        rs.keep[p] = 1;
+        rs.order[r] = p;   // pivot of row r
+      } else {
+        rs.nkeep = -1;
+      }
+    }
+    __syncthreads();
+    const int p = rs.nkeep;
+    if (p < 0) break;
+    const double piv = sqrt(S[p * k + p].re);
+    // R[r][b] = S[p][b] / piv over remaining b (R[r][p] = piv)
+    for (int b2 = tid; b2 < k; b2 += NT) {
+      if (rs.keep[b2] && b2 != p) continue;
+      const cpx<double> v = S[p * k + b2];
+      R[r * k + b2] = b2 == p ? cpx<double>{piv, 0.0} : cpx<double>{v.re / piv, v.im / piv};
+    }
+    __syncthreads();
+    // S[a][b] -= conj(R[r][a]) R[r][b] over remaining a, b
+    for (int e = tid; e < k * k; e += NT) {
+      const int a = e / k, b2 = e % k;
+      if (rs.keep[a] || rs.keep[b2]) continue;
+      const cpx<double> x = R[r * k + a], y = R[r * k + b2];
+      S[e].re -= x.re * y.re + x.im * y.im;
+      S[e].im -= x.re * y.im - x.im * y.re;
+    }
+    __syncthreads();
+  }
+  if (r == 0) return 0;
+  // keep R (r x k) in S, then B = R G_U R^H: T1 = G_U R^H (k x r) into Z first
+  for (int e = tid; e < r * k; e += NT) S[e] = R[e];
+  __syncthreads();
+  for (int e = tid; e < k * r; e += NT) {
+    const int x = e / r, b2 = e % r;
     cpx<double> acc = {0, 0};
     for (int y = 0; y < k; ++y) {
-      cpx<double> p = cmul(GU[x * cap + y], Q[y * k + qb]);
-      acc.re += p.re;
-      acc.im += p.im;
+      const cpx<double> g = GU[x * cap + y], rr = S[b2 * k + y];
+      acc.re += g.re * rr.re + g.im * rr.im;   // g conj(rr)
+      acc.im += g.im * rr.re - g.re * rr.im;
     }
-    Z[x * kk + b] = acc;
+    Z[e] = acc;
   }
   __syncthreads();
-  for (int e = tid; e < kk * kk; e += NT) {
-    const int a = e / kk, b = e % kk;
-    const int qa = rs.keep[a];
+  for (int e = tid; e < r * r; e += NT) {
+    const int a = e / r, b2 = e % r;
     cpx<double> acc = {0, 0};
     for (int x = 0; x < k; ++x) {
-      cpx<double> p = cmulc(Q[x * k + qa], Z[x * kk + b]);
+      const cpx<double> p = cmul(S[a * k + x], Z[x * r + b2]);
       acc.re += p.re;
       acc.im += p.im;
     }
-    const double sc = sqrt(rs.lam[qa] * rs.lam[rs.keep[b]]);
-    B[a * kk + b] = {acc.re * sc, acc.im * sc};
+    B[e] = acc;
   }
   __syncthreads();
-  for (int e = tid; e < kk * kk; e += NT) {  // Hermitian part
-    const int a = e / kk, b = e % kk;
-    if (a < b) {
-      cpx<double> x = B[a * kk + b], y = B[b * kk + a];
+  for (int e = tid; e < r * r; e += NT) {  // Hermitian part
+    const int a = e / r, b2 = e % r;
+    if (a < b2) {
+      cpx<double> x = B[a * r + b2], y = B[b2 * r + a];
       cpx<double> h = {0.5 * (x.re + y.re), 0.5 * (x.im - y.im)};
-      B[a * kk + b] = h;
-      B[b * kk + a] = {h.re, -h.im};
-    } else if (a == b) {
-      B[a * kk + a].im = 0.0;
+      B[a * r + b2] = h;
+      B[b2 * r + a] = {h.re, -h.im};
+    } else if (a == b2) {
+      B[a * r + a].im = 0.0;
     }
   }
   __syncthreads();
-  jacobi_grp<NW>(B, Z, kk, rs);
-  if (tid < kk) rs.sg[tid] = fmax(B[tid * kk + tid].re, 0.0);
+  jacobi_grp<NW>(B, Z, r, rs);
+  if (tid < r) rs.sg[tid] = fmax(B[tid * r + tid].re, 0.0);
   __syncthreads();
-  if (tid < kk) {  // descending order, ties by index
+  if (tid < r) {  // descending order, ties by index
     int pos = 0;
-    for (int b = 0; b < kk; ++b)
-      if (rs.sg[b] > rs.sg[tid] || (rs.sg[b] == rs.sg[tid] && b < tid)) ++pos;
-    rs.order[pos] = tid;
+    for (int b2 = 0; b2 < r; ++b2)
+      if (rs.sg[b2] > rs.sg[tid] || (rs.sg[b2] == rs.sg[tid] && b2 < tid)) ++pos;
+    rs.keep[pos] = tid;   // (the elimination flags are no longer needed)
   }
   __syncthreads();
   if (tid == 0) {
     double total = 0.0;
-    for (int a = 0; a < kk; ++a) total += rs.sg[a];
+    for (int a = 0; a < r; ++a) total += rs.sg[a];
     double tail = 0.0;
-    int t = kk;
+    int t = r;
     const double ref = fmax(sqrt(total), nu);
-    for (int a = kk - 1; a >= 0; --a) {
-      tail += rs.sg[rs.order[a]];
+    for (int a = r - 1; a >= 0; --a) {
+      tail += rs.sg[rs.keep[a]];
       if (sqrt(tail) <= tol * ref) t = a;
       else break;
     }
@@ -418,26 +512,33 @@ __device__ inline int recompress_grp(int k, int cap, cpx<double>* GU, cpx<double
   }
   __syncthreads();
   const int t = rs.tcut;
+  // CU = R^H Z_t (k x t) over GU
   for (int e = tid; e < k * t; e += NT) {
     const int x = e / t, c = e % t;
-    const int zc = rs.order[c];
-    cpx<double> au = {0, 0}, av = {0, 0};
-    for (int a = 0; a < kk; ++a) {
-      const int qa = rs.keep[a];
-      cpx<double> p = cmul(Q[x * k + qa], Z[a * kk + zc]);
-      const double sl = sqrt(rs.lam[qa]);
-      au.re += p.re * sl;
-      au.im += p.im * sl;
-      av.re += p.re / sl;
-      av.im += p.im / sl;
+    const int zc = rs.keep[c];
+    cpx<double> acc = {0, 0};
+    for (int a = 0; a < r; ++a) {
+      const cpx<double> p = cmulc(S[a * k + x], Z[a * r + zc]);   // conj(R[a][x]) Z[a][zc]
+      acc.re += p.re;
+      acc.im += p.im;
     }
-    A[e] = au;  // A and B are free now
-    B[e] = av;
+    GU[e] = acc;
   }
+  // CV: rows order[j] of R_P^{-1} Z_t, R_P[i][j] = R[i][order[j]] upper triangular
+  for (int e = tid; e < k * t; e += NT) GV[e] = {0.0, 0.0};
   __syncthreads();
-  for (int e = tid; e < k * t; e += NT) {
-    GU[e] = A[e];
-    GV[e] = B[e];
+  for (int c = tid; c < t; c += NT) {
+    const int zc = rs.keep[c];
+    for (int i = r - 1; i >= 0; --i) {
+      cpx<double> acc = Z[i * r + zc];
+      for (int j = i + 1; j < r; ++j) {
+        const cpx<double> p = cmul(S[i * k + rs.order[j]], GV[rs.order[j] * t + c]);
+        acc.re -= p.re;
+        acc.im -= p.im;
+      }
+      const double dii = S[i * k + rs.order[i]].re;   // real positive pivot
+      GV[rs.order[i] * t + c] = {acc.re / dii, acc.im / dii};
+    }
   }
   __syncthreads();
   return t;

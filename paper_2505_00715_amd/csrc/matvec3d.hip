@@ -44,70 +44,6 @@ __global__ void zero3(cpx<T>* p, int64_t n) {
     p[e] = {T(0), T(0)};
 }
 
-// one wave per (block, column): the slices are re-read for every column
-template <typename T>
-__global__ void __launch_bounds__(64) perfreq_kernel(
-    const int* __restrict__ blk, int nblocks, const int* __restrict__ bterm,
-    const int* __restrict__ trank, const int64_t* __restrict__ toff,
-    const int64_t* __restrict__ tfoff, const cpx<T>* __restrict__ pool,
-    const int* __restrict__ colpos, int L, int n, const cpx<T>* __restrict__ Xp,
-    cpx<T>* __restrict__ Yp) {
-  __shared__ cpx<T> tv[64];
-  const int lane = threadIdx.x;
-  const int64_t total = int64_t(nblocks) * L;
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-    const int b = int(w % nblocks), k = int(w / nblocks);
-    const int rb = blk[5 * b], m = blk[5 * b + 1] - rb, cb = blk[5 * b + 2], nn = blk[5 * b + 3] - cb;
-    const int kp = colpos[k];
-    const cpx<T>* x = Xp + int64_t(k) * n + cb;
-    cpx<T>* y = Yp + int64_t(k) * n + rb;
-    for (int d = bterm[b]; d < bterm[b + 1]; ++d) {
-      const cpx<T> f = pool[tfoff[d] + kp];
-      const int t = trank[d];
-      const cpx<T>* S = pool + toff[d];
-      if (t < 0) {
-        for (int i = lane; i < m; i += WAVE) {
-          cpx<T> acc = {0, 0};
-          for (int j = 0; j < nn; ++j) {
-            cpx<T> p = cmul(S[int64_t(j) * m + i], x[j]);
-            acc.re += p.re;
-            acc.im += p.im;
-          }
-          cpx<T> v = cmul(f, acc);
-          atomicAdd(&y[i].re, v.re);
-          atomicAdd(&y[i].im, v.im);
-        }
-      } else {
-        const cpx<T>* V = S + int64_t(t) * m;
-        __syncthreads();
-        for (int c = 0; c < t; ++c) {
-          T sr = 0, si = 0;
-          for (int j = lane; j < nn; j += WAVE) {
-            cpx<T> p = cmulc(V[int64_t(c) * nn + j], x[j]);
-            sr += p.re;
-            si += p.im;
-          }
-          sr = wave_sum(sr);
-          si = wave_sum(si);
-          if (lane == 0) tv[c] = cmul(f, cpx<T>{sr, si});
-        }
-        __syncthreads();
-        for (int i = lane; i < m; i += WAVE) {
-          cpx<T> acc = {0, 0};
-          for (int c = 0; c < t; ++c) {
-            cpx<T> p = cmul(S[int64_t(c) * m + i], tv[c]);
-            acc.re += p.re;
-            acc.im += p.im;
-          }
-          atomicAdd(&y[i].re, acc.re);
-          atomicAdd(&y[i].im, acc.im);
-        }
-      }
-    }
-  }
-}
-
-
 // Xp[p][k] = X[k][perm[p]] (frequency fastest), conjugated for columns applied
 // through their conjugate partner; and the inverse for the result
 template <typename TI, typename TO>
@@ -306,8 +242,9 @@ template <typename T>
 __global__ void __launch_bounds__(64) wsum_kernel(
     const int* __restrict__ blk, int nblocks, const int* __restrict__ bterm,
     const int* __restrict__ trank, const int64_t* __restrict__ toff,
-    const int64_t* __restrict__ tfoff, const cpx<T>* __restrict__ pool,
-    const int* __restrict__ colpos, const int* __restrict__ conjf, int L, int n,
+    const int64_t* __restrict__ tvoff, const int64_t* __restrict__ tfoff,
+    const cpx<T>* __restrict__ pool, const int* __restrict__ colpos,
+    const int* __restrict__ conjf, int L, int n,
     const cpx<T>* __restrict__ X, cpx<T>* __restrict__ ybuf, cpx<T>* __restrict__ scratch,
     int64_t sstride) {
   __shared__ cpx<T> t1[64], t2[64];
@@ -353,7 +290,7 @@ __global__ void __launch_bounds__(64) wsum_kernel(
           atomicAdd(&ybuf[rb + i].im, s1.im - s2.im);
         }
       } else {
-        const cpx<T>* V = S + int64_t(t) * m;
+        const cpx<T>* V = pool + tvoff[d];
         for (int c = 0; c < t; ++c) {
           T r1 = 0, i1 = 0, r2 = 0, i2 = 0;
           for (int j = lane; j < nn; j += WAVE) {
@@ -444,7 +381,8 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
     hipLaunchKernelGGL(zero3<T>, dim3(64), dim3(256), 0, st, Yp, int64_t(n));
     hipLaunchKernelGGL(wsum_kernel<T>, dim3(wgrid), dim3(64), 0, st, ctx->d_blk.as<int>(), nb,
                        F.d_bterm.as<int>(), F.d_trank.as<int>(), F.d_toff.as<int64_t>(),
-                       F.d_tfoff.as<int64_t>(), F.slices.as<cpx<T>>(), d_colpos, d_conj, L, n, Xp,
+                       F.d_tvoff.as<int64_t>(), F.d_tfoff.as<int64_t>(), F.slices.as<cpx<T>>(),
+                       d_colpos, d_conj, L, n, Xp,
                        Yp, Yp + n, int64_t(2) * maxn);
     if (precision == GCQ_C128)
       hipLaunchKernelGGL((perm_out3<T, double>), dim3(64), dim3(256), 0, st, Yp, (cpx<double>*)Y,

@@ -88,9 +88,13 @@ def test_argument_and_state_errors():
 
 def test_tuning_roundtrip_and_rejection():
     ctx = g.Context(-1)
-    assert list(ctx.get_tuning().aca3d_waves) == [1, 2, 4, 8]
-    ctx.set_tuning(aca3d_waves=(1, 1, 2, 4))
+    assert list(ctx.get_tuning().aca3d_waves) == [4, 4, 4, 4]
+    assert ctx.get_tuning().aca3d_stack_slices == 8
+    ctx.set_tuning(aca3d_waves=(1, 1, 2, 4), aca3d_stack_slices=2)
     assert list(ctx.get_tuning().aca3d_waves) == [1, 1, 2, 4]
     with pytest.raises(g.GcqError):
         ctx.set_tuning(aca3d_waves=(1, 3, 4, 8))
+    with pytest.raises(g.GcqError):
+        ctx.set_tuning(aca3d_stack_slices=0)
     assert list(ctx.get_tuning().aca3d_waves) == [1, 1, 2, 4]
+    assert ctx.get_tuning().aca3d_stack_slices == 2

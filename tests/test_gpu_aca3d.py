@@ -97,12 +97,14 @@ def test_products_without_conjugate_symmetry(setup):
     assert rel(Yg, Yt) <= 1e-4
 
 
-@pytest.mark.parametrize("waves", [(1, 1, 1, 1), (2, 2, 2, 2), (4, 4, 4, 4), (8, 8, 8, 8)])
-def test_aca3d_group_sizes(setup, waves):
-    """Every group size (waves per block) gives the oracle's 3D-ACA."""
+@pytest.mark.parametrize("waves,stack", [((1, 1, 1, 1), 8), ((2, 2, 2, 2), 8), ((4, 4, 4, 4), 1),
+                                         ((8, 8, 8, 8), 8), ((1, 2, 4, 8), 1)])
+def test_aca3d_group_sizes(setup, waves, stack):
+    """Every group size (waves per block) gives the oracle's 3D-ACA, also when
+    the stacked slice factors start from a one-slice reservation and move."""
     xyz, tri, s, P, T, B, rep, conj, K, kpos, b3 = setup
     ctx = make_ctx(xyz, tri, 1.0, s, 32, 1.0)
-    ctx.set_tuning(aca3d_waves=waves)
+    ctx.set_tuning(aca3d_waves=waves, aca3d_stack_slices=stack)
     assert list(ctx.get_tuning().aca3d_waves) == list(waves)
     ctx.aca3d(TOLA, TOLF, 40, g.C128)
     num = den = 0.0
