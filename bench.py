@@ -32,6 +32,37 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 # algorithmic operations per far-field quadrature point and frequency:
 # 3 sub + 3 fma (r^2) + sqrt + 2 mul + exp + sin + cos + rcp + 2 mul + 2 fma (accumulate)
 OPS_PER_QPOINT = 20
+# HBM traffic of the 3D-ACA admissible-block kernel from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE counters (calibrated against a copy kernel), valid for the sources
+# it was measured on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "aca3d_far_sphere20480_traffic.txt")
+KERNEL_SOURCES = ["aca3d.hip", "lowrank.h", "device_common.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2505_00715_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(config):
+    """Bytes per launch from the committed counter summary, or None when the
+    kernel sources changed since it was taken or it covers another workload."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_sha1") != kernel_source_hash() or kv.get("workload") != config:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -43,6 +74,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="first copy this many GiB device to device (a reference kernel of "
+                         "known traffic for hardware counter runs)")
     return ap.parse_args()
 
 
@@ -85,6 +119,15 @@ def main():
 
     cfg = configs.get(args.config)
     L = len(cfg["s"])
+    if args.calibrate_copy_gib > 0:
+        nbytes = int(args.calibrate_copy_gib * 2 ** 30)
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] reference copy: {nbytes} bytes read, {nbytes} bytes written",
+              file=sys.stderr, flush=True)
+        del src, dst
     ctx = g.Context(0)
     ctx.upload_mesh(cfg["xyz"], cfg["tri"], cfg["c"])
     ctx.set_frequencies(cfg["s"], True)
@@ -178,9 +221,17 @@ def main():
     # X read once, Y written once (complex64)
     mv_bytes = s3.storage_bytes + 2 * L * ctx.n * 8
     mv_gbps = mv_bytes / (mv_ms / 1e3) / 1e9
-    # ALU work of the ACA kernel: entry evaluations x 7 quadrature points
+    # ALU work of the per-frequency ACA kernel: entry evaluations x 7 quadrature points
     aca_ops = sa.entries * 7 * OPS_PER_QPOINT
     aca_tflops = aca_ops / (aca_kernel_ms / 1e3) / 1e12
+    # the dominant kernel: 3D-ACA of the admissible blocks; algorithmic work
+    # counted on the device (gcq_aca3d_stats.far_flops), time from HIP events
+    far_ms = float(np.median([r["a3"].far_ms for r in recs]))
+    far_tflops = s3.far_flops / (far_ms / 1e3) / 1e12
+    traffic = measured_traffic(args.config)
+    # compressed product on the matrix cores: one complex multiply-add (8 flops)
+    # per stored slice element and frequency column
+    mv_tflops = (s3.storage_bytes / 8) * L * 8 / (mv_ms / 1e3) / 1e12
 
     # accuracy of the compressed product on sampled rows against the oracle's
     # dense rows (float64)
@@ -224,11 +275,18 @@ def main():
         "aca3d": {"rank_mean": s3.rank_mean, "rank_max": s3.rank_max,
                   "compression_rate": s3.compression_rate, "storage_GB": s3.storage_bytes / 1e9},
         "plain": plain,
-        "roofline": {"bound": "alu", "kernel": "aca_kernel<float>", "achieved": aca_tflops,
-                     "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": aca_tflops / FP32_VALU_PEAK_TFLOPS, "traffic": None},
-        "roofline_matvec": {"bound": "hbm", "achieved": mv_gbps, "peak": HBM_PEAK_GBPS,
-                            "unit": "GB/s", "frac": mv_gbps / HBM_PEAK_GBPS},
+        "roofline": {"bound": "alu", "kernel": "aca3d_kernel<float, true, 4>",
+                     "achieved": far_tflops, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": far_tflops / FP32_VALU_PEAK_TFLOPS, "traffic": traffic,
+                     "launch_ms": far_ms, "flops_per_launch": s3.far_flops,
+                     "entries_per_launch": s3.far_entries},
+        "roofline_matvec": {"bound": "hbm", "kernel": "perfreq_mfma", "achieved": mv_gbps,
+                            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": mv_gbps / HBM_PEAK_GBPS,
+                            "mfma_tflops": mv_tflops, "mfma_peak_tflops": FP32_MFMA_PEAK_TFLOPS,
+                            "mfma_frac": mv_tflops / FP32_MFMA_PEAK_TFLOPS},
+        "roofline_aca_blocks": {"bound": "alu", "kernel": "aca_kernel<float, true>",
+                                "achieved": aca_tflops, "peak": FP32_VALU_PEAK_TFLOPS,
+                                "unit": "TFLOP/s", "frac": aca_tflops / FP32_VALU_PEAK_TFLOPS},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -140,6 +140,14 @@ typedef struct {
   int64_t storage_bytes;      /* slices + fibers                               */
   double compression_rate;    /* storage / dense storage of all |K| matrices  */
   double device_ms;
+  /* work of the admissible blocks' kernel, counted on the device: kernel
+   * entries evaluated (slice rows and columns, fibers), and the algorithmic
+   * floating-point operations of the method's steps (20 per far-field
+   * quadrature point, 8 per complex multiply-add of the residual corrections,
+   * pivot expansions, Gram and slice inner products, fibers) */
+  int64_t far_entries;
+  double far_flops;
+  double far_ms;              /* device time of the admissible blocks' kernels */
 } gcq_aca3d_stats;
 
 typedef struct {

@@ -41,7 +41,8 @@ class Aca3dStats(C.Structure):
     _fields_ = [("n_blocks", C.c_int32), ("rank_min", C.c_int32), ("rank_max", C.c_int32),
                 ("rank_mean", C.c_double), ("n_capped", C.c_int32),
                 ("slice_rank_sum", C.c_int64), ("storage_bytes", C.c_int64),
-                ("compression_rate", C.c_double), ("device_ms", C.c_double)]
+                ("compression_rate", C.c_double), ("device_ms", C.c_double),
+                ("far_entries", C.c_int64), ("far_flops", C.c_double), ("far_ms", C.c_double)]
 
 
 class SolveStats(C.Structure):

@@ -291,7 +291,8 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
     const double2* __restrict__ sigK, int nK, double tol_aca, double tol, int rmax, int aca_cap,
     unsigned char* __restrict__ ws, int64_t ws_stride, cpx<T>* __restrict__ pool,
     unsigned long long* __restrict__ cursor, int64_t capacity, Term3* __restrict__ terms,
-    int* __restrict__ brank, int* __restrict__ bstatus, int* __restrict__ counter) {
+    int* __restrict__ brank, int* __restrict__ bstatus, int* __restrict__ counter,
+    unsigned long long* __restrict__ work) {
   constexpr int NT = NW * WAVE;
   using SH = Shared3<T, NW>;
   constexpr int JK = SH::JK;
@@ -324,6 +325,8 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
     int64_t sbase = sh.alloc;
     int ell = 0, kcur = 0, status = 0, nres = 0;
     double norm2 = 0.0;
+    // algorithmic work of this block: entries and operations (see gcq_aca3d_stats)
+    double wentries = 0.0, wflops = 0.0;
     if (sbase < 0) status |= ST_DEFERRED;
     cpx<T>* Us = pool + (sbase < 0 ? 0 : sbase);
     cpx<T>* Vs = Us + int64_t(S) * m;
@@ -348,8 +351,15 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       ResidualEntry<T, ALLFAR, NW> ent{&tab, B.rb, B.cb, m, n, sg.x, sg.y, B.all_far != 0, nres, &sh,
                                        Us, Vs, true};
       int ast = 0;
-      const int k = aca_grp<NW, T>(ent, m, n, cap, aca_cap, tol_aca, nu, U, W, GU, GV, sh.aca, ast);
+      const int k = aca_grp<NW, true, T>(ent, m, n, cap, aca_cap, tol_aca, nu, U, W, GU, GV, sh.aca, ast);
       if (ast & ST_CAPPED) status |= ST_CAPPED;
+      {
+        // rows (length n) and columns (length m) with their residual sums
+        const double e = double(sh.aca.nrows) * n + double(k) * m;
+        wentries += e;
+        wflops += e * (7.0 * 20.0 + 8.0 * nres) + 8.0 * (m + n) * 0.5 * double(k) * (k - 1) +
+                  2.0 * 8.0 * (m + n) * 0.5 * double(k) * (k - 1);   // residual terms, Gram entries
+      }
       cpx<double>* A = recompress_mats(k) <= recompress_mats(JK) ? sh.mats : jmats;
       const int t = recompress_grp<NW>(k, cap, GU, GV, tol_aca, nu, true, A, sh.rs);
       // the candidate slice goes to the next free stacked columns
@@ -387,6 +397,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       cur.rank = t;
       cur.freq = kcur;
       // ---- pivot: largest modulus, first in row-major order on ties
+      wflops += 8.0 * (double(t) * (m + n) * k + double(m) * n * t);   // apply, expansion
       double best;
       int be;
       lowrank_argmax<T, NW>(pool + cur.slice, pool + cur.vslice, m, n, t, best, be);
@@ -400,6 +411,13 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       if (foff < 0) { status |= ST_DEFERRED; break; }
       cur.fiber = foff;
       // ---- fiber over K
+      wentries += nK;
+      wflops += double(nK) * (7.0 * 20.0 + 8.0 * ell);
+      {
+        double tt = double(t);
+        for (int d = 0; d < ell; ++d) tt += sh.term[d].rank;
+        wflops += 8.0 * double(t) * tt * (m + n) + 8.0 * double(nK) * ell;   // inner products
+      }
       const cpx<T> inv = cinv(piv);
       double nf2 = 0.0;
       for (int kk = tid; kk < nK; kk += NT) {
@@ -482,6 +500,10 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
     if (tid == 0) {
       brank[b] = ell;
       bstatus[b] = status;
+      if (!(status & (ST_DEFERRED | ST_ESCALATE))) {
+        atomicAdd(work, (unsigned long long)wentries);
+        atomicAdd(work + 1, (unsigned long long)wflops);
+      }
     }
     __syncthreads();
   }
@@ -764,6 +786,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   unsigned long long* d_cursor = ctx->scratchD.as<unsigned long long>();
   int* d_counter = reinterpret_cast<int*>(ctx->scratchD.as<unsigned char>() + 16);
   int* d_near_counter = d_counter + 8;
+  unsigned long long* d_work = reinterpret_cast<unsigned long long*>(ctx->scratchD.as<unsigned char>() + 96);
   Term3* d_terms = reinterpret_cast<Term3*>(ctx->scratchD.as<unsigned char>() + 128);
   int* d_rank = reinterpret_cast<int*>(d_terms + size_t(nb) * R3_MAX);
   int* d_stat = d_rank + nb;
@@ -785,6 +808,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   DevBuf tensor;
   const int64_t tensor_budget = std::max<int64_t>(int64_t(1) << 28,
                                                   std::min<int64_t>(int64_t(48) << 30, int64_t(double(freeb) * 0.25)));
+  hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, reinterpret_cast<int*>(d_work), 4);
   std::vector<int> opos(nb);
   for (int i = 0; i < nb; ++i) opos[order[i]] = i;
   std::vector<int> todo = order;
@@ -842,7 +866,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
               nw, lgrid[l], st, ctx->tab(), (const BlockDesc3*)ctx->scratchB.as<BlockDesc3>(),
               (const int*)(d_order + loff[l]), cnt, (const double2*)ctx->scratchC.as<double2>(), nK,
               tol_aca, tol, int(max_freq_rank), aca_cap, wsp, lstride[l], F.slices.as<cpx<double>>(),
-              d_cursor, capacity, d_terms, d_rank, d_stat, d_counter + l);
+              d_cursor, capacity, d_terms, d_rank, d_stat, d_counter + l, d_work);
         };
         if (af) go(std::true_type()); else go(std::false_type());
       } else {
@@ -851,7 +875,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
               nw, lgrid[l], st, ctx->tab(), (const BlockDesc3*)ctx->scratchB.as<BlockDesc3>(),
               (const int*)(d_order + loff[l]), cnt, (const double2*)ctx->scratchC.as<double2>(), nK,
               tol_aca, tol, int(max_freq_rank), aca_cap, wsp, lstride[l], F.slices.as<cpx<float>>(),
-              d_cursor, capacity, d_terms, d_rank, d_stat, d_counter + l);
+              d_cursor, capacity, d_terms, d_rank, d_stat, d_counter + l, d_work);
         };
         if (af) go(std::true_type()); else go(std::false_type());
       }
@@ -1017,6 +1041,11 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
       }
     }
     bcol[nb] = int32_t(cols.size() / 3);
+    // the product reads a far block's stacked columns as one m x R and one n x R matrix
+    for (int b = 0; b < nb; ++b)
+      for (int c = bcol[b] + 1; c < bcol[b + 1]; ++c)
+        if (cols[3 * c] != cols[3 * (c - 1)] + bd[b].m || cols[3 * c + 1] != cols[3 * (c - 1) + 1] + bd[b].n)
+          return fail(GCQ_ERR_STATE, "block %d: slice factors are not stacked", b);
     std::vector<int32_t> mo;
     for (int b = 0; b < nb; ++b)
       if (F.brank[b] > 0) mo.push_back(b);
@@ -1048,6 +1077,11 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
     stats->storage_bytes = F.storage_bytes;
     stats->compression_rate = double(F.storage_bytes) / double(F.dense_bytes);
     stats->device_ms = ms;
+    unsigned long long work[2] = {0, 0};
+    GCQ_HIP(hipMemcpy(work, d_work, sizeof(work), hipMemcpyDeviceToHost));
+    stats->far_entries = int64_t(work[0]);
+    stats->far_flops = double(work[1]);
+    stats->far_ms = ms_far;
   }
   return ncap > 0 ? GCQ_RANK_CAPPED : GCQ_OK;
 }

@@ -44,6 +44,7 @@ template <typename T>
 struct AcaShared {
   unsigned used[ACA_MAXM / 32];
   cpx<T> ubuf[64];
+  int nrows;   // rows evaluated by the last approximation
 };
 
 struct RecompShared {
@@ -75,7 +76,8 @@ __host__ __device__ inline int recompress_mats(int k) { return 3 * k * k; }
 // nu: absolute norm floor of the stopping test (0: relative to the block itself)
 // NW wave64s of the workgroup run the approximation together: rows and
 // columns are split over all threads, each Gram entry is summed by one wave.
-template <int NW, typename T, typename Ent>
+// SPLIT: rows shorter than the group spread each entry over several lanes.
+template <int NW, bool SPLIT, typename T, typename Ent>
 __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol, double nu,
                        cpx<T>* __restrict__ U, cpx<T>* __restrict__ W,
                        cpx<double>* __restrict__ GU, cpx<double>* __restrict__ GV,
@@ -96,7 +98,19 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
     __syncthreads();
     double best = -1.0;
     int bj = 0x7fffffff;
-    {
+    if constexpr (!SPLIT) {
+      for (int j = tid; j < n; j += NT) {
+        cpx<T> a = ent.part(i, j, 0, 1);
+        for (int l = 0; l < k; ++l) {
+          cpx<T> q = cmul(sm.ubuf[l], W[int64_t(l) * n + j]);
+          a.re -= q.re;
+          a.im -= q.im;
+        }
+        W[int64_t(k) * n + j] = a;
+        double v = mag2(a);
+        if (v > best) { best = v; bj = j; }
+      }
+    } else {
       // P lanes per entry when the row is short: they split the quadrature
       // points and the residual sums
       const int P = split_lanes(NT, n), E = NT / P, p = tid % P;
@@ -153,7 +167,22 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
     double nu2 = 0.0;
     double bestu = -1.0;
     int bi = 0x7fffffff;
-    {
+    if constexpr (!SPLIT) {
+      for (int r = tid; r < m; r += NT) {
+        cpx<T> a = ent.part(r, jstar, 0, 1);
+        for (int l = 0; l < k; ++l) {
+          cpx<T> q = cmul(sm.ubuf[l], U[int64_t(l) * m + r]);
+          a.re -= q.re;
+          a.im -= q.im;
+        }
+        U[int64_t(k) * m + r] = a;
+        nu2 += double(a.re) * double(a.re) + double(a.im) * double(a.im);
+        if (!((sm.used[r >> 5] >> (r & 31)) & 1u)) {
+          double v = mag2(a);
+          if (v > bestu) { bestu = v; bi = r; }
+        }
+      }
+    } else {
       const int P = split_lanes(NT, m), E = NT / P, p = tid % P;
       for (int r0 = 0; r0 < m; r0 += E) {
         const int r = r0 + tid / P;
@@ -227,6 +256,7 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
     else if (cap >= max_rank) status |= ST_CAPPED;
     else status |= ST_OVERFLOW;
   }
+  if (tid == 0) sm.nrows = nused;
   __syncthreads();
   return k;
 }
@@ -236,7 +266,7 @@ __device__ inline int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, do
                                cpx<T>* __restrict__ U, cpx<T>* __restrict__ W,
                                cpx<double>* __restrict__ GU, cpx<double>* __restrict__ GV,
                                AcaShared<T>& sm, int& status) {
-  return aca_grp<1, T, Ent>(ent, m, n, cap, max_rank, tol, nu, U, W, GU, GV, sm, status);
+  return aca_grp<1, false, T, Ent>(ent, m, n, cap, max_rank, tol, nu, U, W, GU, GV, sm, status);
 }
 
 // ---- Hermitian Jacobi eigen-solver, one group, k <= 64 ------------------------

@@ -7,6 +7,8 @@
 #include <cstring>
 
 #include "internal.h"
+#include <type_traits>
+
 #include "matvec.h"
 
 namespace gcq {
@@ -235,6 +237,184 @@ __global__ void __launch_bounds__(256) perfreq_tiled(
   }
 }
 
+// ---- complex64 product on the matrix cores ------------------------------------
+// Per far block (R stacked columns, Ubar m x R, Vbar n x R, column-major, the
+// block's stack contiguous) and chunk of 64 frequency columns k:
+//   T = Vbar^H X_J (R x 64), T' = F o T with F[c][k] = f_c[rep(k)],
+//   Y_I += Ubar T'.
+// Per near block: Y_I += sum_d f_d[rep(k)] (D_d X_J)[:, k].
+// Complex products as four real v_mfma_f32_32x32x2f32 (A[i][k] in lane
+// i + 32 k, B[k][j] in lane j + 32 k, D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
+// in element r of lane l).  One workgroup of 4 waves per block; T' of up to
+// 128 stacked columns is held in LDS, larger stacks go 128 columns at a time.
+typedef float mf_v16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ mf_v16 mf_zero() {
+  mf_v16 z;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) z[r] = 0.f;
+  return z;
+}
+__device__ __forceinline__ mf_v16 mfma32(float a, float b, mf_v16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int MV_CC = 128;   // stacked columns per LDS chunk of T'
+constexpr int MV_KU = 8;     // MFMA steps whose operands are loaded ahead
+
+__global__ void __launch_bounds__(256) perfreq_mfma(
+    const int* __restrict__ blk, const int* __restrict__ order, int nmv,
+    const int* __restrict__ bterm, const int64_t* __restrict__ toff,
+    const int64_t* __restrict__ tfoff, const int64_t* __restrict__ cols,
+    const int* __restrict__ bcol, const cpx<float>* __restrict__ pool,
+    const int* __restrict__ colpos, int L, const cpx<float>* __restrict__ Xp,
+    cpx<float>* __restrict__ Yp) {
+  __shared__ cpx<float> Ts[MV_CC * 64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lr = lane & 31, lh = lane >> 5;   // MFMA operand row / k-half
+  for (int ob = blockIdx.x; ob < nmv; ob += gridDim.x) {
+    const int b = order[ob];
+    const int rb = blk[5 * b], m = blk[5 * b + 1] - rb, cb = blk[5 * b + 2],
+              n = blk[5 * b + 3] - cb;
+    const bool adm = blk[5 * b + 4] & 1;
+    const int mt = (m + 31) >> 5;
+    for (int kc = 0; kc < L; kc += 64) {
+      if (!adm) {
+        // near block: every wave owns output tiles (row tile, k tile)
+        const int d0 = bterm[b], d1 = bterm[b + 1];
+        for (int tile = w; tile < mt * 2; tile += 4) {
+          const int it = tile >> 1, kt = tile & 1;
+          const int kcol = kc + kt * 32 + lr;
+          const bool kin = kcol < L;
+          const int kp = kin ? colpos[kcol] : 0;
+          const int ia = it * 32 + lr;   // A row of this lane
+          mf_v16 yr = mf_zero(), yi = mf_zero();
+          for (int d = d0; d < d1; ++d) {
+            const cpx<float>* D = pool + toff[d];
+            mf_v16 pr = mf_zero(), pi = mf_zero();
+            for (int j0 = 0; j0 < n; j0 += 2 * MV_KU) {
+              // operands of MV_KU steps first, then their products
+              cpx<float> a[MV_KU], x[MV_KU];
+#pragma unroll
+              for (int u = 0; u < MV_KU; ++u) {
+                const int j = j0 + 2 * u + lh;
+                a[u] = (ia < m && j < n) ? D[int64_t(j) * m + ia] : cpx<float>{0.f, 0.f};
+                x[u] = (kin && j < n) ? Xp[int64_t(cb + j) * L + kcol] : cpx<float>{0.f, 0.f};
+              }
+#pragma unroll
+              for (int u = 0; u < MV_KU; ++u) {
+                pr = mfma32(a[u].re, x[u].re, pr);
+                pr = mfma32(-a[u].im, x[u].im, pr);
+                pi = mfma32(a[u].re, x[u].im, pi);
+                pi = mfma32(a[u].im, x[u].re, pi);
+              }
+            }
+            const cpx<float> f = kin ? pool[tfoff[d] + kp] : cpx<float>{0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              yr[r] += f.re * pr[r] - f.im * pi[r];
+              yi[r] += f.re * pi[r] + f.im * pr[r];
+            }
+          }
+          if (kin) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int row = it * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+              if (row < m) {
+                cpx<float>* y = Yp + int64_t(rb + row) * L + kcol;
+                atomicAdd(&y->re, yr[r]);
+                atomicAdd(&y->im, yi[r]);
+              }
+            }
+          }
+        }
+        continue;
+      }
+      const int c0b = bcol[b], R = bcol[b + 1] - c0b;
+      if (R == 0) continue;
+      const cpx<float>* Ust = pool + cols[3 * c0b];
+      const cpx<float>* Vst = pool + cols[3 * c0b + 1];
+      for (int cc = 0; cc < R; cc += MV_CC) {
+        const int cn = min(MV_CC, R - cc);
+        const int ct = (cn + 31) >> 5;
+        __syncthreads();   // Ts free
+        // T' = F o (Vbar^H X_J) for stacked columns cc .. cc + cn
+        for (int tile = w; tile < ct * 2; tile += 4) {
+          const int ti = tile >> 1, kt = tile & 1;
+          const int kcol = kc + kt * 32 + lr;
+          const bool kin = kcol < L;
+          const int ca = cc + ti * 32 + lr;   // A row (stacked column) of this lane
+          const cpx<float>* Vc = Vst + int64_t(ca) * n;
+          mf_v16 tr = mf_zero(), tim = mf_zero();
+          for (int j0 = 0; j0 < n; j0 += 2 * MV_KU) {
+            cpx<float> v[MV_KU], x[MV_KU];
+#pragma unroll
+            for (int u = 0; u < MV_KU; ++u) {
+              const int j = j0 + 2 * u + lh;
+              v[u] = (ca < R && j < n) ? Vc[j] : cpx<float>{0.f, 0.f};
+              x[u] = (kin && j < n) ? Xp[int64_t(cb + j) * L + kcol] : cpx<float>{0.f, 0.f};
+            }
+#pragma unroll
+            for (int u = 0; u < MV_KU; ++u) {   // conj(v) x
+              tr = mfma32(v[u].re, x[u].re, tr);
+              tr = mfma32(v[u].im, x[u].im, tr);
+              tim = mfma32(v[u].re, x[u].im, tim);
+              tim = mfma32(-v[u].im, x[u].re, tim);
+            }
+          }
+          const int kp = kin ? colpos[kcol] : 0;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int cl = ti * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);   // local stacked column
+            cpx<float> t = {0.f, 0.f};
+            if (cl < cn && kin) {
+              const cpx<float> f = pool[cols[3 * (c0b + cc + cl) + 2] + kp];
+              t = {f.re * tr[r] - f.im * tim[r], f.re * tim[r] + f.im * tr[r]};
+            }
+            Ts[cl * 64 + kt * 32 + lr] = t;
+          }
+        }
+        __syncthreads();
+        // Y_I += Ubar[:, cc .. cc + cn] T'
+        for (int tile = w; tile < mt * 2; tile += 4) {
+          const int it = tile >> 1, kt = tile & 1;
+          const int kcol = kc + kt * 32 + lr;
+          const int ia = it * 32 + lr;
+          mf_v16 yr = mf_zero(), yi = mf_zero();
+          for (int c2 = 0; c2 < ct * 32; c2 += 2 * MV_KU) {
+            cpx<float> uu[MV_KU], tt[MV_KU];
+#pragma unroll
+            for (int q = 0; q < MV_KU; ++q) {
+              const int cl = c2 + 2 * q + lh;   // < ct * 32 (ct * 32 is a multiple of 2 MV_KU)
+              uu[q] = (ia < m && cl < cn) ? Ust[int64_t(cc + cl) * m + ia] : cpx<float>{0.f, 0.f};
+              tt[q] = Ts[cl * 64 + kt * 32 + lr];
+            }
+#pragma unroll
+            for (int q = 0; q < MV_KU; ++q) {
+              yr = mfma32(uu[q].re, tt[q].re, yr);
+              yr = mfma32(-uu[q].im, tt[q].im, yr);
+              yi = mfma32(uu[q].re, tt[q].im, yi);
+              yi = mfma32(uu[q].im, tt[q].re, yi);
+            }
+          }
+          if (kcol < L) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int row = it * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+              if (row < m) {
+                cpx<float>* y = Yp + int64_t(rb + row) * L + kcol;
+                atomicAdd(&y->re, yr[r]);
+                atomicAdd(&y->im, yi[r]);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 // eq. product: one wave per block; per slice the frequency sums w1 (plain
 // columns) and w2 (conjugate-represented columns, conjugated input) are formed
 // first, then y_I += H w1 + conj(H w2)
@@ -357,11 +537,19 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
     int cus = 256;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
-    hipLaunchKernelGGL(perfreq_tiled<T>, dim3(std::max(1, std::min(F.n_mvblocks, cus * 2))),
-                       dim3(256), 0, st, ctx->d_blk.as<int>(), F.d_mvorder.as<int>(),
-                       F.n_mvblocks, F.d_bterm.as<int>(), F.d_toff.as<int64_t>(),
-                       F.d_tfoff.as<int64_t>(), F.d_cols.as<int64_t>(), F.d_bcol.as<int>(),
-                       F.slices.as<cpx<T>>(), d_colpos, L, Xp, Yp);
+    if constexpr (std::is_same<T, float>::value) {
+      hipLaunchKernelGGL(perfreq_mfma, dim3(std::max(1, std::min(F.n_mvblocks, cus * 4))), dim3(256),
+                         0, st, ctx->d_blk.as<int>(), F.d_mvorder.as<int>(), F.n_mvblocks,
+                         F.d_bterm.as<int>(), F.d_toff.as<int64_t>(), F.d_tfoff.as<int64_t>(),
+                         F.d_cols.as<int64_t>(), F.d_bcol.as<int>(), F.slices.as<cpx<float>>(),
+                         d_colpos, L, Xp, Yp);
+    } else {
+      hipLaunchKernelGGL(perfreq_tiled<T>, dim3(std::max(1, std::min(F.n_mvblocks, cus * 2))),
+                         dim3(256), 0, st, ctx->d_blk.as<int>(), F.d_mvorder.as<int>(),
+                         F.n_mvblocks, F.d_bterm.as<int>(), F.d_toff.as<int64_t>(),
+                         F.d_tfoff.as<int64_t>(), F.d_cols.as<int64_t>(), F.d_bcol.as<int>(),
+                         F.slices.as<cpx<T>>(), d_colpos, L, Xp, Yp);
+    }
     if (precision == GCQ_C128)
       hipLaunchKernelGGL((perm_out_t<T, double>), dim3(g), dim3(256), 0, st, Yp, (cpx<double>*)Y,
                          perm, d_conj, n, L);
