@@ -37,8 +37,9 @@ struct Term3 {
 // three uses that never overlap in time: the residual coefficients of the
 // slice ACA (RES of them: the sum of the accepted slices' ranks; a block whose
 // slices need more is redone by the next larger group), the recompression
-// matrices (ranks up to JK in LDS, larger ones in the global workspace), and
-// the 16 KB row staging of the slice inner products.
+// matrices (ranks up to JK in LDS, larger ones in the global workspace), the
+// 16 KB row staging of the slice inner products and the factor staging of the
+// pivot search (at most 24 KB).
 template <int NW>
 struct Cls;
 template <>
@@ -47,7 +48,7 @@ struct Cls<1> {
 };
 template <>
 struct Cls<2> {
-  static constexpr int JK = 20;
+  static constexpr int JK = 24;
 };
 template <>
 struct Cls<4> {
@@ -55,7 +56,7 @@ struct Cls<4> {
 };
 template <>
 struct Cls<8> {
-  static constexpr int JK = 28;
+  static constexpr int JK = 36;
 };
 
 enum : int {
@@ -171,47 +172,73 @@ __device__ inline cpx<T> slice_at(const Term3& t, const cpx<T>* pool, int m, int
 }
 
 // Pivot of a factored slice H = Ubar Vbar^H (m x n, rank t): largest |H[i, j]|,
-// first in row-major order on ties.  Each thread expands 4 x 4 tiles of the
-// product (the dense block is never stored).
+// first in row-major order on ties.  The product is expanded chunk by chunk
+// (CR x CC entries, one 4 x 4 tile per thread) and never stored; the chunk's
+// rows of Ubar and Vbar pass through LDS TC columns at a time, so that every
+// factor entry is read once per chunk row / column instead of once per tile.
+// stage: LDS scratch of (CR + CC) * 128 bytes.
 template <typename T, int NW>
 __device__ inline void lowrank_argmax(const cpx<T>* __restrict__ U, const cpx<T>* __restrict__ V,
-                                      int m, int n, int t, double& best, int& be) {
-  const int ti = (m + 3) >> 2, tj = (n + 3) >> 2;
+                                      int m, int n, int t, double& best, int& be, cpx<T>* stage) {
+  constexpr int NT = NW * WAVE;
+  constexpr int CR = NW >= 4 ? 64 : 32;                  // chunk rows
+  constexpr int CC = NT * 16 / CR;                       // chunk columns: NT tiles of 4 x 4
+  constexpr int TC = int(128 / sizeof(cpx<T>));          // factor columns per stage
+  const int tid = threadIdx.x;
+  cpx<T>* su = stage;             // [c][r], CR rows
+  cpx<T>* sv = stage + TC * CR;   // [c][j], CC rows
+  const int ti = tid % (CR / 4), tj = tid / (CR / 4);    // this thread's tile in the chunk
   best = -1.0;
   be = 0x7fffffff;
-  for (int tile = threadIdx.x; tile < ti * tj; tile += NW * WAVE) {
-    const int i0 = (tile / tj) * 4, j0 = (tile % tj) * 4;
-    cpx<T> acc[4][4];
+  for (int i0 = 0; i0 < m; i0 += CR) {
+    for (int j0 = 0; j0 < n; j0 += CC) {
+      cpx<T> acc[4][4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = {T(0), T(0)};
-    for (int c = 0; c < t; ++c) {
-      cpx<T> u[4], v[4];
+        for (int y = 0; y < 4; ++y) acc[x][y] = {T(0), T(0)};
+      for (int c0 = 0; c0 < t; c0 += TC) {
+        __syncthreads();
+        for (int e = tid; e < TC * CR; e += NT) {
+          const int c = e / CR, r = e % CR;
+          su[e] = (c0 + c < t && i0 + r < m) ? U[int64_t(c0 + c) * m + i0 + r] : cpx<T>{T(0), T(0)};
+        }
+        for (int e = tid; e < TC * CC; e += NT) {
+          const int c = e / CC, r = e % CC;
+          sv[e] = (c0 + c < t && j0 + r < n) ? V[int64_t(c0 + c) * n + j0 + r] : cpx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+        const int cn = min(TC, t - c0);
+        for (int c = 0; c < cn; ++c) {
+          cpx<T> u[4], v[4];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        u[x] = i0 + x < m ? U[int64_t(c) * m + i0 + x] : cpx<T>{T(0), T(0)};
-        v[x] = j0 + x < n ? V[int64_t(c) * n + j0 + x] : cpx<T>{T(0), T(0)};
+          for (int x = 0; x < 4; ++x) {
+            u[x] = su[c * CR + 4 * ti + x];
+            v[x] = sv[c * CC + 4 * tj + x];
+          }
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {   // u conj(v)
+              acc[x][y].re += u[x].re * v[y].re + u[x].im * v[y].im;
+              acc[x][y].im += u[x].im * v[y].re - u[x].re * v[y].im;
+            }
+        }
       }
 #pragma unroll
       for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {   // u conj(v)
-          acc[x][y].re += u[x].re * v[y].re + u[x].im * v[y].im;
-          acc[x][y].im += u[x].im * v[y].re - u[x].re * v[y].im;
+        for (int y = 0; y < 4; ++y) {
+          const int i = i0 + 4 * ti + x, j = j0 + 4 * tj + y;
+          if (i < m && j < n) {
+            const double val = mag2(acc[x][y]);
+            const int e = i * n + j;
+            if (val > best || (val == best && e < be)) { best = val; be = e; }
+          }
         }
     }
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        if (i0 + x < m && j0 + y < n) {
-          const double val = mag2(acc[x][y]);
-          const int e = (i0 + x) * n + j0 + y;
-          if (val > best || (val == best && e < be)) { best = val; be = e; }
-        }
-      }
   }
+  __syncthreads();
   grp_argmax<NW>(best, be);
 }
 
@@ -305,7 +332,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
   for (;;) {
     if (tid == 0) sh.idx = atomicAdd(counter, 1);
     __syncthreads();
-    const int idx = sh.idx;
+    const int idx = uni(sh.idx);
     if (idx >= nblocks) break;
     const int b = order[idx];
     const BlockDesc3 B = blocks[b];
@@ -322,7 +349,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
     int S = B.sres;
     if (tid == 0) sh.alloc = pool_alloc(cursor, int64_t(m + n) * S, capacity);
     __syncthreads();
-    int64_t sbase = sh.alloc;
+    int64_t sbase = uni64(sh.alloc);
     int ell = 0, kcur = 0, status = 0, nres = 0;
     double norm2 = 0.0;
     // algorithmic work of this block: entries and operations (see gcq_aca3d_stats)
@@ -346,12 +373,13 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
         const double pi = double(a.im) * bb.re - double(a.re) * bb.im;
         nu2 += pr * g.re - pi * g.im;
       }
-      const double nu = sqrt(fmax(grp_sum<NW>(nu2), 0.0));
+      const double nu = unid(sqrt(fmax(grp_sum<NW>(nu2), 0.0)));
       // ---- residual slice at k_cur: ACA, then recompression
       ResidualEntry<T, ALLFAR, NW> ent{&tab, B.rb, B.cb, m, n, sg.x, sg.y, B.all_far != 0, nres, &sh,
                                        Us, Vs, true};
       int ast = 0;
-      const int k = aca_grp<NW, true, T>(ent, m, n, cap, aca_cap, tol_aca, nu, U, W, GU, GV, sh.aca, ast);
+      const int k = uni(aca_grp<NW, true, T>(ent, m, n, cap, aca_cap, tol_aca, nu, U, W, GU, GV, sh.aca, ast));
+      ast = uni(ast);
       if (ast & ST_CAPPED) status |= ST_CAPPED;
       {
         // rows (length n) and columns (length m) with their residual sums
@@ -361,7 +389,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
                   2.0 * 8.0 * (m + n) * 0.5 * double(k) * (k - 1);   // residual terms, Gram entries
       }
       cpx<double>* A = recompress_mats(k) <= recompress_mats(JK) ? sh.mats : jmats;
-      const int t = recompress_grp<NW>(k, cap, GU, GV, tol_aca, nu, true, A, sh.rs);
+      const int t = uni(recompress_grp<NW>(k, cap, GU, GV, tol_aca, nu, true, A, sh.rs));
       // the candidate slice goes to the next free stacked columns
       if (nres + t > SH::RES) { status |= ST_ESCALATE; break; }   // needs a larger group
       if (nres + t > S) {
@@ -369,7 +397,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
         const int S2 = min(R3_MAX * 64, max(2 * S, ((nres + t + 15) / 16) * 16));
         if (tid == 0) sh.alloc = pool_alloc(cursor, int64_t(m + n) * S2, capacity);
         __syncthreads();
-        const int64_t nbase = sh.alloc;
+        const int64_t nbase = uni64(sh.alloc);
         if (nbase < 0) { status |= ST_DEFERRED; break; }
         cpx<T>* nUs = pool + nbase;
         cpx<T>* nVs = nUs + int64_t(S2) * m;
@@ -400,14 +428,16 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       wflops += 8.0 * (double(t) * (m + n) * k + double(m) * n * t);   // apply, expansion
       double best;
       int be;
-      lowrank_argmax<T, NW>(pool + cur.slice, pool + cur.vslice, m, n, t, best, be);
+      lowrank_argmax<T, NW>(pool + cur.slice, pool + cur.vslice, m, n, t, best, be,
+                            reinterpret_cast<cpx<T>*>(sh.mats));
       if (!(best > PivFloor<T>::v)) break;   // zero pivot: rank stays ell
+      be = uni(be);
       const int ip = be / n, jp = be % n;
       const cpx<T> piv = slice_at<T>(cur, pool, m, n, ip, jp);
       for (int d = tid; d < ell; d += NT) sh.hp[d] = slice_at<T>(sh.term[d], pool, m, n, ip, jp);
       if (tid == 0) sh.alloc = pool_alloc(cursor, nK, capacity);
       __syncthreads();
-      const int64_t foff = sh.alloc;
+      const int64_t foff = uni64(sh.alloc);
       if (foff < 0) { status |= ST_DEFERRED; break; }
       cur.fiber = foff;
       // ---- fiber over K
@@ -433,7 +463,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
         nf2 += double(f.re) * double(f.re) + double(f.im) * double(f.im);
       }
       __syncthreads();
-      nf2 = grp_sum<NW>(nf2);
+      nf2 = unid(grp_sum<NW>(nf2));
       // ---- eq. norm: <H_d, H_l> = tr((U_l^H U_d)(V_d^H V_l)), |H_l|^2 with d = l
       double nh2 = 0.0;
       {
@@ -447,7 +477,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
           if (d < ell) {
             if (tid == 0) sh.hin[d] = h;
           } else {
-            nh2 = h.re;
+            nh2 = unid(h.re);
           }
         }
       }
@@ -465,7 +495,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
         fi = wave_sum(fi);
         crossw += sh.hin[d].re * fr - sh.hin[d].im * fi;
       }
-      const double cross = grp_sum<NW>(lane == 0 ? crossw : 0.0);
+      const double cross = unid(grp_sum<NW>(lane == 0 ? crossw : 0.0));
       norm2 += 2.0 * cross + nh2 * nf2;
       if (tid == 0) sh.usedk[kcur >> 5] |= 1u << (kcur & 31);
       __syncthreads();
@@ -490,6 +520,8 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
         if (v > bf) { bf = v; bk = kk; }
       }
       grp_argmax<NW>(bf, bk);
+      bk = uni(bk);
+      bf = unid(bf);
       if (bk == 0x7fffffff) break;                       // every frequency used
       if (ell >= rmax) { status |= ST_CAPPED; break; }
       if (!(bf > 0.0)) break;                            // fiber zero at all unused ones

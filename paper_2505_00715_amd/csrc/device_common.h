@@ -88,6 +88,20 @@ __device__ __forceinline__ void wave_argmax(T& val, int& idx) {
   }
 }
 
+// ---- wave-uniform values ----------------------------------------------------
+// A value that every lane holds alike (a group reduction's result, a value read
+// from LDS by all lanes) is moved to a scalar register, which frees vector
+// registers for the loops.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(v))));
+  const int hi = __builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(v) >> 32)));
+  return int64_t((uint64_t(uint32_t(hi)) << 32) | uint64_t(uint32_t(lo)));
+}
+__device__ __forceinline__ double unid(double v) {
+  return __builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, v)));
+}
+
 // ---- group reductions: NW wave64s of one workgroup -------------------------
 // Every thread of the workgroup receives the result.  The waves' partial
 // results are combined in wave order, so the result does not depend on timing.

@@ -137,6 +137,8 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
     if (tid == 0) sm.used[i >> 5] |= 1u << (i & 31);
     ++nused;
     grp_argmax<NW>(best, bj);
+    best = unid(best);
+    bj = uni(bj);
     __syncthreads();
     if (!(best > PivFloor<T>::v)) {
       int cand = 0x7fffffff;
@@ -145,7 +147,7 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
         if (w == (m - 1) / 32 && (m & 31)) free_bits &= (1u << (m & 31)) - 1u;
         if (free_bits) cand = min(cand, w * 32 + __ffs(free_bits) - 1);
       }
-      cand = grp_min_int<NW>(cand);
+      cand = uni(grp_min_int<NW>(cand));
       if (cand == 0x7fffffff || nused >= m) { status |= ST_EXACT; break; }
       i = cand;
       continue;
@@ -209,6 +211,8 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
     }
     __syncthreads();
     grp_sum2<NW>(nw2, nu2);
+    nw2 = unid(nw2);
+    nu2 = unid(nu2);
     // Gram entries of the new term: entry l by wave l mod NW
     double crossw = 0.0;
     for (int l = wid; l < k; l += NW) {
@@ -236,7 +240,7 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
         GV[k * cap + l] = {gwr, gwi};
       }
     }
-    const double cross = grp_sum<NW>(lane == 0 ? crossw : 0.0);
+    const double cross = unid(grp_sum<NW>(lane == 0 ? crossw : 0.0));
     if (tid == 0) {
       GU[k * cap + k] = {nu2, 0.0};
       GV[k * cap + k] = {nw2, 0.0};
@@ -248,6 +252,7 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
       break;
     }
     grp_argmax<NW>(bestu, bi);
+    bi = uni(bi);
     if (nused >= m || bi == 0x7fffffff) { status |= ST_EXACT; break; }
     i = bi;
   }
@@ -441,7 +446,7 @@ __device__ inline int recompress_grp(int k, int cap, cpx<double>* GU, cpx<double
     rs.dmax = d0;
   }
   __syncthreads();
-  const double dlim = 1e-14 * rs.dmax;
+  const double dlim = 1e-14 * unid(rs.dmax);
   int r = 0;
   for (; r < k; ++r) {
     // pivot: largest remaining diagonal (lowest index on ties)
@@ -459,7 +464,7 @@ __device__ inline int recompress_grp(int k, int cap, cpx<double>* GU, cpx<double
       }
     }
     __syncthreads();
-    const int p = rs.nkeep;
+    const int p = uni(rs.nkeep);
     if (p < 0) break;
     const double piv = sqrt(S[p * k + p].re);
     // R[r][b] = S[p][b] / piv over remaining b (R[r][p] = piv)
@@ -541,7 +546,7 @@ __device__ inline int recompress_grp(int k, int cap, cpx<double>* GU, cpx<double
     rs.tcut = t;
   }
   __syncthreads();
-  const int t = rs.tcut;
+  const int t = uni(rs.tcut);
   // CU = R^H Z_t (k x t) over GU
   for (int e = tid; e < k * t; e += NT) {
     const int x = e / t, c = e % t;
