@@ -102,10 +102,16 @@ enum {
  *   aca3d_stack_slices: initial reservation of an admissible block's stacked
  *     slice factors, in slices of full ACA rank (1..64, default 8); a block
  *     that needs more moves its stack to a reservation twice as large.
+ *   aca_waves, product_graph: see the fields.
  * Results do not depend on the configuration beyond rounding order. */
 typedef struct {
   int32_t aca3d_waves[4];
   int32_t aca3d_stack_slices;
+  int32_t aca_waves;           /* wave64s per (block, frequency) pair in gcq_aca_blocks:
+                                  1, 2 or 4 (default 1) */
+  int32_t product_graph;       /* 1 (default): gcq_compressed_matvec and gcq_solve replay
+                                  the per-frequency product as a captured HIP graph;
+                                  0: plain launches */
 } gcq_tuning;
 
 typedef struct {

@@ -51,7 +51,8 @@ class SolveStats(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("aca3d_waves", C.c_int32 * 4), ("aca3d_stack_slices", C.c_int32)]
+    _fields_ = [("aca3d_waves", C.c_int32 * 4), ("aca3d_stack_slices", C.c_int32),
+                ("aca_waves", C.c_int32), ("product_graph", C.c_int32)]
 
 
 class TrainCfg(C.Structure):
@@ -175,10 +176,17 @@ class Context:
     def kernel_ms(self, name: str) -> float:
         return _lib.gcq_kernel_ms(self._h, name.encode())
 
-    def set_tuning(self, aca3d_waves=None, aca3d_stack_slices=None):
+    def set_tuning(self, aca3d_waves=None, aca3d_stack_slices=None, aca_waves=None,
+                   product_graph=None):
         """aca3d_waves: 4 group sizes (waves per block) of the 3D-ACA size classes;
-        aca3d_stack_slices: initial stack reservation of a far block (slices)."""
+        aca3d_stack_slices: initial stack reservation of a far block (slices);
+        aca_waves: waves per pair of aca_blocks; product_graph: replay the
+        per-frequency product as a captured graph."""
         t = self.get_tuning()
+        if aca_waves is not None:
+            t.aca_waves = int(aca_waves)
+        if product_graph is not None:
+            t.product_graph = int(product_graph)
         if aca3d_waves is not None:
             for c, w in enumerate(aca3d_waves):
                 t.aca3d_waves[c] = int(w)

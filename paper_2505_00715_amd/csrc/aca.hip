@@ -27,19 +27,29 @@ struct PlainEntry {
 
 // ALLFAR = true serves the pairs of blocks without self/near-tier entries,
 // ALLFAR = false the others; each instance skips the pairs of the other kind.
-template <typename T, bool ALLFAR>
-__global__ void __launch_bounds__(64) aca_kernel(Tab tab, const PairDesc* __restrict__ pairs,
-                                                 const int* __restrict__ order, int npairs,
-                                                 unsigned char* __restrict__ ws, double tol,
-                                                 int max_rank, int* __restrict__ out_rank,
-                                                 int* __restrict__ out_status,
-                                                 int* __restrict__ counter) {
+// NW waves work on one pair together.
+template <typename T, bool ALLFAR, int NW>
+__global__ void __launch_bounds__(NW * 64) aca_kernel(Tab tab, const PairDesc* __restrict__ pairs,
+                                                      const int* __restrict__ order, int npairs,
+                                                      unsigned char* __restrict__ ws, double tol,
+                                                      int max_rank, int* __restrict__ out_rank,
+                                                      int* __restrict__ out_status,
+                                                      int* __restrict__ counter) {
   __shared__ AcaShared<T> sm;
-  const int lane = threadIdx.x;
+  __shared__ int slot;
+  const int tid = threadIdx.x;
   for (;;) {
-    int idx = 0;
-    if (lane == 0) idx = atomicAdd(counter, 1);
-    idx = __shfl(idx, 0, WAVE);
+    int idx;
+    if constexpr (NW == 1) {
+      idx = 0;
+      if (tid == 0) idx = atomicAdd(counter, 1);
+      idx = __shfl(idx, 0, WAVE);
+    } else {
+      if (tid == 0) slot = atomicAdd(counter, 1);
+      __syncthreads();
+      idx = uni(slot);
+      __syncthreads();
+    }
     if (idx >= npairs) break;
     const int pid = order ? order[idx] : idx;
     const PairDesc d = pairs[pid];
@@ -49,13 +59,22 @@ __global__ void __launch_bounds__(64) aca_kernel(Tab tab, const PairDesc* __rest
     cpx<double>* GU = reinterpret_cast<cpx<double>*>(ws + d.ws + ws_gram_off<T>(d.cap, d.m, d.n));
     PlainEntry<T, ALLFAR> ent{&tab, d.rb, d.cb, d.sr, d.si, d.all_far != 0};
     int status = 0;
-    const int k = aca_wave<T>(ent, d.m, d.n, d.cap, max_rank, tol, 0.0, U, W, GU,
-                              GU + d.cap * d.cap, sm, status);
-    if (lane == 0) {
+    const int k = aca_grp<NW, (NW > 1), T>(ent, d.m, d.n, d.cap, max_rank, tol, 0.0, U, W, GU,
+                                           GU + d.cap * d.cap, sm, status);
+    if (tid == 0) {
       out_rank[pid] = k;
       out_status[pid] = status;
     }
     __syncthreads();
+  }
+}
+
+template <typename T, bool AF, typename... Args>
+static void launch_aca(int nw, int grid, hipStream_t st, Args... args) {
+  switch (nw) {
+    case 1: hipLaunchKernelGGL((aca_kernel<T, AF, 1>), dim3(grid), dim3(64), 0, st, args...); break;
+    case 2: hipLaunchKernelGGL((aca_kernel<T, AF, 2>), dim3(grid), dim3(128), 0, st, args...); break;
+    default: hipLaunchKernelGGL((aca_kernel<T, AF, 4>), dim3(grid), dim3(256), 0, st, args...); break;
   }
 }
 
@@ -155,17 +174,17 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
     hipLaunchKernelGGL(zero_int, dim3(1), dim3(64), 0, st, d_counter, 8);
     int nnf = 0;
     for (int a = 0; a < nc; ++a) nnf += cd[a].all_far == 0;
-    const int grid = std::min(nc, dev_cus * 32);
+    const int nw = ctx->tune.aca_waves;
+    const int grid = std::min(nc, dev_cus * 32 / nw);
     GCQ_TRY(timed_begin(ctx));
-    hipLaunchKernelGGL((aca_kernel<T, true>), dim3(grid), dim3(64), 0, st, ctx->tab(),
-                       ctx->scratchB.as<PairDesc>(), (const int*)nullptr, nc,
-                       ctx->scratchA.as<unsigned char>(), tol, max_rank, d_rank, d_status,
-                       d_counter);
+    launch_aca<T, true>(nw, grid, st, ctx->tab(), (const PairDesc*)ctx->scratchB.as<PairDesc>(),
+                        (const int*)nullptr, nc, ctx->scratchA.as<unsigned char>(), tol, max_rank,
+                        d_rank, d_status, d_counter);
     if (nnf > 0)
-      hipLaunchKernelGGL((aca_kernel<T, false>), dim3(std::min(grid, nnf)), dim3(64), 0, st,
-                         ctx->tab(), ctx->scratchB.as<PairDesc>(), (const int*)nullptr, nc,
-                         ctx->scratchA.as<unsigned char>(), tol, max_rank, d_rank, d_status,
-                         d_counter + 1);
+      launch_aca<T, false>(nw, std::min(grid, nnf), st, ctx->tab(),
+                           (const PairDesc*)ctx->scratchB.as<PairDesc>(), (const int*)nullptr, nc,
+                           ctx->scratchA.as<unsigned char>(), tol, max_rank, d_rank, d_status,
+                           d_counter + 1);
     GCQ_HIP(hipGetLastError());
     ms_aca += timed_end(ctx, "aca");
     // recompression; matrices above 32 terms live in global scratch

@@ -741,6 +741,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   GCQ_HIP(hipSetDevice(ctx->device));
   Faces3D& F = ctx->F;
   F.valid = false;
+  F.graphs.clear();   // they refer to the tables rebuilt below
   F.precision = precision;
   F.nK = nK;
   const int nb = int(ctx->blocks.size());

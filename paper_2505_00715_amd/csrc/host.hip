@@ -175,6 +175,10 @@ GCQ_API int gcq_create(int device, void* hip_stream, gcq_context** out) {
   if (!ctx) return fail(GCQ_ERR_NOMEM, "host allocation failed");
   ctx->device = device;
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->cus = prop.multiProcessorCount;
+  }
   if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
     delete ctx;
     return fail(GCQ_ERR_HIP, "hipEventCreate failed");
@@ -225,6 +229,10 @@ GCQ_API int gcq_set_tuning(gcq_context* ctx, const gcq_tuning* tuning) {
   }
   if (tuning->aca3d_stack_slices < 1 || tuning->aca3d_stack_slices > 64)
     return fail(GCQ_ERR_ARG, "aca3d_stack_slices = %d is not in 1..64", tuning->aca3d_stack_slices);
+  if (tuning->aca_waves != 1 && tuning->aca_waves != 2 && tuning->aca_waves != 4)
+    return fail(GCQ_ERR_ARG, "aca_waves = %d is not 1, 2 or 4", tuning->aca_waves);
+  if (tuning->product_graph != 0 && tuning->product_graph != 1)
+    return fail(GCQ_ERR_ARG, "product_graph = %d is not 0 or 1", tuning->product_graph);
   ctx->tune = *tuning;
   return GCQ_OK;
 }
@@ -254,6 +262,7 @@ GCQ_API int gcq_upload_mesh(gcq_context* ctx, const double* xyz, int64_t n_verti
   // invalidate everything downstream
   ctx->have_mesh = ctx->have_tree = false;
   ctx->H.valid = ctx->F.valid = false;
+  ctx->F.graphs.clear();
   const int n = int(n_triangles);
   for (int64_t i = 0; i < 3 * n_vertices; ++i)
     if (!std::isfinite(xyz[i])) return fail(GCQ_ERR_NUMERIC, "non-finite vertex coordinate");
@@ -312,6 +321,7 @@ GCQ_API int gcq_set_frequencies(gcq_context* ctx, const gcq_c128* s, int32_t n_f
     if (!(s[k].re > 0.0)) return fail(GCQ_ERR_ARG, "frequency %d has Re s <= 0", k);
   }
   ctx->H.valid = ctx->F.valid = false;
+  ctx->F.graphs.clear();
   ctx->L = n_freq;
   ctx->s.resize(n_freq);
   for (int k = 0; k < n_freq; ++k) ctx->s[k] = {s[k].re, s[k].im};
@@ -349,6 +359,7 @@ GCQ_API int gcq_build_cluster_tree(gcq_context* ctx, int32_t leaf_size, double e
   if (ctx->device >= 0) GCQ_HIP(hipSetDevice(ctx->device));
   ctx->have_tree = false;
   ctx->H.valid = ctx->F.valid = false;
+  ctx->F.graphs.clear();
   const int n = ctx->n;
   ctx->leaf = leaf_size;
   ctx->eta = eta;

@@ -104,6 +104,27 @@ struct HFaces {
 };
 
 // ---- 3D-ACA result --------------------------------------------------------------------
+// instantiated graphs of the per-frequency product, keyed by the caller's
+// buffers and the precision; destroyed with the operator they were captured on
+struct ProductGraphs {
+  struct Entry {
+    const void* X;
+    void* Y;
+    int precision;
+    hipGraphExec_t exec;
+  };
+  std::vector<Entry> e;
+  hipStream_t cap = nullptr;   // capture stream
+  ~ProductGraphs() {
+    clear();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+  void clear() {
+    for (auto& x : e) (void)hipGraphExecDestroy(x.exec);
+    e.clear();
+  }
+};
+
 struct Faces3D {
   bool valid = false;
   int precision = GCQ_C128;
@@ -120,6 +141,10 @@ struct Faces3D {
   // product tables: per far block its stacked columns (U column offset, V
   // column offset, fiber offset), blocks ordered by work, largest first
   DevBuf d_cols, d_bcol, d_mvorder;
+  // the product's own buffers: frequency-major copies of X and Y, frequency
+  // tables (position in K, conjugation flag); fixed while the operator lives
+  DevBuf pxy, pmeta;
+  ProductGraphs graphs;
   int n_mvblocks = 0;
   int64_t storage_bytes = 0;
   int64_t dense_bytes = 0;
@@ -137,6 +162,7 @@ struct RankModel {
 
 struct gcq_context {
   int device = 0;
+  int cus = 256;   // compute units of the device
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::map<std::string, double> kernel_ms;
@@ -145,7 +171,7 @@ struct gcq_context {
   hipStream_t side[3] = {nullptr, nullptr, nullptr};
   hipEvent_t evfork = nullptr, evjoin[3] = {nullptr, nullptr, nullptr};
   // launch configuration
-  gcq_tuning tune = {{4, 4, 4, 4}, 8};
+  gcq_tuning tune = {{4, 4, 4, 4}, 8, 1, 1};
 
   // mesh
   bool have_mesh = false;

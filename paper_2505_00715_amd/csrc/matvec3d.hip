@@ -500,11 +500,109 @@ __global__ void __launch_bounds__(64) wsum_kernel(
   }
 }
 
+// the kernels of the per-frequency product on stream st (no allocation, no
+// host transfer: a capturable sequence)
+template <typename T>
+static void enqueue_perfreq(gcq_context* ctx, hipStream_t st, int precision, const void* X, void* Y) {
+  Faces3D& F = ctx->F;
+  const int n = ctx->n, L = ctx->L;
+  const int64_t nl = int64_t(n) * L;
+  cpx<T>* Xp = F.pxy.as<cpx<T>>();
+  cpx<T>* Yp = Xp + nl;
+  const int* d_colpos = F.pmeta.as<int>();
+  const int* d_conj = d_colpos + L;
+  const int* perm = ctx->d_perm.as<int>();
+  const int g = 4096;
+  if (precision == GCQ_C128)
+    hipLaunchKernelGGL((perm_in_t<double, T>), dim3(g), dim3(256), 0, st, (const cpx<double>*)X, Xp,
+                       perm, d_conj, n, L);
+  else
+    hipLaunchKernelGGL((perm_in_t<float, T>), dim3(g), dim3(256), 0, st, (const cpx<float>*)X, Xp,
+                       perm, d_conj, n, L);
+  hipLaunchKernelGGL(zero3<T>, dim3(g), dim3(256), 0, st, Yp, nl);
+  const int cus = ctx->cus;
+  if constexpr (std::is_same<T, float>::value) {
+    hipLaunchKernelGGL(perfreq_mfma, dim3(std::max(1, std::min(F.n_mvblocks, cus * 4))), dim3(256), 0,
+                       st, ctx->d_blk.as<int>(), F.d_mvorder.as<int>(), F.n_mvblocks,
+                       F.d_bterm.as<int>(), F.d_toff.as<int64_t>(), F.d_tfoff.as<int64_t>(),
+                       F.d_cols.as<int64_t>(), F.d_bcol.as<int>(), F.slices.as<cpx<float>>(), d_colpos,
+                       L, Xp, Yp);
+  } else {
+    hipLaunchKernelGGL(perfreq_tiled<T>, dim3(std::max(1, std::min(F.n_mvblocks, cus * 2))), dim3(256),
+                       0, st, ctx->d_blk.as<int>(), F.d_mvorder.as<int>(), F.n_mvblocks,
+                       F.d_bterm.as<int>(), F.d_toff.as<int64_t>(), F.d_tfoff.as<int64_t>(),
+                       F.d_cols.as<int64_t>(), F.d_bcol.as<int>(), F.slices.as<cpx<T>>(), d_colpos, L,
+                       Xp, Yp);
+  }
+  if (precision == GCQ_C128)
+    hipLaunchKernelGGL((perm_out_t<T, double>), dim3(g), dim3(256), 0, st, Yp, (cpx<double>*)Y, perm,
+                       d_conj, n, L);
+  else
+    hipLaunchKernelGGL((perm_out_t<T, float>), dim3(g), dim3(256), 0, st, Yp, (cpx<float>*)Y, perm,
+                       d_conj, n, L);
+}
+
+// the product's buffers and frequency tables (once per operator)
+template <typename T>
+static int product_setup(gcq_context* ctx) {
+  Faces3D& F = ctx->F;
+  const int n = ctx->n, L = ctx->L;
+  const size_t need = size_t(2) * n * L * sizeof(cpx<T>);
+  if (F.pxy.bytes < need || !F.pmeta.p) {
+    F.graphs.clear();   // captured graphs refer to the old buffers
+    GCQ_TRY(F.pxy.ensure(need));
+    std::vector<int> meta(2 * L);
+    for (int k = 0; k < L; ++k) {
+      meta[k] = ctx->kpos[k];
+      meta[L + k] = ctx->conj[k];
+    }
+    GCQ_TRY(upload(F.pmeta, meta, ctx->stream));
+    GCQ_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  return GCQ_OK;
+}
+
 template <typename T>
 static int compressed_impl(gcq_context* ctx, int mode, int precision, const void* X, void* Y) {
   Faces3D& F = ctx->F;
   hipStream_t st = ctx->stream;
   const int n = ctx->n, L = ctx->L, nb = int(ctx->blocks.size());
+  if (mode == GCQ_PER_FREQUENCY) {
+    GCQ_TRY(product_setup<T>(ctx));
+    if (ctx->tune.product_graph) {
+      hipGraphExec_t exec = nullptr;
+      for (auto& x : F.graphs.e)
+        if (x.X == X && x.Y == Y && x.precision == precision) exec = x.exec;
+      if (!exec) {
+        if (!F.graphs.cap) GCQ_HIP(hipStreamCreateWithFlags(&F.graphs.cap, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        GCQ_HIP(hipStreamBeginCapture(F.graphs.cap, hipStreamCaptureModeThreadLocal));
+        enqueue_perfreq<T>(ctx, F.graphs.cap, precision, X, Y);
+        const hipError_t ce = hipGetLastError();
+        GCQ_HIP(hipStreamEndCapture(F.graphs.cap, &graph));
+        if (ce != hipSuccess) {
+          (void)hipGraphDestroy(graph);
+          return fail(GCQ_ERR_HIP, "capture of the product failed: %s", hipGetErrorString(ce));
+        }
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return fail(GCQ_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+        if (F.graphs.e.size() >= 8) {   // keep the most recent few
+          (void)hipGraphExecDestroy(F.graphs.e.front().exec);
+          F.graphs.e.erase(F.graphs.e.begin());
+        }
+        F.graphs.e.push_back({X, Y, precision, exec});
+      }
+      GCQ_TRY(timed_begin(ctx));
+      GCQ_HIP(hipGraphLaunch(exec, st));
+    } else {
+      GCQ_TRY(timed_begin(ctx));
+      enqueue_perfreq<T>(ctx, st, precision, X, Y);
+    }
+    GCQ_HIP(hipGetLastError());
+    timed_end(ctx, "matvec_perfreq");
+    return GCQ_OK;
+  }
   std::vector<int> meta(2 * L);
   for (int k = 0; k < L; ++k) {
     meta[k] = ctx->kpos[k];
@@ -524,39 +622,7 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
   const int g = 4096;
   const int* perm = ctx->d_perm.as<int>();
   GCQ_TRY(timed_begin(ctx));
-  if (mode == GCQ_PER_FREQUENCY) {
-    GCQ_TRY(ctx->scratchA.ensure(size_t(nl) * sizeof(cpx<T>)));
-    Yp = ctx->scratchA.as<cpx<T>>();
-    if (precision == GCQ_C128)
-      hipLaunchKernelGGL((perm_in_t<double, T>), dim3(g), dim3(256), 0, st, (const cpx<double>*)X,
-                         Xp, perm, d_conj, n, L);
-    else
-      hipLaunchKernelGGL((perm_in_t<float, T>), dim3(g), dim3(256), 0, st, (const cpx<float>*)X, Xp,
-                         perm, d_conj, n, L);
-    hipLaunchKernelGGL(zero3<T>, dim3(g), dim3(256), 0, st, Yp, nl);
-    int cus = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
-    if constexpr (std::is_same<T, float>::value) {
-      hipLaunchKernelGGL(perfreq_mfma, dim3(std::max(1, std::min(F.n_mvblocks, cus * 4))), dim3(256),
-                         0, st, ctx->d_blk.as<int>(), F.d_mvorder.as<int>(), F.n_mvblocks,
-                         F.d_bterm.as<int>(), F.d_toff.as<int64_t>(), F.d_tfoff.as<int64_t>(),
-                         F.d_cols.as<int64_t>(), F.d_bcol.as<int>(), F.slices.as<cpx<float>>(),
-                         d_colpos, L, Xp, Yp);
-    } else {
-      hipLaunchKernelGGL(perfreq_tiled<T>, dim3(std::max(1, std::min(F.n_mvblocks, cus * 2))),
-                         dim3(256), 0, st, ctx->d_blk.as<int>(), F.d_mvorder.as<int>(),
-                         F.n_mvblocks, F.d_bterm.as<int>(), F.d_toff.as<int64_t>(),
-                         F.d_tfoff.as<int64_t>(), F.d_cols.as<int64_t>(), F.d_bcol.as<int>(),
-                         F.slices.as<cpx<T>>(), d_colpos, L, Xp, Yp);
-    }
-    if (precision == GCQ_C128)
-      hipLaunchKernelGGL((perm_out_t<T, double>), dim3(g), dim3(256), 0, st, Yp, (cpx<double>*)Y,
-                         perm, d_conj, n, L);
-    else
-      hipLaunchKernelGGL((perm_out_t<T, float>), dim3(g), dim3(256), 0, st, Yp, (cpx<float>*)Y,
-                         perm, d_conj, n, L);
-  } else {
+  {
     // the weighted sum keeps X unconjugated (the conjugation is applied per slice)
     std::vector<int> zero(L, 0);
     GCQ_TRY(upload(ctx->scratchD, zero, st));
@@ -580,7 +646,7 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
                          perm, ctx->scratchD.as<int>(), n, 1);
   }
   GCQ_HIP(hipGetLastError());
-  timed_end(ctx, mode == GCQ_PER_FREQUENCY ? "matvec_perfreq" : "matvec_wsum");
+  timed_end(ctx, "matvec_wsum");
   return GCQ_OK;
 }
 

@@ -23,11 +23,13 @@ def _problem():
     return xyz, tri, s
 
 
-@pytest.mark.parametrize("prec", [g.C128, g.C64])
-def test_aca_blocks_match_oracle(prec):
+@pytest.mark.parametrize("prec,waves", [(g.C128, 1), (g.C64, 1), (g.C128, 2), (g.C64, 4)])
+def test_aca_blocks_match_oracle(prec, waves):
+    """Also with 2 and 4 waves per (block, frequency) pair."""
     xyz, tri, s = _problem()
     P, T, B, perm, blocks = oracle_tree(xyz, tri, 32, 1.0)
     ctx = make_ctx(xyz, tri, 1.0, s, 32, 1.0)
+    ctx.set_tuning(aca_waves=waves)
     st = ctx.aca_blocks(TOL, 64, prec, g.FLAG_RECOMPRESS)
     rep, conj, K, kpos = kpos_map(s)
     assert st.n_pairs == int(blocks[:, 4].sum()) * len(K)

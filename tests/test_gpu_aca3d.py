@@ -125,3 +125,36 @@ def test_aca3d_group_sizes(setup, waves, stack):
     assert err <= 1e-5, err
     assert same >= 0.9 * nfar
 
+
+
+@pytest.mark.parametrize("prec", [g.C128, g.C64])
+def test_product_graph_replays_match_plain_launches(setup, prec):
+    """The captured product graph, replayed several times with other work and
+    synchronisations in between, gives the plain launches' result every time."""
+    xyz, tri, s, P, T, B, rep, conj, K, kpos, b3 = setup
+    ctx = make_ctx(xyz, tri, 1.0, s, 32, 1.0)
+    ctx.aca3d(TOLA, TOLF, 40, prec)
+    dt = torch.complex128 if prec == g.C128 else torch.complex64
+    X = to_dev(rhs.random_complex(len(s), P.n, 0), prec).reshape(-1)
+    X2 = to_dev(rhs.random_complex(len(s), P.n, 5), prec).reshape(-1)
+    Y0 = torch.zeros(len(s) * P.n, dtype=dt, device="cuda")
+    ctx.set_tuning(product_graph=0)
+    ctx.compressed_matvec(g.PER_FREQUENCY, prec, X, Y0)
+    ref = from_dev(Y0)
+    ref2 = None
+    tol = 1e-12 if prec == g.C128 else 1e-5
+    Y = torch.empty_like(Y0)
+    for rep_i in range(4):
+        ctx.set_tuning(product_graph=1)
+        Y.fill_(7.0)   # the same buffers every time: the same graph is replayed
+        ctx.compressed_matvec(g.PER_FREQUENCY, prec, X, Y)
+        assert rel(from_dev(Y), ref) <= tol, rep_i
+        # eager work between the replays: a plain product on other buffers
+        ctx.set_tuning(product_graph=0)
+        Y2 = torch.zeros_like(Y0)
+        ctx.compressed_matvec(g.PER_FREQUENCY, prec, X2, Y2)
+        y2 = from_dev(Y2)
+        if ref2 is None:
+            ref2 = y2
+        assert rel(y2, ref2) <= tol
+        torch.cuda.synchronize()
