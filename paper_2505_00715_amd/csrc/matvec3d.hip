@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(256) perfreq_tiled(
 //   T = Vbar^H X_J (R x 64), T' = F o T with F[c][k] = f_c[rep(k)],
 //   Y_I += Ubar T'.
 // Per near block: Y_I += sum_d f_d[rep(k)] (D_d X_J)[:, k].
-// Complex products as four real v_mfma_f32_32x32x2f32 (A[i][k] in lane
+// Complex products as three real v_mfma_f32_32x32x2f32 (Gauss's form; A[i][k] in lane
 // i + 32 k, B[k][j] in lane j + 32 k, D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
 // in element r of lane l).  One workgroup of 4 waves per block; T' of up to
 // 128 stacked columns is held in LDS, larger stacks go 128 columns at a time.
@@ -257,6 +257,15 @@ __device__ __forceinline__ mf_v16 mf_zero() {
 }
 __device__ __forceinline__ mf_v16 mfma32(float a, float b, mf_v16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// one step of a complex product A B accumulated with three real products
+// (Gauss): k1 += (a_r + a_i) b_r, k2 += a_r (b_i - b_r), k3 += a_i (b_r + b_i);
+// then Re = k1 - k3, Im = k1 + k2
+__device__ __forceinline__ void gauss3(cpx<float> a, cpx<float> b, mf_v16& k1, mf_v16& k2, mf_v16& k3) {
+  k1 = mfma32(a.re + a.im, b.re, k1);
+  k2 = mfma32(a.re, b.im - b.re, k2);
+  k3 = mfma32(a.im, b.re + b.im, k3);
 }
 
 constexpr int MV_CC = 128;   // stacked columns per LDS chunk of T'
@@ -292,7 +301,7 @@ __global__ void __launch_bounds__(256) perfreq_mfma(
           mf_v16 yr = mf_zero(), yi = mf_zero();
           for (int d = d0; d < d1; ++d) {
             const cpx<float>* D = pool + toff[d];
-            mf_v16 pr = mf_zero(), pi = mf_zero();
+            mf_v16 k1 = mf_zero(), k2 = mf_zero(), k3 = mf_zero();
             for (int j0 = 0; j0 < n; j0 += 2 * MV_KU) {
               // operands of MV_KU steps first, then their products
               cpx<float> a[MV_KU], x[MV_KU];
@@ -303,18 +312,14 @@ __global__ void __launch_bounds__(256) perfreq_mfma(
                 x[u] = (kin && j < n) ? Xp[int64_t(cb + j) * L + kcol] : cpx<float>{0.f, 0.f};
               }
 #pragma unroll
-              for (int u = 0; u < MV_KU; ++u) {
-                pr = mfma32(a[u].re, x[u].re, pr);
-                pr = mfma32(-a[u].im, x[u].im, pr);
-                pi = mfma32(a[u].re, x[u].im, pi);
-                pi = mfma32(a[u].im, x[u].re, pi);
-              }
+              for (int u = 0; u < MV_KU; ++u) gauss3(a[u], x[u], k1, k2, k3);
             }
             const cpx<float> f = kin ? pool[tfoff[d] + kp] : cpx<float>{0.f, 0.f};
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-              yr[r] += f.re * pr[r] - f.im * pi[r];
-              yi[r] += f.re * pi[r] + f.im * pr[r];
+              const float pr = k1[r] - k3[r], pi = k1[r] + k2[r];
+              yr[r] += f.re * pr - f.im * pi;
+              yi[r] += f.re * pi + f.im * pr;
             }
           }
           if (kin) {
@@ -346,22 +351,24 @@ __global__ void __launch_bounds__(256) perfreq_mfma(
           const bool kin = kcol < L;
           const int ca = cc + ti * 32 + lr;   // A row (stacked column) of this lane
           const cpx<float>* Vc = Vst + int64_t(ca) * n;
-          mf_v16 tr = mf_zero(), tim = mf_zero();
+          mf_v16 k1 = mf_zero(), k2 = mf_zero(), k3 = mf_zero();
           for (int j0 = 0; j0 < n; j0 += 2 * MV_KU) {
             cpx<float> v[MV_KU], x[MV_KU];
 #pragma unroll
             for (int u = 0; u < MV_KU; ++u) {
               const int j = j0 + 2 * u + lh;
-              v[u] = (ca < R && j < n) ? Vc[j] : cpx<float>{0.f, 0.f};
+              const cpx<float> vv = (ca < R && j < n) ? Vc[j] : cpx<float>{0.f, 0.f};
+              v[u] = {vv.re, -vv.im};   // conj(v)
               x[u] = (kin && j < n) ? Xp[int64_t(cb + j) * L + kcol] : cpx<float>{0.f, 0.f};
             }
 #pragma unroll
-            for (int u = 0; u < MV_KU; ++u) {   // conj(v) x
-              tr = mfma32(v[u].re, x[u].re, tr);
-              tr = mfma32(v[u].im, x[u].im, tr);
-              tim = mfma32(v[u].re, x[u].im, tim);
-              tim = mfma32(-v[u].im, x[u].re, tim);
-            }
+            for (int u = 0; u < MV_KU; ++u) gauss3(v[u], x[u], k1, k2, k3);
+          }
+          mf_v16 tr, tim;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            tr[r] = k1[r] - k3[r];
+            tim[r] = k1[r] + k2[r];
           }
           const int kp = kin ? colpos[kcol] : 0;
 #pragma unroll
@@ -381,7 +388,7 @@ __global__ void __launch_bounds__(256) perfreq_mfma(
           const int it = tile >> 1, kt = tile & 1;
           const int kcol = kc + kt * 32 + lr;
           const int ia = it * 32 + lr;
-          mf_v16 yr = mf_zero(), yi = mf_zero();
+          mf_v16 k1 = mf_zero(), k2 = mf_zero(), k3 = mf_zero();
           for (int c2 = 0; c2 < ct * 32; c2 += 2 * MV_KU) {
             cpx<float> uu[MV_KU], tt[MV_KU];
 #pragma unroll
@@ -391,12 +398,13 @@ __global__ void __launch_bounds__(256) perfreq_mfma(
               tt[q] = Ts[cl * 64 + kt * 32 + lr];
             }
 #pragma unroll
-            for (int q = 0; q < MV_KU; ++q) {
-              yr = mfma32(uu[q].re, tt[q].re, yr);
-              yr = mfma32(-uu[q].im, tt[q].im, yr);
-              yi = mfma32(uu[q].re, tt[q].im, yi);
-              yi = mfma32(uu[q].im, tt[q].re, yi);
-            }
+            for (int q = 0; q < MV_KU; ++q) gauss3(uu[q], tt[q], k1, k2, k3);
+          }
+          mf_v16 yr, yi;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            yr[r] = k1[r] - k3[r];
+            yi[r] = k1[r] + k2[r];
           }
           if (kcol < L) {
 #pragma unroll
