@@ -91,9 +91,14 @@ __global__ void __launch_bounds__(64) recompress_kernel(const PairDesc* __restri
     const PairDesc d = pairs[pid];
     const int k = rank_in[pid], cap = d.cap;
     cpx<double>* GU = reinterpret_cast<cpx<double>*>(ws + d.ws + ws_gram_off<T>(cap, d.m, d.n));
-    cpx<double>* A = recompress_mats(k) <= 4 * 16 * 16 ? mats
-                             : reinterpret_cast<cpx<double>*>(jws) + int64_t(blockIdx.x) * 4 * 64 * 64;
-    const int t = recompress_wave(k, cap, GU, GU + cap * cap, tol, 0.0, do_recompress != 0, A, rs);
+    // working matrices in LDS when they fit, else in global memory (two call
+    // sites, so that the LDS one compiles to LDS instructions)
+    int t;
+    if (recompress_mats(k) <= 4 * 16 * 16)
+      t = recompress_wave(k, cap, GU, GU + cap * cap, tol, 0.0, do_recompress != 0, mats, rs);
+    else
+      t = recompress_wave(k, cap, GU, GU + cap * cap, tol, 0.0, do_recompress != 0,
+                          reinterpret_cast<cpx<double>*>(jws) + int64_t(blockIdx.x) * 4 * 64 * 64, rs);
     if (threadIdx.x == 0) out_t[pid] = t;
   }
 }

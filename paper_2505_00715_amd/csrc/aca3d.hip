@@ -388,8 +388,13 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
         wflops += e * (7.0 * 20.0 + 8.0 * nres) + 8.0 * (m + n) * 0.5 * double(k) * (k - 1) +
                   2.0 * 8.0 * (m + n) * 0.5 * double(k) * (k - 1);   // residual terms, Gram entries
       }
-      cpx<double>* A = recompress_mats(k) <= recompress_mats(JK) ? sh.mats : jmats;
-      const int t = uni(recompress_grp<NW>(k, cap, GU, GV, tol_aca, nu, true, A, sh.rs));
+      // working matrices in LDS when they fit, else in the workspace (two call
+      // sites, so that the LDS one compiles to LDS instructions)
+      int t;
+      if (recompress_mats(k) <= recompress_mats(JK))
+        t = uni(recompress_grp<NW>(k, cap, GU, GV, tol_aca, nu, true, sh.mats, sh.rs));
+      else
+        t = uni(recompress_grp<NW>(k, cap, GU, GV, tol_aca, nu, true, jmats, sh.rs));
       // the candidate slice goes to the next free stacked columns
       if (nres + t > SH::RES) { status |= ST_ESCALATE; break; }   // needs a larger group
       if (nres + t > S) {
@@ -503,7 +508,11 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       if (tid == 0) sh.term[ell] = cur;
       for (int x = tid; x < t; x += NT) sh.cterm[nres + x] = (unsigned char)ell;
       nres += t;
-      for (int d = tid; d <= ell; d += NT) {
+      // (the empty asm keeps tid * R3_MAX from being kept live across the
+      // whole kernel, which would cost the register that holds two waves per SIMD)
+      int d0 = tid;
+      asm volatile("" : "+v"(d0));
+      for (int d = d0; d <= ell; d += NT) {
         // <H_d, H_l> (d < l) and |H_l|^2
         const cpx<double> h = d < ell ? sh.hin[d] : cpx<double>{nh2, 0.0};
         G3[d * R3_MAX + ell] = h;

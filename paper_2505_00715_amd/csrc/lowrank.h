@@ -285,8 +285,12 @@ __device__ inline int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, do
 // result equals the cyclic sweep in that pair order.  A round is two phases:
 // the rotation parameters, then G^H A G by 2 x 2 blocks (rows of pair i,
 // columns of pair j) together with Q G.
+// Always inlined: callers pass A and Q either in LDS or in global memory, and
+// the accesses compile to LDS instructions only where the pointer's origin is
+// visible.
 template <int NW>
-__device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompShared& rs) {
+__device__ __attribute__((always_inline)) inline void jacobi_grp(cpx<double>* A, cpx<double>* Q,
+                                                                 int k, RecompShared& rs) {
   constexpr int NT = NW * WAVE;
   const int tid = threadIdx.x;
   for (int r = tid; r < k * k; r += NT) Q[r] = {(r / k == r % k) ? 1.0 : 0.0, 0.0};
@@ -294,6 +298,11 @@ __device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompS
   if (k < 2) return;
   const int ke = (k + 1) & ~1;   // even number of positions (one dummy when k is odd)
   const int np = ke / 2;
+  // work items of the update phase: x = row np + j, row < np the 2 x 2 block
+  // (row, j) of A, row >= np row (row - np) of Q with pair j; a thread takes
+  // x = tid, tid + NT, ..., decomposed once and advanced with a carry
+  const int nitems = np * (np + k);
+  const int row0 = tid / np, j0 = tid % np, drow = NT / np, dj = NT % np;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dg = 0.0;
     for (int r = tid; r < k * k; r += NT) {
@@ -306,7 +315,12 @@ __device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompS
     for (int round = 0; round < ke - 1; ++round) {
       if (tid < np) {
         // circle method: position 0 fixed, positions 1..ke-1 rotate
-        auto idx = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (ke - 1); };
+        auto idx = [&](int pos) {
+          if (pos == 0) return 0;
+          int v = pos - 1 + round;   // < 2 (ke - 1)
+          if (v >= ke - 1) v -= ke - 1;
+          return 1 + v;
+        };
         int p = idx(tid), q = idx(ke - 1 - tid);
         if (p > q) { int t = p; p = q; q = t; }
         double c = 1.0, sv = 0.0, a = 0.0, d = 0.0, tb = 0.0;
@@ -338,10 +352,15 @@ __device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompS
         rs.jtb[tid] = tb;
       }
       __syncthreads();
-      for (int x = tid; x < np * np + k * np; x += NT) {
-        if (x < np * np) {
+      int rowc = row0, jc = j0;
+      for (int x = tid; x < nitems; x += NT) {
+        const int row = rowc, j = jc;
+        rowc += drow;
+        jc += dj;
+        if (jc >= np) { jc -= np; ++rowc; }
+        if (row < np) {
           // block (rows of pair i, columns of pair j) of G^H A G
-          const int i = x / np, j = x % np;
+          const int i = row;
           const int pi = rs.jp[i], qi = rs.jq[i], pj = rs.jp[j], qj = rs.jq[j];
           const bool ai = rs.jact[i] != 0, aj = rs.jact[j] != 0;
           if (!ai && !aj) continue;
@@ -385,8 +404,7 @@ __device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompS
           if (qiv && qjv) A[qi * k + qj] = aqq;
         } else {
           // Q G: row r, columns of pair j
-          const int y = x - np * np;
-          const int r = y / np, j = y % np;
+          const int r = row - np;
           if (!rs.jact[j]) continue;
           const int p = rs.jp[j], q = rs.jq[j];
           const double c = rs.jc[j], sv = rs.js[j];
@@ -415,10 +433,11 @@ __device__ inline void jacobi_grp(cpx<double>* A, cpx<double>* Q, int k, RecompS
 //      inverse of R supported on the pivot rows (triangular solve).
 // CU and CV (k x t, leading dimension t) are written over GU and GV.  Without
 // recompression CU = CV = I, t = k.  Returns t.
+// Always inlined, for the reason given at jacobi_grp.
 template <int NW>
-__device__ inline int recompress_grp(int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol,
-                                     double nu, bool do_recompress, cpx<double>* mats,
-                                     RecompShared& rs) {
+__device__ __attribute__((always_inline)) inline int recompress_grp(
+    int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol, double nu, bool do_recompress,
+    cpx<double>* mats, RecompShared& rs) {
   constexpr int NT = NW * WAVE;
   const int tid = threadIdx.x;
   if (k == 0 || !do_recompress) {
@@ -579,7 +598,7 @@ __device__ inline int recompress_grp(int k, int cap, cpx<double>* GU, cpx<double
   return t;
 }
 
-__device__ inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol,
+__device__ __attribute__((always_inline)) inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol,
                                       double nu, bool do_recompress, cpx<double>* mats,
                                       RecompShared& rs) {
   return recompress_grp<1>(k, cap, GU, GV, tol, nu, do_recompress, mats, rs);
