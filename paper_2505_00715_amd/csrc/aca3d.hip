@@ -84,6 +84,7 @@ struct Shared3 {
   cpx<T> fk[R3_MAX];           // f_d[k_cur]
   cpx<T> hp[R3_MAX];           // H_d[i_l, j_l]
   cpx<double> hin[R3_MAX];     // <H_d, H_l>
+  cpx<double> colsum[64];      // per-column sums of the slice inner products
   unsigned usedk[NK_MAX / 32];
   int64_t alloc;
   int idx;
@@ -242,32 +243,61 @@ __device__ inline void lowrank_argmax(const cpx<T>* __restrict__ U, const cpx<T>
   grp_argmax<NW>(best, be);
 }
 
-// <H_d, H_l>_F = sum_{a,b} (U_l^H U_d)[a][b] (V_d^H V_l)[b][a] for factored
-// slices.  Each thread owns up to PP (a, b) pairs per pass and accumulates both
-// factors over the rows, which are staged through LDS R at a time.
-// stage: LDS scratch of 16 KB (2 * 64 * R elements).
+// <H_d, H_l>_F for every accepted slice d and the candidate slice l (d = l
+// included), in one pass over the block's stacked factors.  With
+// P = Ubar_l^H [Ubar_0 .. Ubar_l] and Q = [Vbar_0 .. Vbar_l]^H Vbar_l,
+// <H_d, H_l> = sum over the columns b of slice d and a of slice l of
+// P[a][b] Q[b][a].  Stack columns [0, nres) hold the accepted slices in term
+// order, [nres, nres + t) the candidate.  Pairs (a, b) are taken b-major, up
+// to 64 columns b and PAIRS pairs per pass; each thread accumulates both
+// factors of its pairs over the rows, staged through LDS R rows at a time.
+// The products are then summed per column b and, by thread d, over the
+// columns of slice d.  Writes h[d] (d <= ell, h[ell] = |H_l|^2).
+// stage: LDS scratch of 16 KB; colsum: 64 complex doubles of LDS.
 template <typename T, int NW>
-__device__ inline cpx<double> lowrank_inner(const cpx<T>* __restrict__ Ul, const cpx<T>* __restrict__ Vl,
-                                            int tl, const cpx<T>* __restrict__ Ud,
-                                            const cpx<T>* __restrict__ Vd, int td, int m, int n,
-                                            cpx<T>* stage) {
+__device__ inline void stack_inner(const cpx<T>* __restrict__ Us, const cpx<T>* __restrict__ Vs,
+                                   int m, int n, int nres, int t, int ell, const Term3* terms,
+                                   int64_t sbase, cpx<T>* stage, cpx<double>* colsum,
+                                   cpx<double>* h) {
   constexpr int NT = NW * WAVE;
   constexpr int R = int(128 / sizeof(cpx<T>));   // 16 (float) or 8 (double)
-  constexpr int PP = 4;
+  constexpr int PAIRS = NT * 4 < 1024 ? NT * 4 : 1024;
+  constexpr int PP = PAIRS / NT;
   const int tid = threadIdx.x;
-  cpx<T>* sl = stage;           // [a][r]
-  cpx<T>* sd = stage + 64 * R;  // [b][r]
-  double re = 0.0, im = 0.0;
-  const int npair = tl * td;
-  for (int p0 = 0; p0 < npair; p0 += PP * NT) {
+  cpx<T>* sl = stage;           // [column][r]
+  cpx<T>* sd = stage + 64 * R;  // [column][r]
+  cpx<double>* prod = reinterpret_cast<cpx<double>*>(stage);   // after the row loops
+  const int W = nres + t;
+  const int nbmax = min(64, PAIRS / t);
+  // the columns of this thread's slice d = tid
+  int c_lo = 0, c_hi = 0;
+  if (tid < ell) {
+    c_lo = int((terms[tid].slice - sbase) / m);
+    c_hi = c_lo + terms[tid].rank;
+  } else if (tid == ell) {
+    c_lo = nres;
+    c_hi = W;
+  }
+  double hr = 0.0, hi = 0.0;
+  const cpx<T>* Ul = Us + int64_t(nres) * m;
+  const cpx<T>* Vl = Vs + int64_t(nres) * n;
+  for (int b0 = 0; b0 < W; b0 += nbmax) {
+    const int nb = min(nbmax, W - b0);
+    const int npair = nb * t;
     double pr[PP], pi[PP], qr[PP], qi[PP];
+    int pb[PP], pa[PP];
 #pragma unroll
-    for (int q = 0; q < PP; ++q) pr[q] = pi[q] = qr[q] = qi[q] = 0.0;
+    for (int q = 0; q < PP; ++q) {
+      pr[q] = pi[q] = qr[q] = qi[q] = 0.0;
+      const int p = q * NT + tid;
+      pb[q] = p / t;
+      pa[q] = p % t;
+    }
     for (int side = 0; side < 2; ++side) {
       const int len = side == 0 ? m : n;
-      const cpx<T>* X = side == 0 ? Ul : Vd;   // conjugated operand
-      const cpx<T>* Y = side == 0 ? Ud : Vl;
-      const int tx = side == 0 ? tl : td, ty = side == 0 ? td : tl;
+      const cpx<T>* X = side == 0 ? Ul : Vs + int64_t(b0) * n;   // conjugated operand
+      const cpx<T>* Y = side == 0 ? Us + int64_t(b0) * m : Vl;
+      const int tx = side == 0 ? t : nb, ty = side == 0 ? nb : t;
       for (int r0 = 0; r0 < len; r0 += R) {
         const int rn = min(R, len - r0);
         __syncthreads();
@@ -282,10 +312,8 @@ __device__ inline cpx<double> lowrank_inner(const cpx<T>* __restrict__ Ul, const
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PP; ++q) {
-          const int p = p0 + q * NT + tid;
-          if (p < npair) {
-            const int a = p / td, b = p % td;
-            const int ax = side == 0 ? a : b, ay = side == 0 ? b : a;
+          if (q * NT + tid < npair) {
+            const int ax = side == 0 ? pa[q] : pb[q], ay = side == 0 ? pb[q] : pa[q];
             double sr = 0.0, si = 0.0;
 #pragma unroll 4
             for (int r = 0; r < R; ++r) {
@@ -298,15 +326,31 @@ __device__ inline cpx<double> lowrank_inner(const cpx<T>* __restrict__ Ul, const
         }
       }
     }
+    __syncthreads();   // the staging area becomes the product array
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
-      re += pr[q] * qr[q] - pi[q] * qi[q];
-      im += pr[q] * qi[q] + pi[q] * qr[q];
+      const int p = q * NT + tid;
+      if (p < npair) prod[p] = {pr[q] * qr[q] - pi[q] * qi[q], pr[q] * qi[q] + pi[q] * qr[q]};
+    }
+    __syncthreads();
+    if (tid < nb) {
+      double sr = 0.0, si = 0.0;
+      for (int a = 0; a < t; ++a) {
+        const cpx<double> v = prod[tid * t + a];
+        sr += v.re;
+        si += v.im;
+      }
+      colsum[tid] = {sr, si};
+    }
+    __syncthreads();
+    const int lo = max(c_lo, b0), hi2 = min(c_hi, b0 + nb);
+    for (int c = lo; c < hi2; ++c) {
+      hr += colsum[c - b0].re;
+      hi += colsum[c - b0].im;
     }
   }
+  if (tid <= ell) h[tid] = {hr, hi};
   __syncthreads();
-  grp_sum2<NW>(re, im);
-  return {re, im};
 }
 
 // 3D-ACA of admissible blocks, NW waves per block.  ALLFAR = true: blocks
@@ -344,7 +388,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
     cpx<double>* GV = GU + cap * cap;
     cpx<double>* jmats = reinterpret_cast<cpx<double>*>(myws + ws_bytes<T>(cap, m, n));
     cpx<double>* G3 = jmats + 4 * 64 * 64;
-    for (int w = tid; w < (nK + 31) / 32; w += NT) sh.usedk[w] = 0u;
+    for (int w = opaque_tid(); w < (nK + 31) / 32; w += NT) sh.usedk[w] = 0u;
     // the block's stacked slice factors: U (m x S) then V (n x S)
     int S = B.sres;
     if (tid == 0) sh.alloc = pool_alloc(cursor, int64_t(m + n) * S, capacity);
@@ -353,7 +397,8 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
     int ell = 0, kcur = 0, status = 0, nres = 0;
     double norm2 = 0.0;
     // algorithmic work of this block: entries and operations (see gcq_aca3d_stats)
-    double wentries = 0.0, wflops = 0.0;
+    // (integers of wave-uniform values, so that they stay in scalar registers)
+    int64_t wentries = 0, wflops = 0;
     if (sbase < 0) status |= ST_DEFERRED;
     cpx<T>* Us = pool + (sbase < 0 ? 0 : sbase);
     cpx<T>* Vs = Us + int64_t(S) * m;
@@ -383,10 +428,10 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       if (ast & ST_CAPPED) status |= ST_CAPPED;
       {
         // rows (length n) and columns (length m) with their residual sums
-        const double e = double(sh.aca.nrows) * n + double(k) * m;
+        const int64_t e = int64_t(uni(sh.aca.nrows)) * n + int64_t(k) * m;
         wentries += e;
-        wflops += e * (7.0 * 20.0 + 8.0 * nres) + 8.0 * (m + n) * 0.5 * double(k) * (k - 1) +
-                  2.0 * 8.0 * (m + n) * 0.5 * double(k) * (k - 1);   // residual terms, Gram entries
+        // residual terms; Gram entries (8 (m + n) per pair, twice: k (k - 1) / 2 pairs)
+        wflops += e * (7 * 20 + 8 * int64_t(nres)) + 12 * int64_t(m + n) * k * (k - 1);
       }
       // working matrices in LDS when they fit, else in the workspace (two call
       // sites, so that the LDS one compiles to LDS instructions)
@@ -430,7 +475,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       cur.rank = t;
       cur.freq = kcur;
       // ---- pivot: largest modulus, first in row-major order on ties
-      wflops += 8.0 * (double(t) * (m + n) * k + double(m) * n * t);   // apply, expansion
+      wflops += 8 * (int64_t(t) * (m + n) * k + int64_t(m) * n * t);   // apply, expansion
       double best;
       int be;
       lowrank_argmax<T, NW>(pool + cur.slice, pool + cur.vslice, m, n, t, best, be,
@@ -447,11 +492,11 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       cur.fiber = foff;
       // ---- fiber over K
       wentries += nK;
-      wflops += double(nK) * (7.0 * 20.0 + 8.0 * ell);
+      wflops += int64_t(nK) * (7 * 20 + 8 * ell);
       {
-        double tt = double(t);
+        int tt = t;
         for (int d = 0; d < ell; ++d) tt += sh.term[d].rank;
-        wflops += 8.0 * double(t) * tt * (m + n) + 8.0 * double(nK) * ell;   // inner products
+        wflops += 8 * int64_t(t) * uni(tt) * (m + n) + 8 * int64_t(nK) * ell;   // inner products
       }
       const cpx<T> inv = cinv(piv);
       double nf2 = 0.0;
@@ -470,23 +515,9 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       __syncthreads();
       nf2 = unid(grp_sum<NW>(nf2));
       // ---- eq. norm: <H_d, H_l> = tr((U_l^H U_d)(V_d^H V_l)), |H_l|^2 with d = l
-      double nh2 = 0.0;
-      {
-        const cpx<T>* Ul = pool + cur.slice;
-        const cpx<T>* Vl = pool + cur.vslice;
-        cpx<T>* stage = reinterpret_cast<cpx<T>*>(sh.mats);
-        for (int d = 0; d <= ell; ++d) {
-          const Term3 td = d < ell ? sh.term[d] : cur;
-          const cpx<double> h =
-              lowrank_inner<T, NW>(Ul, Vl, t, pool + td.slice, pool + td.vslice, td.rank, m, n, stage);
-          if (d < ell) {
-            if (tid == 0) sh.hin[d] = h;
-          } else {
-            nh2 = unid(h.re);
-          }
-        }
-      }
-      __syncthreads();
+      stack_inner<T, NW>(Us, Vs, m, n, nres, t, ell, sh.term, sbase, reinterpret_cast<cpx<T>*>(sh.mats),
+                         sh.colsum, sh.hin);
+      const double nh2 = unid(sh.hin[ell].re);
       // <f_d, f_l> = sum f_d conj(f_l), slice d by wave d mod NW
       double crossw = 0.0;
       for (int d = wid; d < ell; d += NW) {
@@ -508,11 +539,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       if (tid == 0) sh.term[ell] = cur;
       for (int x = tid; x < t; x += NT) sh.cterm[nres + x] = (unsigned char)ell;
       nres += t;
-      // (the empty asm keeps tid * R3_MAX from being kept live across the
-      // whole kernel, which would cost the register that holds two waves per SIMD)
-      int d0 = tid;
-      asm volatile("" : "+v"(d0));
-      for (int d = d0; d <= ell; d += NT) {
+      for (int d = opaque_tid(); d <= ell; d += NT) {
         // <H_d, H_l> (d < l) and |H_l|^2
         const cpx<double> h = d < ell ? sh.hin[d] : cpx<double>{nh2, 0.0};
         G3[d * R3_MAX + ell] = h;
@@ -523,7 +550,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       // next frequency: largest |f_l[k]| among unused k (lowest k on ties)
       double bf = -1.0;
       int bk = 0x7fffffff;
-      for (int kk = tid; kk < nK; kk += NT) {
+      for (int kk = opaque_tid(); kk < nK; kk += NT) {
         if ((sh.usedk[kk >> 5] >> (kk & 31)) & 1u) continue;
         double v = mag2(pool[foff + kk]);
         if (v > bf) { bf = v; bk = kk; }
@@ -537,7 +564,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       kcur = bk;
     }
     __syncthreads();
-    for (int d = tid; d < ell; d += NT) terms[int64_t(b) * R3_MAX + d] = sh.term[d];
+    for (int d = opaque_tid(); d < ell; d += NT) terms[int64_t(b) * R3_MAX + d] = sh.term[d];
     if (tid == 0) {
       brank[b] = ell;
       bstatus[b] = status;

@@ -459,6 +459,15 @@ __device__ __forceinline__ cpx<T> entry_part(const Tab& t, int pi, int pj, doubl
   return far_entry_part<T>(t, c[pi], c[n + pi], c[2 * n + pi], pj, T(sr), T(si), p, P);
 }
 
+// threadIdx.x hidden from loop-invariant code motion: address arithmetic
+// derived from it stays next to its use instead of holding a register across
+// an enclosing persistent loop (the empty asm emits no instruction)
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // lanes per entry when a row of len entries is spread over nt threads: the
 // largest power of two <= 8 that still gives every entry its own lanes
 __device__ __forceinline__ int split_lanes(int nt, int len) {

@@ -62,6 +62,48 @@ struct RecompShared {
 // working memory of the recompression of k terms (complex doubles)
 __host__ __device__ inline int recompress_mats(int k) { return 3 * k * k; }
 
+// The reductions that end an ACA step, in one exchange: group sums of a and b
+// (per-thread partials), of c (a value each wave already holds summed), and
+// the group argmax of (val, idx) (largest val, lowest idx on ties).  Waves
+// are combined in wave order, so the results do not depend on timing.  The
+// exchange slots are this function's own; the barriers between two calls of
+// one ACA step keep their readers apart.
+template <int NW>
+__device__ __forceinline__ void grp_step_reduce(double& a, double& b, double& c, double& val,
+                                                int& idx) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  wave_argmax(val, idx);
+  if constexpr (NW > 1) {
+    __shared__ double ra[NW], rb[NW], rc[NW], rv[NW];
+    __shared__ int ri[NW];
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+      const int w = threadIdx.x / WAVE;
+      ra[w] = a;
+      rb[w] = b;
+      rc[w] = c;
+      rv[w] = val;
+      ri[w] = idx;
+    }
+    __syncthreads();
+    a = ra[0];
+    b = rb[0];
+    c = rc[0];
+    val = rv[0];
+    idx = ri[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      a += ra[w];
+      b += rb[w];
+      c += rc[w];
+      if (rv[w] > val || (rv[w] == val && ri[w] < idx)) {
+        val = rv[w];
+        idx = ri[w];
+      }
+    }
+  }
+}
+
 // ---- ACA of an entry function --------------------------------------------------
 // Ent: prep_row(i) / prep_col(j) (group-collective, may be empty) and
 // part(i, j, p, P) -> cpx<T>, part p of P of the entry (i, j), the parts of
@@ -210,9 +252,6 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
       }
     }
     __syncthreads();
-    grp_sum2<NW>(nw2, nu2);
-    nw2 = unid(nw2);
-    nu2 = unid(nu2);
     // Gram entries of the new term: entry l by wave l mod NW
     double crossw = 0.0;
     for (int l = wid; l < k; l += NW) {
@@ -240,7 +279,12 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
         GV[k * cap + l] = {gwr, gwi};
       }
     }
-    const double cross = unid(grp_sum<NW>(lane == 0 ? crossw : 0.0));
+    // one exchange for |w_k|^2, |u_k|^2, the cross terms and the next row
+    grp_step_reduce<NW>(nw2, nu2, crossw, bestu, bi);
+    nw2 = unid(nw2);
+    nu2 = unid(nu2);
+    const double cross = unid(crossw);
+    bi = uni(bi);
     if (tid == 0) {
       GU[k * cap + k] = {nu2, 0.0};
       GV[k * cap + k] = {nw2, 0.0};
@@ -251,8 +295,6 @@ __device__ int aca_grp(Ent& ent, int m, int n, int cap, int max_rank, double tol
       status |= ST_CONVERGED;
       break;
     }
-    grp_argmax<NW>(bestu, bi);
-    bi = uni(bi);
     if (nused >= m || bi == 0x7fffffff) { status |= ST_EXACT; break; }
     i = bi;
   }
@@ -459,27 +501,35 @@ __device__ __attribute__((always_inline)) inline int recompress_grp(
   }
   if (tid < k) rs.keep[tid] = 0;   // eliminated flags
   __syncthreads();
-  if (tid == 0) {
+  if (tid < WAVE) {   // largest diagonal, by wave 0
     double d0 = 0.0;
-    for (int a = 0; a < k; ++a) d0 = fmax(d0, S[a * k + a].re);
-    rs.dmax = d0;
+    for (int a = tid; a < k; a += WAVE) d0 = fmax(d0, S[a * k + a].re);
+    int dummy = 0;
+    wave_argmax(d0, dummy);
+    if (tid == 0) rs.dmax = d0;
   }
   __syncthreads();
   const double dlim = 1e-14 * unid(rs.dmax);
   int r = 0;
   for (; r < k; ++r) {
-    // pivot: largest remaining diagonal (lowest index on ties)
-    if (tid == 0) {
-      int p = -1;
-      double best = 0.0;
-      for (int a = 0; a < k; ++a)
-        if (!rs.keep[a] && S[a * k + a].re > best) { best = S[a * k + a].re; p = a; }
-      if (p >= 0 && best > dlim && best > 0.0) {
-        rs.nkeep = p;
-        rs.keep[p] = 1;
-        rs.order[r] = p;   // pivot of row r
-      } else {
-        rs.nkeep = -1;
+    // pivot: largest remaining diagonal (lowest index on ties), by wave 0
+    if (tid < WAVE) {
+      double best = -1.0;
+      int p = 0x7fffffff;
+      for (int a = tid; a < k; a += WAVE) {
+        if (rs.keep[a]) continue;
+        const double v = S[a * k + a].re;
+        if (v > best) { best = v; p = a; }
+      }
+      wave_argmax(best, p);
+      if (tid == 0) {
+        if (p != 0x7fffffff && best > dlim && best > 0.0) {
+          rs.nkeep = p;
+          rs.keep[p] = 1;
+          rs.order[r] = p;   // pivot of row r
+        } else {
+          rs.nkeep = -1;
+        }
       }
     }
     __syncthreads();
