@@ -189,8 +189,10 @@ struct Consts {
 
 // ---- panel table (cluster-permuted order, structure of arrays) --------------
 // q64/q32 hold 28 arrays of n: qx[7], qy[7], qz[7], qw[7]; qw already
-// includes the panel area and 1/(4 pi).  c32/q32 are coordinates relative to
-// the mesh centre (`shift`), in float.
+// includes the panel area and 1/(4 pi).  c32/q32/q4 are coordinates relative to
+// the mesh centre (`shift`), in float.  q4 holds the same float points as 7
+// arrays of n (x, y, z, w) quadruples, point-major, so that one 16-byte load
+// per point brings all four and consecutive panels stay contiguous.
 struct Tab {
   int n;
   const double* cen;   // 3n: x[], y[], z[]
@@ -200,6 +202,7 @@ struct Tab {
   const double* q64;   // 28n
   const float* c32;    // 3n
   const float* q32;    // 28n
+  const float4* q4;    // 7n: (x, y, z, w) of point a of panel p at a n + p
   const Consts* K;
 };
 
@@ -260,17 +263,18 @@ __device__ __forceinline__ cpx<T> far_entry(const Tab& t, T xi, T yi, T zi, int 
 template <>
 __device__ __forceinline__ cpx<float> far_entry<float>(const Tab& t, float xi, float yi, float zi,
                                                        int pj, float sr, float si) {
-  const float* q = t.q32;
+  const float4* q = t.q4;
   const int n = t.n;
   const float a2 = -sr * 1.44269504088896340736f;   // -sr log2(e)
   const float rv = si * 0.159154943091895335769f;   // si / (2 pi)
   float ar = 0.f, ai = 0.f;
 #pragma unroll
   for (int a = 0; a < NQ_FAR; ++a) {
-    const float dx = xi - q[(a)*n + pj];
-    const float dy = yi - q[(7 + a) * n + pj];
-    const float dz = zi - q[(14 + a) * n + pj];
-    const float w = q[(21 + a) * n + pj];
+    const float4 qa = q[a * n + pj];
+    const float dx = xi - qa.x;
+    const float dy = yi - qa.y;
+    const float dz = zi - qa.z;
+    const float w = qa.w;
     const float r2 = dx * dx + dy * dy + dz * dz;
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ri;
@@ -421,16 +425,17 @@ __device__ __forceinline__ cpx<T> far_entry_part(const Tab& t, T xi, T yi, T zi,
 template <>
 __device__ __forceinline__ cpx<float> far_entry_part<float>(const Tab& t, float xi, float yi, float zi,
                                                             int pj, float sr, float si, int p, int P) {
-  const float* q = t.q32;
+  const float4* q = t.q4;
   const int n = t.n;
   const float a2 = -sr * 1.44269504088896340736f;   // -sr log2(e)
   const float rv = si * 0.159154943091895335769f;   // si / (2 pi)
   float ar = 0.f, ai = 0.f;
   for (int a = p; a < NQ_FAR; a += P) {
-    const float dx = xi - q[(a)*n + pj];
-    const float dy = yi - q[(7 + a) * n + pj];
-    const float dz = zi - q[(14 + a) * n + pj];
-    const float w = q[(21 + a) * n + pj];
+    const float4 qa = q[a * n + pj];
+    const float dx = xi - qa.x;
+    const float dy = yi - qa.y;
+    const float dz = zi - qa.z;
+    const float w = qa.w;
     const float r2 = dx * dx + dy * dy + dz * dz;
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float r = r2 * ri;

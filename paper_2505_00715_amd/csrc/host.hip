@@ -483,7 +483,7 @@ GCQ_API int gcq_build_cluster_tree(gcq_context* ctx, int32_t leaf_size, double e
   // ---- device panel tables in permuted order
   std::vector<double> cen_p(3 * size_t(n)), h2_p(n), vert_p(9 * size_t(n)), area_p(n),
       q64(28 * size_t(n));
-  std::vector<float> c32(3 * size_t(n)), q32(28 * size_t(n));
+  std::vector<float> c32(3 * size_t(n)), q32(28 * size_t(n)), q4(28 * size_t(n));
   double rb[7][3], rw[7];
   radon7(rb, rw);
   for (int p = 0; p < n; ++p) {
@@ -501,10 +501,12 @@ GCQ_API int gcq_build_cluster_tree(gcq_context* ctx, int32_t leaf_size, double e
         double x = rb[a][0] * v[k] + rb[a][1] * v[3 + k] + rb[a][2] * v[6 + k];
         q64[(7 * k + a) * size_t(n) + p] = x;
         q32[(7 * k + a) * size_t(n) + p] = float(x - ctx->shift[k]);
+        q4[4 * (a * size_t(n) + p) + k] = float(x - ctx->shift[k]);
       }
       double w = rw[a] * ctx->area[t] * INV4PI;
       q64[(21 + a) * size_t(n) + p] = w;
       q32[(21 + a) * size_t(n) + p] = float(w);
+      q4[4 * (a * size_t(n) + p) + 3] = float(w);
     }
   }
   std::vector<int32_t> blk(5 * ctx->blocks.size());
@@ -525,6 +527,7 @@ GCQ_API int gcq_build_cluster_tree(gcq_context* ctx, int32_t leaf_size, double e
   GCQ_TRY(upload(ctx->d_q64, q64, st));
   GCQ_TRY(upload(ctx->d_c32, c32, st));
   GCQ_TRY(upload(ctx->d_q32, q32, st));
+  GCQ_TRY(upload(ctx->d_q4, q4, st));
   std::vector<int32_t> perm32(ctx->perm.begin(), ctx->perm.end());
   std::vector<int32_t> iperm32(ctx->iperm.begin(), ctx->iperm.end());
   GCQ_TRY(upload(ctx->d_perm, perm32, st));
