@@ -136,7 +136,7 @@ struct ResidualEntry {
     const cpx<T>* q = sh->coef;
     if (rowmode) {
       const cpx<T>* V = Vs + j;
-#pragma unroll 8
+#pragma unroll 12
       for (int x = p; x < nres; x += P) {
         const cpx<T> v = V[int64_t(x) * n], c = q[x];
         ar += c.re * v.re + c.im * v.im;   // c conj(v)
@@ -144,7 +144,7 @@ struct ResidualEntry {
       }
     } else {
       const cpx<T>* U = Us + i;
-#pragma unroll 8
+#pragma unroll 12
       for (int x = p; x < nres; x += P) {
         const cpx<T> u = U[int64_t(x) * m], c = q[x];
         ar += u.re * c.re - u.im * c.im;
