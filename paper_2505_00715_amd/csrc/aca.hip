@@ -148,9 +148,7 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
   rank_out.assign(np, 0);
   status.assign(np, 0);
   out_off.assign(np, -1);
-  int dev_cus = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) dev_cus = prop.multiProcessorCount;
+  const int dev_cus = ctx->cus;
   // chunks in work-list order, each within the workspace budget
   size_t pos = 0;
   std::vector<int64_t> pend_off;

@@ -734,6 +734,14 @@ static __global__ void zero_int_3d(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// the accepted terms of every block, compacted: out[tb[b] + d] = terms[b R3_MAX + d]
+static __global__ void gather_terms(const Term3* __restrict__ terms, const int* __restrict__ brank,
+                                    const int* __restrict__ tb, int nb, Term3* __restrict__ out) {
+  for (int b = blockIdx.x; b < nb; b += gridDim.x)
+    for (int d = threadIdx.x; d < brank[b]; d += blockDim.x)
+      out[tb[b] + d] = terms[int64_t(b) * R3_MAX + d];
+}
+
 // launch of the far kernel with NW waves per block
 template <typename T, bool AF, typename... Args>
 static void launch_far(int nw, int grid, hipStream_t st, Args... args) {
@@ -819,9 +827,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
     return ((precision == GCQ_C128 ? ws_bytes<double>(aca_cap, mn, 0) : ws_bytes<float>(aca_cap, mn, 0)) +
             int64_t(4) * 64 * 64 * 16 + int64_t(R3_MAX) * R3_MAX * 16 + 4095) & ~int64_t(4095);
   };
-  int cus = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
+  const int cus = ctx->cus;
   GCQ_TRY(ensure_side_streams(ctx));
   // waves per admissible block, by size class (tuning table); doubled for a
   // block whose residual stack outgrows its group
@@ -844,10 +850,12 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   const int64_t rexp = std::max(8, int(max_freq_rank) / 2 + 4);
   int64_t want = near_elems * rexp + far_stack + int64_t(nb) * rexp * nK;
   int64_t capacity = std::min<int64_t>(want, int64_t(double(freeb) * 0.5) / csz);
-  F.slices.release();
+  // the pool of an earlier call is reused (its contents are rebuilt); it only
+  // grows when this operator needs more
   GCQ_TRY(F.slices.ensure(size_t(capacity) * csz + 256));
+  capacity = std::max<int64_t>(capacity, int64_t((F.slices.bytes - 256) / csz));
   std::vector<int32_t> blkrank(nb), blkstat(nb);
-  std::vector<Term3> terms(size_t(nb) * R3_MAX);
+  std::vector<Term3> terms;
   GCQ_TRY(upload(ctx->scratchB, bd, ctx->stream));
   GCQ_TRY(upload(ctx->scratchC, sig, ctx->stream));
   // scratch layout: cursor (8 B), 16 work counters, terms, ranks, status, work order
@@ -868,13 +876,8 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   std::vector<int> near_pos(nb, -1);
   for (size_t q = 0; q < ctx->near_ids.size(); ++q) near_pos[ctx->near_ids[q]] = int(q);
   // element offsets of the self/near-tier entries, for batching
-  std::vector<int64_t> sing_off(ctx->n_sing);
-  if (ctx->n_sing > 0) {
-    std::vector<SingEntry> sl(ctx->n_sing);
-    GCQ_HIP(hipMemcpy(sl.data(), ctx->d_sing.p, sizeof(SingEntry) * ctx->n_sing, hipMemcpyDeviceToHost));
-    for (int64_t a = 0; a < ctx->n_sing; ++a) sing_off[a] = sl[a].off;
-  }
-  DevBuf tensor;
+  const std::vector<int64_t>& sing_off = ctx->sing_off;
+  DevBuf& tensor = ctx->scratchT;
   const int64_t tensor_budget = std::max<int64_t>(int64_t(1) << 28,
                                                   std::min<int64_t>(int64_t(48) << 30, int64_t(double(freeb) * 0.25)));
   hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, reinterpret_cast<int*>(d_work), 4);
@@ -1048,7 +1051,21 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
     todo.swap(again);
   }
   if (!todo.empty()) return fail(GCQ_ERR_NOMEM, "3D-ACA pool could not hold the result");
-  GCQ_HIP(hipMemcpy(terms.data(), d_terms, sizeof(Term3) * terms.size(), hipMemcpyDeviceToHost));
+  // download the accepted terms only (compacted on the device)
+  std::vector<int32_t> tb(nb + 1, 0);
+  for (int b = 0; b < nb; ++b) tb[b + 1] = tb[b] + blkrank[b];
+  {
+    DevBuf d_tb, d_compact;
+    GCQ_TRY(upload(d_tb, tb, ctx->stream));
+    GCQ_TRY(d_compact.ensure(sizeof(Term3) * size_t(std::max(tb[nb], 1))));
+    hipLaunchKernelGGL(gather_terms, dim3(std::min(nb, 65536)), dim3(64), 0, ctx->stream, d_terms, d_rank,
+                       d_tb.as<int>(), nb, d_compact.as<Term3>());
+    GCQ_HIP(hipGetLastError());
+    terms.resize(size_t(tb[nb]));
+    GCQ_HIP(hipMemcpyAsync(terms.data(), d_compact.p, sizeof(Term3) * terms.size(), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    GCQ_HIP(hipStreamSynchronize(ctx->stream));
+  }
   ctx->kernel_ms["aca3d"] = ms;
   ctx->kernel_ms["aca3d_far"] = ms_far;
   ctx->kernel_ms["aca3d_near"] = ms_near;
@@ -1069,7 +1086,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
     F.bterm[b] = nt;
     ncap += (blkstat[b] & ST_CAPPED) != 0;
     for (int d = 0; d < F.brank[b]; ++d) {
-      const Term3& t = terms[size_t(b) * R3_MAX + d];
+      const Term3& t = terms[size_t(tb[b]) + d];
       F.tfreq.push_back(t.freq);
       F.trank.push_back(t.rank);
       F.toff.push_back(t.slice);
@@ -1091,6 +1108,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   {
     // product tables: stacked far columns and the block order of the product
     std::vector<int64_t> cols;
+    cols.reserve(3 * size_t(slice_rank_sum));
     std::vector<int32_t> bcol(nb + 1, 0);
     std::vector<double> work(nb, 0.0);
     for (int b = 0; b < nb; ++b) {

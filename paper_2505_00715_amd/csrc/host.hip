@@ -557,6 +557,8 @@ GCQ_API int gcq_build_cluster_tree(gcq_context* ctx, int32_t leaf_size, double e
     }
     ctx->near_total = acc;
     ctx->n_sing = int64_t(sing.size());
+    ctx->sing_off.resize(sing.size());
+    for (size_t a = 0; a < sing.size(); ++a) ctx->sing_off[a] = sing[a].off;
     std::vector<int32_t> nid(ctx->near_ids.begin(), ctx->near_ids.end());
     GCQ_TRY(upload(ctx->d_near_off, ctx->near_off, st));
     GCQ_TRY(upload(ctx->d_near_ids, nid, st));

@@ -205,6 +205,7 @@ struct gcq_context {
   std::vector<int64_t> near_off;
   int64_t near_total = 0;
   int64_t n_sing = 0;
+  std::vector<int64_t> sing_off;             // element offset of each listed entry (host copy)
   gcq::DevBuf d_near_off, d_near_ids, d_sing;
 
   // device tables (permuted order)
@@ -217,6 +218,7 @@ struct gcq_context {
 
   // scratch
   gcq::DevBuf scratchA, scratchB, scratchC, scratchD;
+  gcq::DevBuf scratchT;                      // entry tensor of the inadmissible blocks (3D-ACA)
 
   gcq::Tab tab() const {
     gcq::Tab t;
