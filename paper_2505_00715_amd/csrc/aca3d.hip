@@ -742,6 +742,29 @@ static __global__ void gather_terms(const Term3* __restrict__ terms, const int* 
       out[tb[b] + d] = terms[int64_t(b) * R3_MAX + d];
 }
 
+// product table of the stacked far columns: column x of block b's stack
+// (b's far terms in order, bcol[b] the first) gets its Ubar column, Vbar
+// column and fiber offsets
+static __global__ void build_cols(const int* __restrict__ blk, const int* __restrict__ bterm,
+                                  const int* __restrict__ trank, const int64_t* __restrict__ toff,
+                                  const int64_t* __restrict__ tvoff, const int64_t* __restrict__ tfoff,
+                                  const int* __restrict__ bcol, int nb, int64_t* __restrict__ cols) {
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int m = blk[5 * b + 1] - blk[5 * b], n = blk[5 * b + 3] - blk[5 * b + 2];
+    int64_t c = bcol[b];
+    for (int d = bterm[b]; d < bterm[b + 1]; ++d) {
+      const int r = trank[d];
+      if (r < 0) continue;   // dense slice of an inadmissible block
+      for (int x = threadIdx.x; x < r; x += blockDim.x) {
+        cols[3 * (c + x)] = toff[d] + int64_t(x) * m;
+        cols[3 * (c + x) + 1] = tvoff[d] + int64_t(x) * n;
+        cols[3 * (c + x) + 2] = tfoff[d];
+      }
+      c += r;
+    }
+  }
+}
+
 // launch of the far kernel with NW waves per block
 template <typename T, bool AF, typename... Args>
 static void launch_far(int nw, int grid, hipStream_t st, Args... args) {
@@ -1106,41 +1129,42 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   GCQ_TRY(upload(F.d_tvoff, F.tvoff, ctx->stream));
   GCQ_TRY(upload(F.d_tfoff, F.tfoff, ctx->stream));
   {
-    // product tables: stacked far columns and the block order of the product
-    std::vector<int64_t> cols;
-    cols.reserve(3 * size_t(slice_rank_sum));
+    // product tables: stacked far columns (built on the device) and the block
+    // order of the product
     std::vector<int32_t> bcol(nb + 1, 0);
     std::vector<double> work(nb, 0.0);
     for (int b = 0; b < nb; ++b) {
-      bcol[b] = int32_t(cols.size() / 3);
+      int cnt = 0;
+      int64_t nextu = -1, nextv = -1;
       for (int d = 0; d < F.brank[b]; ++d) {
         const int ti = F.bterm[b] + d;
         if (F.trank[ti] < 0) {
           work[b] += double(bd[b].m) * bd[b].n;
           continue;
         }
-        for (int c = 0; c < F.trank[ti]; ++c) {
-          cols.push_back(F.toff[ti] + int64_t(c) * bd[b].m);                                    // Ubar col
-          cols.push_back(F.tvoff[ti] + int64_t(c) * bd[b].n);                                   // Vbar col
-          cols.push_back(F.tfoff[ti]);
-          work[b] += bd[b].m + bd[b].n;
-        }
-      }
-    }
-    bcol[nb] = int32_t(cols.size() / 3);
-    // the product reads a far block's stacked columns as one m x R and one n x R matrix
-    for (int b = 0; b < nb; ++b)
-      for (int c = bcol[b] + 1; c < bcol[b + 1]; ++c)
-        if (cols[3 * c] != cols[3 * (c - 1)] + bd[b].m || cols[3 * c + 1] != cols[3 * (c - 1) + 1] + bd[b].n)
+        // the product reads a far block's stacked columns as one m x R and one n x R matrix
+        if (nextu >= 0 && (F.toff[ti] != nextu || F.tvoff[ti] != nextv))
           return fail(GCQ_ERR_STATE, "block %d: slice factors are not stacked", b);
+        nextu = F.toff[ti] + int64_t(F.trank[ti]) * bd[b].m;
+        nextv = F.tvoff[ti] + int64_t(F.trank[ti]) * bd[b].n;
+        cnt += F.trank[ti];
+        work[b] += double(F.trank[ti]) * (bd[b].m + bd[b].n);
+      }
+      bcol[b + 1] = bcol[b] + cnt;
+    }
     std::vector<int32_t> mo;
     for (int b = 0; b < nb; ++b)
       if (F.brank[b] > 0) mo.push_back(b);
     std::stable_sort(mo.begin(), mo.end(), [&](int a, int b) { return work[a] > work[b]; });
     F.n_mvblocks = int(mo.size());
-    GCQ_TRY(upload(F.d_cols, cols, ctx->stream));
     GCQ_TRY(upload(F.d_bcol, bcol, ctx->stream));
     GCQ_TRY(upload(F.d_mvorder, mo, ctx->stream));
+    GCQ_TRY(F.d_cols.ensure(sizeof(int64_t) * 3 * size_t(std::max(bcol[nb], 1))));
+    hipLaunchKernelGGL(build_cols, dim3(std::min(nb, 65536)), dim3(64), 0, ctx->stream, ctx->d_blk.as<int>(),
+                       F.d_bterm.as<int>(), F.d_trank.as<int>(), F.d_toff.as<int64_t>(),
+                       F.d_tvoff.as<int64_t>(), F.d_tfoff.as<int64_t>(), F.d_bcol.as<int>(), nb,
+                       F.d_cols.as<int64_t>());
+    GCQ_HIP(hipGetLastError());
   }
   GCQ_HIP(hipStreamSynchronize(ctx->stream));
   F.storage_bytes = store * csz;
