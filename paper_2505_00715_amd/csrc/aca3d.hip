@@ -904,6 +904,11 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   const int64_t tensor_budget = std::max<int64_t>(int64_t(1) << 28,
                                                   std::min<int64_t>(int64_t(48) << 30, int64_t(double(freeb) * 0.25)));
   hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, reinterpret_cast<int*>(d_work), 4);
+  // the dense near-field entries at every frequency of K, as the per-frequency
+  // H-matrix of the same frequencies and precision holds them ([k][near
+  // storage]), are reused instead of evaluated again
+  const bool reuse_near = ctx->H.valid && ctx->H.precision == precision && ctx->H.freqs == ctx->K &&
+                          ctx->H.near_slot_elems == ctx->near_total && ctx->H.near.p != nullptr;
   std::vector<int> opos(nb);
   for (int i = 0; i < nb; ++i) opos[order[i]] = i;
   std::vector<int> todo = order;
@@ -985,56 +990,62 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
     size_t pos = 0;
     const int* d_q = d_order + nfar;
     while (pos < lq.size()) {
-      const int q0 = lq[pos];
-      size_t end = pos;
-      while (end < lq.size() &&
-             (ctx->near_off[lq[end]] + int64_t(bd[ctx->near_ids[lq[end]]].m) * bd[ctx->near_ids[lq[end]]].n -
-              ctx->near_off[q0]) * nK * csz <= tensor_budget)
-        ++end;
-      if (end == pos) end = pos + 1;
-      const int q1 = lq[end - 1] + 1;
-      const int64_t base0 = ctx->near_off[q0];
-      const int64_t span = (q1 < int(ctx->near_off.size()) ? ctx->near_off[q1] : ctx->near_total) - base0;
-      GCQ_TRY(tensor.ensure(size_t(span) * nK * csz + 256));
-      // self/near-tier entries of [q0, q1)
-      const int64_t s0 = int64_t(std::lower_bound(sing_off.begin(), sing_off.end(), base0) - sing_off.begin());
-      const int64_t s1 = int64_t(std::lower_bound(sing_off.begin(), sing_off.end(), base0 + span) - sing_off.begin());
-      GCQ_TRY(timed_begin(ctx));
-      const dim3 g1(std::min(q1 - q0, 65536)), g2(4096);
+      size_t end = lq.size();
+      int64_t base0 = 0, span = ctx->near_total;
+      const void* tens = ctx->H.near.p;
       hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, d_near_counter, 1);
-      if (precision == GCQ_C128) {
-        hipLaunchKernelGGL(near_far_tier<double>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
-                           ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(),
-                           ctx->d_near_off.as<int64_t>(), q0, q1, base0,
-                           ctx->scratchC.as<double2>(), nK, tensor.as<cpx<double>>(), span);
-        hipLaunchKernelGGL(near_sing<double>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
-                           ctx->d_sing.as<SingEntry>(), s0, s1, base0, ctx->scratchC.as<double2>(),
-                           nK, tensor.as<cpx<double>>(), span);
-      } else {
-        hipLaunchKernelGGL(near_far_tier<float>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
-                           ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(),
-                           ctx->d_near_off.as<int64_t>(), q0, q1, base0,
-                           ctx->scratchC.as<double2>(), nK, tensor.as<cpx<float>>(), span);
-        hipLaunchKernelGGL(near_sing<float>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
-                           ctx->d_sing.as<SingEntry>(), s0, s1, base0, ctx->scratchC.as<double2>(),
-                           nK, tensor.as<cpx<float>>(), span);
+      if (!reuse_near) {
+        const int q0 = lq[pos];
+        end = pos;
+        while (end < lq.size() &&
+               (ctx->near_off[lq[end]] + int64_t(bd[ctx->near_ids[lq[end]]].m) * bd[ctx->near_ids[lq[end]]].n -
+                ctx->near_off[q0]) * nK * csz <= tensor_budget)
+          ++end;
+        if (end == pos) end = pos + 1;
+        const int q1 = lq[end - 1] + 1;
+        base0 = ctx->near_off[q0];
+        span = (q1 < int(ctx->near_off.size()) ? ctx->near_off[q1] : ctx->near_total) - base0;
+        GCQ_TRY(tensor.ensure(size_t(span) * nK * csz + 256));
+        // self/near-tier entries of [q0, q1)
+        const int64_t s0 = int64_t(std::lower_bound(sing_off.begin(), sing_off.end(), base0) - sing_off.begin());
+        const int64_t s1 = int64_t(std::lower_bound(sing_off.begin(), sing_off.end(), base0 + span) - sing_off.begin());
+        GCQ_TRY(timed_begin(ctx));
+        const dim3 g1(std::min(q1 - q0, 65536)), g2(4096);
+        if (precision == GCQ_C128) {
+          hipLaunchKernelGGL(near_far_tier<double>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
+                             ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(),
+                             ctx->d_near_off.as<int64_t>(), q0, q1, base0,
+                             ctx->scratchC.as<double2>(), nK, tensor.as<cpx<double>>(), span);
+          hipLaunchKernelGGL(near_sing<double>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
+                             ctx->d_sing.as<SingEntry>(), s0, s1, base0, ctx->scratchC.as<double2>(),
+                             nK, tensor.as<cpx<double>>(), span);
+        } else {
+          hipLaunchKernelGGL(near_far_tier<float>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
+                             ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(),
+                             ctx->d_near_off.as<int64_t>(), q0, q1, base0,
+                             ctx->scratchC.as<double2>(), nK, tensor.as<cpx<float>>(), span);
+          hipLaunchKernelGGL(near_sing<float>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
+                             ctx->d_sing.as<SingEntry>(), s0, s1, base0, ctx->scratchC.as<double2>(),
+                             nK, tensor.as<cpx<float>>(), span);
+        }
+        GCQ_HIP(hipGetLastError());
+        ms_tensor += timed_end(ctx, "aca3d_tensor_batch");
+        tens = tensor.p;
       }
-      GCQ_HIP(hipGetLastError());
-      ms_tensor += timed_end(ctx, "aca3d_tensor_batch");
       GCQ_TRY(timed_begin(ctx));
       const int cnt = int(end - pos);
       if (precision == GCQ_C128)
         hipLaunchKernelGGL(aca3d_near_kernel<double>, dim3(std::min(cnt, cus * 16)), dim3(64), 0,
                            ctx->stream, ctx->scratchB.as<BlockDesc3>(), d_q + pos, cnt,
                            ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(), base0,
-                           tensor.as<cpx<double>>(), span, nK, tol, int(max_freq_rank),
+                           static_cast<const cpx<double>*>(tens), span, nK, tol, int(max_freq_rank),
                            F.slices.as<cpx<double>>(), d_cursor, capacity, d_terms, d_rank,
                            d_stat, d_near_counter);
       else
         hipLaunchKernelGGL(aca3d_near_kernel<float>, dim3(std::min(cnt, cus * 16)), dim3(64), 0,
                            ctx->stream, ctx->scratchB.as<BlockDesc3>(), d_q + pos, cnt,
                            ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(), base0,
-                           tensor.as<cpx<float>>(), span, nK, tol, int(max_freq_rank),
+                           static_cast<const cpx<float>*>(tens), span, nK, tol, int(max_freq_rank),
                            F.slices.as<cpx<float>>(), d_cursor, capacity, d_terms, d_rank,
                            d_stat, d_near_counter);
       GCQ_HIP(hipGetLastError());

@@ -158,3 +158,30 @@ def test_product_graph_replays_match_plain_launches(setup, prec):
             ref2 = y2
         assert rel(y2, ref2) <= tol
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [g.C128, g.C64])
+def test_aca3d_reuses_the_h_matrix_near_field(setup, prec):
+    """After gcq_aca_blocks at the same frequencies and precision, the 3D-ACA
+    reads the dense near-field entries the H-matrix holds instead of evaluating
+    them again: every block's terms are those of a 3D-ACA run without it, and
+    the far blocks still match the oracle."""
+    xyz, tri, s, P, T, B, rep, conj, K, kpos, b3 = setup
+    fresh = make_ctx(xyz, tri, 1.0, s, 32, 1.0)
+    fresh.aca3d(TOLA, TOLF, 40, prec)
+    ctx = make_ctx(xyz, tri, 1.0, s, 32, 1.0)
+    ctx.aca_blocks(TOLA, 64, prec, g.FLAG_RECOMPRESS)
+    ctx.aca3d(TOLA, TOLF, 40, prec)
+    assert ctx.kernel_ms("aca3d_tensor") == 0.0   # no entry evaluation of its own
+    nnear = 0
+    for b, Bo in enumerate(b3):
+        f1, fib1, sl1 = fresh.get_aca3d_block(b, len(K))
+        f2, fib2, sl2 = ctx.get_aca3d_block(b, len(K))
+        assert list(f1) == list(f2), b
+        np.testing.assert_array_equal(fib1, fib2)
+        np.testing.assert_array_equal(sl1, sl2)
+        nnear += not Bo.admissible
+    assert nnear > 0
+    # a change of precision makes it evaluate the entries again
+    ctx.aca3d(TOLA, TOLF, 40, g.C64 if prec == g.C128 else g.C128)
+    assert ctx.kernel_ms("aca3d_tensor") > 0.0
