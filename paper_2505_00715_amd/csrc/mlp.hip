@@ -231,6 +231,14 @@ int rank_predict_device(gcq_context* ctx, const float* d_x, int m, float* d_out)
 void rank_features_host(gcq_context* ctx, const std::vector<int>& freqs, std::vector<float>& feat) {
   const int nfar = int(ctx->far_ids.size());
   feat.assign(size_t(nfar) * freqs.size() * 5, 0.f);
+  // per frequency |s|, Re s, |Im s| (the same expressions as per pair)
+  std::vector<double> sabs(freqs.size()), sre(freqs.size()), sim(freqs.size());
+  for (size_t q = 0; q < freqs.size(); ++q) {
+    const std::complex<double> s = ctx->s[freqs[q]];
+    sabs[q] = std::abs(s);
+    sre[q] = s.real();
+    sim[q] = std::abs(s.imag());
+  }
   for (int f = 0; f < nfar; ++f) {
     const Block& B = ctx->blocks[ctx->far_ids[f]];
     const Cluster& A = ctx->clusters[B.row];
@@ -244,14 +252,15 @@ void rank_features_host(gcq_context* ctx, const std::vector<int>& freqs, std::ve
       g[k] = std::max(0.0, std::max(A.bmin[k] - C.bmax[k], C.bmin[k] - A.bmax[k]));
     const double dist = std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     const double dm = std::max(diam(A), diam(C));
+    const float lm = float(std::log2(double(A.end - A.begin)));
+    const float ln = float(std::log2(double(C.end - C.begin)));
     for (size_t q = 0; q < freqs.size(); ++q) {
-      const std::complex<double> s = ctx->s[freqs[q]];
       float* o = &feat[(size_t(f) * freqs.size() + q) * 5];
-      o[0] = float(dm * std::abs(s) / ctx->c);
-      o[1] = float(dist * s.real() / ctx->c);
-      o[2] = float(dist * std::abs(s.imag()) / ctx->c);
-      o[3] = float(std::log2(double(A.end - A.begin)));
-      o[4] = float(std::log2(double(C.end - C.begin)));
+      o[0] = float(dm * sabs[q] / ctx->c);
+      o[1] = float(dist * sre[q] / ctx->c);
+      o[2] = float(dist * sim[q] / ctx->c);
+      o[3] = lm;
+      o[4] = ln;
     }
   }
 }

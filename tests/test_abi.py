@@ -98,3 +98,30 @@ def test_tuning_roundtrip_and_rejection():
         ctx.set_tuning(aca3d_stack_slices=0)
     assert list(ctx.get_tuning().aca3d_waves) == [1, 1, 2, 4]
     assert ctx.get_tuning().aca3d_stack_slices == 2
+
+
+def test_rank_features_match_oracle_definition():
+    """The rank model's pair features (host logic) against the oracle's
+    definition, from the oracle tree's cluster boxes, for every far block and
+    representative frequency."""
+    from oracle import mlp
+    from synth import freq
+    xyz, tri = mesh.icosphere(3)
+    s = freq.bdf2_circle(16, 0.05, 1e-8 ** (1 / 16))
+    ctx = g.Context(-1)
+    ctx.upload_mesh(xyz, tri, 1.0)
+    ctx.set_frequencies(s, True)
+    ctx.build_cluster_tree(32, 1.0)
+    _, T, B, _, _ = oracle_tree(xyz, tri, 32, 1.0)
+    K = np.arange(len(s) // 2 + 1)
+    far = [(a, b) for a, b, adm in B if adm]
+    got = ctx.rank_features(K, len(far)).reshape(len(far), len(K), 5)
+    lo, hi = np.array(T.bmin), np.array(T.bmax)
+    for f, (a, b) in enumerate(far):
+        diam = max(np.linalg.norm(hi[a] - lo[a]), np.linalg.norm(hi[b] - lo[b]))
+        gap = np.maximum(0.0, np.maximum(lo[a] - hi[b], lo[b] - hi[a]))
+        one = np.ones(len(K))
+        ref = mlp.features(diam * one, np.linalg.norm(gap) * one, s[K], 1.0,
+                           (T.end[a] - T.begin[a]) * one, (T.end[b] - T.begin[b]) * one)
+        np.testing.assert_allclose(got[f], ref, rtol=1e-6, atol=1e-6)
+    ctx.destroy()
