@@ -27,6 +27,10 @@ number of points N_Q (N log N for N steps in the paper) is the caller's.
 q = 1 (constant steps, k = 0) is excluded, as the appendix notes; a caller
 with constant steps perturbs q slightly above 1.
 
+Near q = 1 (k and m tiny) the imaginary-part functions, of parameter 1 - m,
+lose digits here because scipy takes the parameter rather than its
+complement: about 1e-10 relative at q = 1.01.
+
 Jacobi functions of the complex argument x + iy follow from those of real
 argument (modulus k at x, complementary modulus at y) by the addition
 formulas (Abramowitz & Stegun 16.21.2-4); scipy's real-argument routines
@@ -62,7 +66,7 @@ def contour(n_q: int, dt_min: float, dt_max: float, stage_ratio: float = 1.0):
     k = modulus(q)
     m = k * k
     K = special.ellipk(m)
-    Kp = special.ellipk(1.0 - m)
+    Kp = special.ellipkm1(m)   # K(1 - m) without forming 1 - m
     l = np.arange(1, n_q + 1)
     x = -K + (l - 0.5) * 4.0 * K / n_q
     y = np.full(n_q, 0.5 * Kp)
