@@ -213,6 +213,24 @@ GCQ_API int gcq_upload_mesh(gcq_context* ctx, const double* xyz, int64_t n_verti
 GCQ_API int gcq_set_frequencies(gcq_context* ctx, const gcq_c128* s, int32_t n_freq,
                                 int32_t use_conjugate_symmetry);
 
+/* gcq_contour: points s_l and weights w_l, l = 1..n_points, of the gCQ
+ *   contour quadrature of App. A (no context, host arrays of n_points
+ *   complex doubles, owned by the caller).  q = stage_ratio * dt_max / dt_min
+ *   (stage_ratio = 1 for implicit Euler, 5 max|lambda(A)| / min|lambda(A)| for
+ *   a Runge-Kutta method of several stages), elliptic modulus
+ *   k = (q - sqrt(2q-1)) / (q + sqrt(2q-1)), K = K(k^2), K' = K(1 - k^2),
+ *   sigma_l = -K + (l - 1/2) 4K / n_points + i K'/2, s_l = gamma(sigma_l),
+ *   w_l = 4K / (2 pi i n_points) gamma'(sigma_l) (the appendix's map gamma;
+ *   the weight's denominator reads 2 pi i n_points where the printed formula
+ *   is garbled).  The contour is traversed clockwise as Re sigma grows:
+ *   sum_l w_l f(s_l) approximates -(1 / 2 pi i) times the counter-clockwise
+ *   integral of f.  The points come in conjugate pairs s_{n+1-l} = conj(s_l);
+ *   for odd n_points the middle point is real.  All points have Re s > 0.
+ *   GCQ_ERR_ARG for n_points < 1, NULL arrays, dt_min <= 0, dt_max < dt_min,
+ *   stage_ratio < 1, or q <= 1 (constant steps: the appendix perturbs q). */
+GCQ_API int gcq_contour(int32_t n_points, double dt_min, double dt_max, double stage_ratio,
+                        gcq_c128* s, gcq_c128* w);
+
 /* gcq_build_cluster_tree: cluster tree and block cluster tree of Sec. 4
  *   (eq. admissible with parameter eta > 0, leaves of at most leaf_size
  *   triangles).  info may be NULL. */

@@ -88,6 +88,7 @@ def _load():
         "gcq_get_tuning": [P, P],
         "gcq_upload_mesh": [P, P, I64, P, I64, D],
         "gcq_set_frequencies": [P, P, I32, I32],
+        "gcq_contour": [I32, D, D, D, P, P],
         "gcq_build_cluster_tree": [P, I32, D, P],
         "gcq_get_tree": [P, P, P],
         "gcq_assemble_slices": [P, P, I64, P, I64, P, I32, I32, P],
@@ -140,6 +141,15 @@ def _dev(t, dtype, numel=None, name="tensor"):
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
     return C.c_void_p(t.data_ptr())
+
+
+def contour(n_points: int, dt_min: float, dt_max: float, stage_ratio: float = 1.0):
+    """Points s (n_points,) and weights w of the gCQ contour quadrature (gcq_contour)."""
+    s = np.zeros(int(n_points), np.complex128)
+    w = np.zeros(int(n_points), np.complex128)
+    _check(_lib.gcq_contour(int(n_points), float(dt_min), float(dt_max), float(stage_ratio),
+                            s.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p)))
+    return s, w
 
 
 class Context:
