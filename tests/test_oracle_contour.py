@@ -88,3 +88,14 @@ def test_weights_reproduce_cauchys_formula(q):
 def test_constant_steps_are_rejected():
     with pytest.raises(ValueError):
         C.contour(16, 0.01, 0.01)
+
+
+@pytest.mark.parametrize("q", [1.5, 4.0, 20.0])
+def test_contour_passes_through_zero_and_two_over_dt_min(q):
+    """gamma(-K + i K'/2) = 0 and gamma(K + i K'/2) = 2 / dt_min (sn = -+1/sqrt(k) there)."""
+    dt_min = 0.01
+    k = C.modulus(q)
+    K, Kp = special.ellipk(k * k), special.ellipkm1(k * k)
+    g = C.gamma_of(np.array([-K + 0.5j * Kp, K + 0.5j * Kp]), dt_min, q)
+    assert abs(g[0]) <= 1e-10 / dt_min
+    assert abs(g[1] - 2.0 / dt_min) <= 1e-10 / dt_min
