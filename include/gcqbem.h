@@ -231,6 +231,25 @@ GCQ_API int gcq_set_frequencies(gcq_context* ctx, const gcq_c128* s, int32_t n_f
 GCQ_API int gcq_contour(int32_t n_points, double dt_min, double dt_max, double stage_ratio,
                         gcq_c128* s, gcq_c128* w);
 
+/* gcq_gcq_convolve: the forward gCQ convolution f = V * q (Sec. 3: the first
+ *   step, eq. gCQ_xn and eq. gcq_formula) with implicit Euler (A = b = c = 1)
+ *   and n_steps constant steps dt, on the operator gcq_aca3d built at
+ *   `precision`.  The context's frequency set must be [1/dt, s_1 .. s_NQ]:
+ *   frequency 0 is the current-step point 1/dt (real; GCQ_ERR_STATE
+ *   otherwise) and frequencies 1..NQ the contour points, whose weights w
+ *   (host, NQ complex doubles, as gcq_contour returns them) are passed here.
+ *   With odd NQ this set has the pairing k <-> n_freq - k that conjugate
+ *   symmetry uses.  Per step n:
+ *     x_{n-1}(s_l) = (x_{n-2}(s_l) + dt q_{n-1}) / (1 - dt s_l), x_0 = 0,
+ *     f_n = V(1/dt) q_n + sum_l V(s_l) w_l x_{n-1}(s_l) / (1 - dt s_l)
+ *   (one product over the set, summed over its columns: f_n is the real
+ *   part).  Q (input) and F
+ *   (output) are device arrays of n_steps x n_triangles doubles, step-major,
+ *   triangle order.  The state x (NQ x n complex doubles) and the product's
+ *   columns are allocated for the call; returns after the last step. */
+GCQ_API int gcq_gcq_convolve(gcq_context* ctx, double dt, int32_t n_steps, const gcq_c128* w,
+                             int32_t precision, const double* Q, double* F);
+
 /* gcq_build_cluster_tree: cluster tree and block cluster tree of Sec. 4
  *   (eq. admissible with parameter eta > 0, leaves of at most leaf_size
  *   triangles).  info may be NULL. */

@@ -89,6 +89,7 @@ def _load():
         "gcq_upload_mesh": [P, P, I64, P, I64, D],
         "gcq_set_frequencies": [P, P, I32, I32],
         "gcq_contour": [I32, D, D, D, P, P],
+        "gcq_gcq_convolve": [P, D, I32, P, I32, P, P],
         "gcq_build_cluster_tree": [P, I32, D, P],
         "gcq_get_tree": [P, P, P],
         "gcq_assemble_slices": [P, P, I64, P, I64, P, I32, I32, P],
@@ -309,6 +310,17 @@ class Context:
         py = _dev(Y, dt, (self.n if mode == WEIGHTED_SUM else self.L * self.n), "Y")
         _check(_lib.gcq_compressed_matvec(self._h, mode, precision, px, py, self.L))
         return Y
+
+    def gcq_convolve(self, dt: float, w, Q, F, precision: int = C128):
+        """Forward gCQ convolution (gcq_gcq_convolve): Q, F device float64
+        tensors of n_steps x n; w the contour weights (host)."""
+        import torch
+        wh, pw = _host(w, np.complex128)
+        n_steps = Q.numel() // self.n
+        pq = _dev(Q, torch.float64, n_steps * self.n, "Q")
+        pf = _dev(F, torch.float64, n_steps * self.n, "F")
+        _check(_lib.gcq_gcq_convolve(self._h, float(dt), int(n_steps), pw, precision, pq, pf))
+        return F
 
     def solve(self, B, X, rtol: float = 1e-6, max_iter: int = 500, restart: int = 50,
               precision: int = C64) -> SolveStats:
