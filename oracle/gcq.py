@@ -45,3 +45,25 @@ def convolve(apply_V, q, dt, s, w):
             acc = acc + apply_V(s[l], w[l] * x[l] / (1.0 - dt[n] * s[l]))
         f[n] = acc
     return f
+
+
+def solve(apply_V, solve_V, f, dt, s, w):
+    """q (N, M) with convolve(apply_V, q, dt, s, w) = f (eq. gcq_formula with
+    (f)_n given): per step the system V(1/dt_n) q_n = f_n - history, the
+    history being the contour sum of eq. gcq_formula over the earlier steps.
+    solve_V(z, b) returns V(z)^{-1} b."""
+    f = np.asarray(f, dtype=np.complex128)
+    dt = np.asarray(dt, dtype=np.float64)
+    s = np.asarray(s, dtype=np.complex128)
+    w = np.asarray(w, dtype=np.complex128)
+    N, M = f.shape
+    x = np.zeros((len(s), M), dtype=np.complex128)
+    q = np.zeros((N, M), dtype=np.complex128)
+    for n in range(N):
+        h = np.zeros(M, dtype=np.complex128)
+        if n > 0:
+            x = (x + dt[n - 1] * q[n - 1][None, :]) / (1.0 - dt[n - 1] * s)[:, None]
+            for l in range(len(s)):
+                h = h + apply_V(s[l], w[l] * x[l] / (1.0 - dt[n] * s[l]))
+        q[n] = solve_V(1.0 / dt[n], f[n] - h)
+    return q

@@ -67,3 +67,27 @@ def test_linearity_and_zero_input():
     f2 = gcq.convolve(V, 2.0 * q, dt, s, w)
     assert np.max(np.abs(f2 - 2.0 * f1)) <= 1e-12 * np.max(np.abs(f1))
     assert np.all(gcq.convolve(V, np.zeros_like(q), dt, s, w) == 0)
+
+
+def test_solve_inverts_implicit_euler_of_the_exponential_kernel():
+    """V = 1/(s + lam): f_n = (f_{n-1} + dt_n q_n) / (1 + lam dt_n), so
+    q_n = ((1 + lam dt_n) f_n - f_{n-1}) / dt_n."""
+    lam = 40.0
+    dt, s, w, f = _setup(20, seed=8)
+    q = gcq.solve(lambda z, X: X / (z + lam), lambda z, b: b * (z + lam), f, dt, s, w)
+    fp = np.vstack([np.zeros(f.shape[1]), f[:-1]])
+    ref = ((1.0 + lam * dt[:, None]) * f - fp) / dt[:, None]
+    assert np.max(np.abs(q - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_solve_and_convolve_are_inverse_for_a_matrix_operator():
+    rng = np.random.default_rng(9)
+    M = 6
+    A0 = rng.standard_normal((M, M)) / M
+    V = lambda z, X: np.linalg.solve(z * np.eye(M) + 30.0 * np.eye(M) + A0, X)   # resolvent-like, analytic
+    Vinv = lambda z, b: (z * np.eye(M) + 30.0 * np.eye(M) + A0) @ b
+    dt, s, w, _ = _setup(15, seed=10)
+    q = rng.standard_normal((15, M))
+    f = gcq.convolve(V, q, dt, s, w)
+    q2 = gcq.solve(V, Vinv, f, dt, s, w)
+    assert np.max(np.abs(q2 - q)) <= 1e-9 * np.max(np.abs(q))
