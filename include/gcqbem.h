@@ -250,6 +250,18 @@ GCQ_API int gcq_contour(int32_t n_points, double dt_min, double dt_max, double s
 GCQ_API int gcq_gcq_convolve(gcq_context* ctx, double dt, int32_t n_steps, const gcq_c128* w,
                              int32_t precision, const double* Q, double* F);
 
+/* gcq_gcq_solve: the same scheme with (f)_n given and the density unknown
+ *   (eq. gcq_formula, "solve the system in case (f)_n is given"): per step the
+ *   history h = sum_l V(s_l) w_l x_{n-1}(s_l) / (1 - dt s_l) of the densities
+ *   found so far, then V(1/dt) q_n = f_n - h by GMRES (gcq_solve's batched
+ *   solver; the other frequencies' systems have zero right-hand sides and end
+ *   at once).  F (input) and Q (output): device doubles, n_steps x n_triangles,
+ *   step-major.  rtol, max_iter, restart as in gcq_solve; *iters_max (may be
+ *   NULL) receives the largest iteration count of a step. */
+GCQ_API int gcq_gcq_solve(gcq_context* ctx, double dt, int32_t n_steps, const gcq_c128* w,
+                          int32_t precision, const double* F, double* Q, double rtol,
+                          int32_t max_iter, int32_t restart, int32_t* iters_max);
+
 /* gcq_build_cluster_tree: cluster tree and block cluster tree of Sec. 4
  *   (eq. admissible with parameter eta > 0, leaves of at most leaf_size
  *   triangles).  info may be NULL. */

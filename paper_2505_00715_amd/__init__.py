@@ -90,6 +90,7 @@ def _load():
         "gcq_set_frequencies": [P, P, I32, I32],
         "gcq_contour": [I32, D, D, D, P, P],
         "gcq_gcq_convolve": [P, D, I32, P, I32, P, P],
+        "gcq_gcq_solve": [P, D, I32, P, I32, P, P, D, I32, I32, P],
         "gcq_build_cluster_tree": [P, I32, D, P],
         "gcq_get_tree": [P, P, P],
         "gcq_assemble_slices": [P, P, I64, P, I64, P, I32, I32, P],
@@ -321,6 +322,20 @@ class Context:
         pf = _dev(F, torch.float64, n_steps * self.n, "F")
         _check(_lib.gcq_gcq_convolve(self._h, float(dt), int(n_steps), pw, precision, pq, pf))
         return F
+
+    def gcq_solve(self, dt: float, w, F, Q, precision: int = C128, rtol: float = 1e-8,
+                  max_iter: int = 300, restart: int = 50) -> int:
+        """Densities of the gCQ scheme for given f (gcq_gcq_solve): F, Q device
+        float64 tensors of n_steps x n; returns the largest GMRES count."""
+        import torch
+        wh, pw = _host(w, np.complex128)
+        n_steps = F.numel() // self.n
+        pf = _dev(F, torch.float64, n_steps * self.n, "F")
+        pq = _dev(Q, torch.float64, n_steps * self.n, "Q")
+        it = C.c_int32(0)
+        _check(_lib.gcq_gcq_solve(self._h, float(dt), int(n_steps), pw, precision, pf, pq,
+                                  float(rtol), int(max_iter), int(restart), C.byref(it)))
+        return it.value
 
     def solve(self, B, X, rtol: float = 1e-6, max_iter: int = 500, restart: int = 50,
               precision: int = C64) -> SolveStats:

@@ -136,3 +136,108 @@ extern "C" GCQ_API int gcq_gcq_convolve(gcq_context* ctx, double dt, int32_t n_s
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return GCQ_OK;
 }
+
+namespace gcq {
+
+// B[0] = f - h (the system of frequency 0), B[k > 0] = 0
+__global__ void __launch_bounds__(256) gcq_rhs(const double* __restrict__ f, const double* __restrict__ h,
+                                               int L, int n, cpx<double>* __restrict__ B) {
+  const int64_t total = int64_t(L) * n;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x)
+    B[e] = e < n ? cpx<double>{f[e] - h[e], 0.0} : cpx<double>{0.0, 0.0};
+}
+
+__global__ void __launch_bounds__(256) gcq_take_real(const cpx<double>* __restrict__ X, int n,
+                                                     double* __restrict__ q) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) q[i] = X[i].re;
+}
+
+}  // namespace gcq
+
+extern "C" GCQ_API int gcq_gcq_solve(gcq_context* ctx, double dt, int32_t n_steps, const gcq_c128* w,
+                                     int32_t precision, const double* F, double* Q, double rtol,
+                                     int32_t max_iter, int32_t restart, int32_t* iters_max) {
+  if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
+  GCQ_NEED_DEVICE(ctx);
+  if (!w || !Q || !F) return fail(GCQ_ERR_ARG, "w, F and Q must not be NULL");
+  if (n_steps < 1) return fail(GCQ_ERR_ARG, "n_steps must be >= 1");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(GCQ_ERR_ARG, "dt must be > 0");
+  if (precision != GCQ_C128 && precision != GCQ_C64)
+    return fail(GCQ_ERR_ARG, "unknown precision %d", precision);
+  if (!ctx->F.valid || ctx->F.precision != precision)
+    return fail(GCQ_ERR_STATE, "run gcq_aca3d at this precision first");
+  const int L = ctx->L, n = ctx->n, nq = L - 1;
+  if (L < 2) return fail(GCQ_ERR_STATE, "the frequency set needs 1/dt and at least one contour point");
+  const std::complex<double> s0 = ctx->s[0];
+  if (std::fabs(s0.real() - 1.0 / dt) > 1e-12 / dt || s0.imag() != 0.0)
+    return fail(GCQ_ERR_STATE, "frequency 0 must be 1/dt (the current-step operator)");
+  GCQ_HIP(hipSetDevice(ctx->device));
+  std::vector<double2> inv1m(nq), wl(nq);
+  for (int l = 0; l < nq; ++l) {
+    const std::complex<double> d = 1.0 - dt * ctx->s[l + 1];
+    if (std::abs(d) == 0.0) return fail(GCQ_ERR_ARG, "contour point %d equals 1/dt", l + 1);
+    const std::complex<double> a = 1.0 / d;
+    inv1m[l] = make_double2(a.real(), a.imag());
+    wl[l] = make_double2(w[l].re, w[l].im);
+  }
+  hipStream_t st = ctx->stream;
+  const size_t csz = csize(precision);
+  DevBuf d_inv, d_w, d_x, d_X, d_Y, d_zero, d_h, d_B, d_S;
+  GCQ_TRY(upload(d_inv, inv1m, st));
+  GCQ_TRY(upload(d_w, wl, st));
+  GCQ_TRY(d_x.ensure(sizeof(double2) * size_t(nq) * n));
+  GCQ_HIP(hipMemsetAsync(d_x.p, 0, sizeof(double2) * size_t(nq) * n, st));
+  GCQ_TRY(d_X.ensure(csz * size_t(L) * n));
+  GCQ_TRY(d_Y.ensure(csz * size_t(L) * n));
+  GCQ_TRY(d_zero.ensure(sizeof(double) * n));
+  GCQ_HIP(hipMemsetAsync(d_zero.p, 0, sizeof(double) * n, st));
+  GCQ_TRY(d_h.ensure(sizeof(double) * n));
+  GCQ_HIP(hipMemsetAsync(d_h.p, 0, sizeof(double) * n, st));
+  GCQ_TRY(d_B.ensure(sizeof(cpx<double>) * size_t(L) * n));
+  GCQ_TRY(d_S.ensure(sizeof(cpx<double>) * size_t(L) * n));
+  const int grid = int(std::min<int64_t>((int64_t(L) * n + 255) / 256, int64_t(ctx->cus) * 16));
+  const int g2 = std::min((n + 255) / 256, ctx->cus * 4);
+  int itmax = 0;
+  GCQ_HIP(hipStreamSynchronize(st));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int step = 0; step < n_steps; ++step) {
+    if (step > 0) {
+      // history of the earlier steps: the sum over the contour with the
+      // current-step column left out
+      const double* qp = Q + int64_t(step - 1) * n;
+      if (precision == GCQ_C128)
+        hipLaunchKernelGGL(gcq_columns<double>, dim3(grid), dim3(256), 0, st, qp, d_zero.as<double>(),
+                           d_inv.as<double2>(), d_w.as<double2>(), nq, n, dt, 1, d_x.as<double2>(),
+                           d_X.as<cpx<double>>());
+      else
+        hipLaunchKernelGGL(gcq_columns<float>, dim3(grid), dim3(256), 0, st, qp, d_zero.as<double>(),
+                           d_inv.as<double2>(), d_w.as<double2>(), nq, n, dt, 1, d_x.as<double2>(),
+                           d_X.as<cpx<float>>());
+      GCQ_HIP(hipGetLastError());
+      GCQ_TRY(gcq_compressed_matvec(ctx, GCQ_PER_FREQUENCY, precision, d_X.p, d_Y.p, L));
+      if (precision == GCQ_C128)
+        hipLaunchKernelGGL(sum_columns_real<double>, dim3(g2), dim3(256), 0, st, d_Y.as<cpx<double>>(), L,
+                           n, d_h.as<double>());
+      else
+        hipLaunchKernelGGL(sum_columns_real<float>, dim3(g2), dim3(256), 0, st, d_Y.as<cpx<float>>(), L, n,
+                           d_h.as<double>());
+      GCQ_HIP(hipGetLastError());
+    }
+    // V(1/dt) q_n = f_n - history
+    hipLaunchKernelGGL(gcq_rhs, dim3(grid), dim3(256), 0, st, F + int64_t(step) * n, d_h.as<double>(), L,
+                       n, d_B.as<cpx<double>>());
+    GCQ_HIP(hipGetLastError());
+    gcq_solve_stats ss;
+    GCQ_TRY(gcq_solve(ctx, d_B.p, d_S.p, rtol, max_iter, restart, precision, &ss));
+    itmax = std::max(itmax, int(ss.iters_max));
+    hipLaunchKernelGGL(gcq_take_real, dim3(g2), dim3(256), 0, st, d_S.as<cpx<double>>(), n,
+                       Q + int64_t(step) * n);
+    GCQ_HIP(hipGetLastError());
+  }
+  GCQ_HIP(hipStreamSynchronize(st));
+  ctx->kernel_ms["gcq_solve"] =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (iters_max) *iters_max = itmax;
+  return GCQ_OK;
+}

@@ -76,3 +76,26 @@ def test_gcq_convolution_rejects_a_set_without_the_step_point(setup):
         ctx.gcq_convolve(2 * DT, w_lib, Q, F, g.C128)      # frequency 0 is not 1/dt
     with pytest.raises(g.GcqError):
         ctx.gcq_convolve(DT, w_lib, Q, F, g.C64)           # operator built at C128
+
+
+@pytest.mark.parametrize("prec,tola,tol", [(g.C128, 1e-10, 1e-6), (g.C64, 1e-6, 1e-3)])
+def test_gcq_solve_recovers_the_density(setup, prec, tola, tol):
+    """gcq_gcq_solve on the oracle's f of a known density q returns q (the
+    scheme's own inverse), up to the operator's compression and the solver
+    tolerance amplified by the conditioning of V(1/dt)."""
+    xyz, tri, P, q, f_or = setup
+    s_lib, w_lib = g.contour(NQ, DT, 1.5 * DT)
+    ctx = make_ctx(xyz, tri, 1.0, _set(s_lib), 16, 1.0)
+    ctx.aca3d(tola, tola, 64, prec)
+    Fd = torch.from_numpy(np.ascontiguousarray(f_or.real).reshape(-1)).cuda()
+    Qd = torch.full_like(Fd, np.nan)
+    it = ctx.gcq_solve(DT, w_lib, Fd, Qd, prec, rtol=1e-12 if prec == g.C128 else 1e-7, max_iter=400)
+    assert it > 0
+    qg = Qd.cpu().numpy().reshape(NSTEP, P.n)
+    err = np.linalg.norm(qg - q) / np.linalg.norm(q)
+    assert err <= tol, err
+    # and the convolution of the recovered density reproduces f
+    F2 = torch.empty_like(Fd)
+    ctx.gcq_convolve(DT, w_lib, Qd, F2, prec)
+    f2 = F2.cpu().numpy().reshape(NSTEP, P.n)
+    assert np.linalg.norm(f2 - f_or.real) / np.linalg.norm(f_or.real) <= (1e-9 if prec == g.C128 else 1e-5)
