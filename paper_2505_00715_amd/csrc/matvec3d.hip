@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(256) perfreq_mfma(
 // first, then y_I += H w1 + conj(H w2)
 template <typename T>
 __global__ void __launch_bounds__(64) wsum_kernel(
-    const int* __restrict__ blk, int nblocks, const int* __restrict__ bterm,
+    const int* __restrict__ blk, const int* __restrict__ order, int nblocks, const int* __restrict__ bterm,
     const int* __restrict__ trank, const int64_t* __restrict__ toff,
     const int64_t* __restrict__ tvoff, const int64_t* __restrict__ tfoff,
     const cpx<T>* __restrict__ pool, const int* __restrict__ colpos,
@@ -438,7 +438,8 @@ __global__ void __launch_bounds__(64) wsum_kernel(
   __shared__ cpx<T> t1[64], t2[64];
   const int lane = threadIdx.x;
   cpx<T>* w1 = scratch + int64_t(blockIdx.x) * sstride;
-  for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+  for (int ob = blockIdx.x; ob < nblocks; ob += gridDim.x) {
+    const int b = order[ob];   // blocks with terms, most work first
     const int rb = blk[5 * b], m = blk[5 * b + 1] - rb, cb = blk[5 * b + 2], nn = blk[5 * b + 3] - cb;
     cpx<T>* w2 = w1 + nn;
     for (int d = bterm[b]; d < bterm[b + 1]; ++d) {
@@ -623,7 +624,8 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
   int maxn = 0;
   for (auto& B : ctx->blocks)
     maxn = std::max(maxn, ctx->clusters[B.col].end - ctx->clusters[B.col].begin);
-  const int wgrid = std::min(nb, 4096);
+  const int nmv = F.n_mvblocks;
+  const int wgrid = std::max(1, std::min(nmv, ctx->cus * 32));
   GCQ_TRY(ctx->scratchB.ensure(size_t(nl + n + 2 * int64_t(maxn) * wgrid) * sizeof(cpx<T>)));
   cpx<T>* Xp = ctx->scratchB.as<cpx<T>>();
   cpx<T>* Yp = Xp + nl;
@@ -641,7 +643,8 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
       hipLaunchKernelGGL((perm_in3<float, T>), dim3(g), dim3(256), 0, st, (const cpx<float>*)X, Xp,
                          perm, ctx->scratchD.as<int>(), n, L);
     hipLaunchKernelGGL(zero3<T>, dim3(64), dim3(256), 0, st, Yp, int64_t(n));
-    hipLaunchKernelGGL(wsum_kernel<T>, dim3(wgrid), dim3(64), 0, st, ctx->d_blk.as<int>(), nb,
+    hipLaunchKernelGGL(wsum_kernel<T>, dim3(wgrid), dim3(64), 0, st, ctx->d_blk.as<int>(),
+                       F.d_mvorder.as<int>(), nmv,
                        F.d_bterm.as<int>(), F.d_trank.as<int>(), F.d_toff.as<int64_t>(),
                        F.d_tvoff.as<int64_t>(), F.d_tfoff.as<int64_t>(), F.slices.as<cpx<T>>(),
                        d_colpos, d_conj, L, n, Xp,
