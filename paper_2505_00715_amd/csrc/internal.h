@@ -100,6 +100,7 @@ struct HFaces {
   int64_t near_slot_elems = 0;
   DevBuf d_near_off;
   DevBuf near;                   // nslot * near_slot_elems
+  DevBuf d_sig;                  // sigma = s / c of each slot (near-field kernels)
   int64_t storage_bytes = 0;
 };
 
