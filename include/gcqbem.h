@@ -233,34 +233,39 @@ GCQ_API int gcq_contour(int32_t n_points, double dt_min, double dt_max, double s
 
 /* gcq_gcq_convolve: the forward gCQ convolution f = V * q (Sec. 3: the first
  *   step, eq. gCQ_xn and eq. gcq_formula) with implicit Euler (A = b = c = 1)
- *   and n_steps constant steps dt, on the operator gcq_aca3d built at
- *   `precision`.  The context's frequency set must be [1/dt, s_1 .. s_NQ]:
- *   frequency 0 is the current-step point 1/dt (real; GCQ_ERR_STATE
- *   otherwise) and frequencies 1..NQ the contour points, whose weights w
- *   (host, NQ complex doubles, as gcq_contour returns them) are passed here.
- *   With odd NQ this set has the pairing k <-> n_freq - k that conjugate
- *   symmetry uses.  Per step n:
- *     x_{n-1}(s_l) = (x_{n-2}(s_l) + dt q_{n-1}) / (1 - dt s_l), x_0 = 0,
- *     f_n = V(1/dt) q_n + sum_l V(s_l) w_l x_{n-1}(s_l) / (1 - dt s_l)
+ *   on the operator gcq_aca3d built at `precision`, for n_steps steps of sizes
+ *   dt[0..n_steps) (host array; variable steps are what the generalised scheme
+ *   is for).  The context's frequency set must be [step points, contour
+ *   points]: its first n_step_points frequencies are the distinct values 1/dt_n
+ *   (real; every step's 1/dt_n must be among them, GCQ_ERR_STATE otherwise),
+ *   the remaining NQ = n_freq - n_step_points are the contour points, whose
+ *   weights w (host, NQ complex doubles, as gcq_contour returns them) are
+ *   passed here.  One step point and odd NQ give the pairing k <-> n_freq - k
+ *   that conjugate symmetry uses; more step points need a set without it.
+ *   Per step n:
+ *     x_{n-1}(s_l) = (x_{n-2}(s_l) + dt_{n-1} q_{n-1}) / (1 - dt_{n-1} s_l), x_0 = 0,
+ *     f_n = V(1/dt_n) q_n + sum_l V(s_l) w_l x_{n-1}(s_l) / (1 - dt_n s_l)
  *   (one product over the set, summed over its columns: f_n is the real
- *   part).  Q (input) and F
- *   (output) are device arrays of n_steps x n_triangles doubles, step-major,
- *   triangle order.  The state x (NQ x n complex doubles) and the product's
- *   columns are allocated for the call; returns after the last step. */
-GCQ_API int gcq_gcq_convolve(gcq_context* ctx, double dt, int32_t n_steps, const gcq_c128* w,
-                             int32_t precision, const double* Q, double* F);
+ *   part).  Q (input) and F (output) are device arrays of n_steps x
+ *   n_triangles doubles, step-major, triangle order.  The state x (NQ x n
+ *   complex doubles) and the product's columns are allocated for the call;
+ *   returns after the last step. */
+GCQ_API int gcq_gcq_convolve(gcq_context* ctx, const double* dt, int32_t n_steps,
+                             int32_t n_step_points, const gcq_c128* w, int32_t precision,
+                             const double* Q, double* F);
 
 /* gcq_gcq_solve: the same scheme with (f)_n given and the density unknown
  *   (eq. gcq_formula, "solve the system in case (f)_n is given"): per step the
- *   history h = sum_l V(s_l) w_l x_{n-1}(s_l) / (1 - dt s_l) of the densities
- *   found so far, then V(1/dt) q_n = f_n - h by GMRES (gcq_solve's batched
+ *   history h = sum_l V(s_l) w_l x_{n-1}(s_l) / (1 - dt_n s_l) of the densities
+ *   found so far, then V(1/dt_n) q_n = f_n - h by GMRES (gcq_solve's batched
  *   solver; the other frequencies' systems have zero right-hand sides and end
  *   at once).  F (input) and Q (output): device doubles, n_steps x n_triangles,
  *   step-major.  rtol, max_iter, restart as in gcq_solve; *iters_max (may be
  *   NULL) receives the largest iteration count of a step. */
-GCQ_API int gcq_gcq_solve(gcq_context* ctx, double dt, int32_t n_steps, const gcq_c128* w,
-                          int32_t precision, const double* F, double* Q, double rtol,
-                          int32_t max_iter, int32_t restart, int32_t* iters_max);
+GCQ_API int gcq_gcq_solve(gcq_context* ctx, const double* dt, int32_t n_steps,
+                          int32_t n_step_points, const gcq_c128* w, int32_t precision,
+                          const double* F, double* Q, double rtol, int32_t max_iter,
+                          int32_t restart, int32_t* iters_max);
 
 /* gcq_build_cluster_tree: cluster tree and block cluster tree of Sec. 4
  *   (eq. admissible with parameter eta > 0, leaves of at most leaf_size

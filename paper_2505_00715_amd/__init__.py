@@ -89,8 +89,8 @@ def _load():
         "gcq_upload_mesh": [P, P, I64, P, I64, D],
         "gcq_set_frequencies": [P, P, I32, I32],
         "gcq_contour": [I32, D, D, D, P, P],
-        "gcq_gcq_convolve": [P, D, I32, P, I32, P, P],
-        "gcq_gcq_solve": [P, D, I32, P, I32, P, P, D, I32, I32, P],
+        "gcq_gcq_convolve": [P, P, I32, I32, P, I32, P, P],
+        "gcq_gcq_solve": [P, P, I32, I32, P, I32, P, P, D, I32, I32, P],
         "gcq_build_cluster_tree": [P, I32, D, P],
         "gcq_get_tree": [P, P, P],
         "gcq_assemble_slices": [P, P, I64, P, I64, P, I32, I32, P],
@@ -312,29 +312,33 @@ class Context:
         _check(_lib.gcq_compressed_matvec(self._h, mode, precision, px, py, self.L))
         return Y
 
-    def gcq_convolve(self, dt: float, w, Q, F, precision: int = C128):
-        """Forward gCQ convolution (gcq_gcq_convolve): Q, F device float64
-        tensors of n_steps x n; w the contour weights (host)."""
+    def gcq_convolve(self, dt, w, Q, F, precision: int = C128, n_step_points: int = 1):
+        """Forward gCQ convolution (gcq_gcq_convolve): dt the step sizes (a
+        number for constant steps), Q, F device float64 tensors of n_steps x n,
+        w the contour weights (host)."""
         import torch
-        wh, pw = _host(w, np.complex128)
         n_steps = Q.numel() // self.n
+        dth, pd = _host(np.broadcast_to(np.asarray(dt, np.float64), (n_steps,)), np.float64)
+        wh, pw = _host(w, np.complex128)
         pq = _dev(Q, torch.float64, n_steps * self.n, "Q")
         pf = _dev(F, torch.float64, n_steps * self.n, "F")
-        _check(_lib.gcq_gcq_convolve(self._h, float(dt), int(n_steps), pw, precision, pq, pf))
+        _check(_lib.gcq_gcq_convolve(self._h, pd, int(n_steps), int(n_step_points), pw, precision,
+                                     pq, pf))
         return F
 
-    def gcq_solve(self, dt: float, w, F, Q, precision: int = C128, rtol: float = 1e-8,
-                  max_iter: int = 300, restart: int = 50) -> int:
+    def gcq_solve(self, dt, w, F, Q, precision: int = C128, rtol: float = 1e-8,
+                  max_iter: int = 300, restart: int = 50, n_step_points: int = 1) -> int:
         """Densities of the gCQ scheme for given f (gcq_gcq_solve): F, Q device
         float64 tensors of n_steps x n; returns the largest GMRES count."""
         import torch
-        wh, pw = _host(w, np.complex128)
         n_steps = F.numel() // self.n
+        dth, pd = _host(np.broadcast_to(np.asarray(dt, np.float64), (n_steps,)), np.float64)
+        wh, pw = _host(w, np.complex128)
         pf = _dev(F, torch.float64, n_steps * self.n, "F")
         pq = _dev(Q, torch.float64, n_steps * self.n, "Q")
         it = C.c_int32(0)
-        _check(_lib.gcq_gcq_solve(self._h, float(dt), int(n_steps), pw, precision, pf, pq,
-                                  float(rtol), int(max_iter), int(restart), C.byref(it)))
+        _check(_lib.gcq_gcq_solve(self._h, pd, int(n_steps), int(n_step_points), pw, precision,
+                                  pf, pq, float(rtol), int(max_iter), int(restart), C.byref(it)))
         return it.value
 
     def solve(self, B, X, rtol: float = 1e-6, max_iter: int = 500, restart: int = 50,

@@ -1,12 +1,14 @@
 // Forward gCQ convolution f = V * q with implicit Euler (Sec. 3: first step,
-// eq. gCQ_xn, eq. gcq_formula) on the compressed operator of gcq_aca3d.
+// eq. gCQ_xn, eq. gcq_formula) on the compressed operator of gcq_aca3d, and
+// the solve for q with f given.
 //
 // Implicit Euler is the one-stage method A = (1), b = c = (1) (b^T A^{-1} = 1).
-// With constant steps dt the current-step operator V(1/dt) is one more
-// frequency of the set, so that each step is one product over the whole set
-// [1/dt, s_1 .. s_NQ] followed by the sum of its columns:
-//   f_n = V(1/dt) q_n + sum_l V(s_l) w_l x_{n-1}(s_l) / (1 - dt s_l),
-//   x_{n-1}(s_l) = (x_{n-2}(s_l) + dt q_{n-1}) / (1 - dt s_l),  x_0 = 0.
+// The current-step operators V(1/dt_n) are frequencies of the set too: the set
+// is [step points 1/dt (the distinct ones), contour points s_1 .. s_NQ], and
+// each step is one product over the whole set followed by the sum of its
+// columns:
+//   f_n = V(1/dt_n) q_n + sum_l V(s_l) w_l x_{n-1}(s_l) / (1 - dt_n s_l),
+//   x_{n-1}(s_l) = (x_{n-2}(s_l) + dt_{n-1} q_{n-1}) / (1 - dt_{n-1} s_l),  x_0 = 0.
 // The state x (NQ x n, complex double) stays on the device; one kernel updates
 // it and writes the product's input columns.  The sum over the set runs as the
 // per-frequency product on the matrix cores (replayed as a graph) and a column
@@ -21,36 +23,44 @@
 
 namespace gcq {
 
-// x_l <- (x_l + dt q_prev) / (1 - dt s_l) (when `advance`), then the product's
-// columns: X[0] = q_cur, X[1 + l] = w_l x_l / (1 - dt s_l), for l < nq and the
-// n triangles (vector-major, triangle order)
+// complex a / b
+__device__ inline double2 zdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// The product's columns for one step, n triangles each (vector-major, triangle
+// order): the np step-point columns hold q_cur in column kcur and 0 elsewhere;
+// contour column np + l first advances x_l <- (x_l + dt_prev q_prev) /
+// (1 - dt_prev s_l) (when `advance`), then holds w_l x_l / (1 - dt_cur s_l).
 template <typename T>
 __global__ void __launch_bounds__(256) gcq_columns(const double* __restrict__ q_prev,
                                                    const double* __restrict__ q_cur,
-                                                   const double2* __restrict__ inv1m,
-                                                   const double2* __restrict__ wl, int nq, int n,
-                                                   double dt, int advance,
-                                                   double2* __restrict__ x, cpx<T>* __restrict__ X) {
-  const int64_t total = int64_t(nq + 1) * n;
+                                                   const double2* __restrict__ sl,
+                                                   const double2* __restrict__ wl, int np, int kcur,
+                                                   int nq, int n, double dt_prev, double dt_cur,
+                                                   int advance, double2* __restrict__ x,
+                                                   cpx<T>* __restrict__ X) {
+  const int64_t total = int64_t(np + nq) * n;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
     const int col = int(e / n), i = int(e % n);
-    if (col == 0) {
-      X[i] = {T(q_cur[i]), T(0)};
+    if (col < np) {
+      X[e] = {col == kcur ? T(q_cur[i]) : T(0), T(0)};
       continue;
     }
-    const int l = col - 1;
-    const double2 a = inv1m[l];   // 1 / (1 - dt s_l)
+    const int l = col - np;
+    const double2 s = sl[l];
     double2 v = x[int64_t(l) * n + i];
     if (advance) {
-      const double re = v.x + dt * q_prev[i], im = v.y;
-      v = make_double2(re * a.x - im * a.y, re * a.y + im * a.x);
+      v = zdiv(make_double2(v.x + dt_prev * q_prev[i], v.y),
+               make_double2(1.0 - dt_prev * s.x, -dt_prev * s.y));
       x[int64_t(l) * n + i] = v;
     }
-    // w_l v / (1 - dt s_l)
     const double2 b = wl[l];
-    const double pr = v.x * a.x - v.y * a.y, pi = v.x * a.y + v.y * a.x;
-    X[e] = {T(pr * b.x - pi * b.y), T(pr * b.y + pi * b.x)};
+    const double2 u = make_double2(v.x * b.x - v.y * b.y, v.x * b.y + v.y * b.x);   // w_l x_l
+    const double2 r = zdiv(u, make_double2(1.0 - dt_cur * s.x, -dt_cur * s.y));
+    X[e] = {T(r.x), T(r.y)};
   }
 }
 
@@ -69,83 +79,17 @@ __global__ void __launch_bounds__(256) sum_columns_real(const cpx<T>* __restrict
 
 using namespace gcq;
 
-extern "C" GCQ_API int gcq_gcq_convolve(gcq_context* ctx, double dt, int32_t n_steps,
-                                        const gcq_c128* w, int32_t precision, const double* Q,
-                                        double* F) {
-  if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
-  GCQ_NEED_DEVICE(ctx);
-  if (!w || !Q || !F) return fail(GCQ_ERR_ARG, "w, Q and F must not be NULL");
-  if (n_steps < 1) return fail(GCQ_ERR_ARG, "n_steps must be >= 1");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(GCQ_ERR_ARG, "dt must be > 0");
-  if (precision != GCQ_C128 && precision != GCQ_C64)
-    return fail(GCQ_ERR_ARG, "unknown precision %d", precision);
-  if (!ctx->F.valid || ctx->F.precision != precision)
-    return fail(GCQ_ERR_STATE, "run gcq_aca3d at this precision first");
-  const int L = ctx->L, n = ctx->n, nq = L - 1;
-  if (L < 2) return fail(GCQ_ERR_STATE, "the frequency set needs 1/dt and at least one contour point");
-  const std::complex<double> s0 = ctx->s[0];
-  if (std::fabs(s0.real() - 1.0 / dt) > 1e-12 / dt || s0.imag() != 0.0)
-    return fail(GCQ_ERR_STATE, "frequency 0 must be 1/dt (the current-step operator)");
-  GCQ_HIP(hipSetDevice(ctx->device));
-  std::vector<double2> inv1m(nq), wl(nq);
-  for (int l = 0; l < nq; ++l) {
-    const std::complex<double> d = 1.0 - dt * ctx->s[l + 1];
-    if (std::abs(d) == 0.0) return fail(GCQ_ERR_ARG, "contour point %d equals 1/dt", l + 1);
-    const std::complex<double> a = 1.0 / d;
-    inv1m[l] = make_double2(a.real(), a.imag());
-    wl[l] = make_double2(w[l].re, w[l].im);
-  }
-  hipStream_t st = ctx->stream;
-  DevBuf d_inv, d_w, d_x, d_X, d_y;
-  GCQ_TRY(upload(d_inv, inv1m, st));
-  GCQ_TRY(upload(d_w, wl, st));
-  GCQ_TRY(d_x.ensure(sizeof(double2) * size_t(nq) * n));
-  GCQ_HIP(hipMemsetAsync(d_x.p, 0, sizeof(double2) * size_t(nq) * n, st));
-  const size_t csz = csize(precision);
-  GCQ_TRY(d_X.ensure(csz * size_t(L) * n));
-  GCQ_TRY(d_y.ensure(csz * size_t(L) * n));
-  const int grid = int(std::min<int64_t>((int64_t(L) * n + 255) / 256, int64_t(ctx->cus) * 16));
-  // (each product synchronises on its own timing event, so the loop is timed
-  // on the host clock)
-  GCQ_HIP(hipStreamSynchronize(st));
-  const auto t0 = std::chrono::steady_clock::now();
-  for (int step = 0; step < n_steps; ++step) {
-    const double* qp = step > 0 ? Q + int64_t(step - 1) * n : Q;
-    const double* qc = Q + int64_t(step) * n;
-    if (precision == GCQ_C128)
-      hipLaunchKernelGGL(gcq_columns<double>, dim3(grid), dim3(256), 0, st, qp, qc, d_inv.as<double2>(),
-                         d_w.as<double2>(), nq, n, dt, step > 0 ? 1 : 0, d_x.as<double2>(),
-                         d_X.as<cpx<double>>());
-    else
-      hipLaunchKernelGGL(gcq_columns<float>, dim3(grid), dim3(256), 0, st, qp, qc, d_inv.as<double2>(),
-                         d_w.as<double2>(), nq, n, dt, step > 0 ? 1 : 0, d_x.as<double2>(),
-                         d_X.as<cpx<float>>());
-    GCQ_HIP(hipGetLastError());
-    GCQ_TRY(gcq_compressed_matvec(ctx, GCQ_PER_FREQUENCY, precision, d_X.p, d_y.p, L));
-    const int g2 = std::min((n + 255) / 256, ctx->cus * 4);
-    if (precision == GCQ_C128)
-      hipLaunchKernelGGL(sum_columns_real<double>, dim3(g2), dim3(256), 0, st, d_y.as<cpx<double>>(), L,
-                         n, F + int64_t(step) * n);
-    else
-      hipLaunchKernelGGL(sum_columns_real<float>, dim3(g2), dim3(256), 0, st, d_y.as<cpx<float>>(), L, n,
-                         F + int64_t(step) * n);
-    GCQ_HIP(hipGetLastError());
-  }
-  GCQ_HIP(hipStreamSynchronize(st));
-  ctx->kernel_ms["gcq_convolve"] =
-      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  return GCQ_OK;
-}
-
 namespace gcq {
 
-// B[0] = f - h (the system of frequency 0), B[k > 0] = 0
+// B[kcur] = f - h (the system of the current step's point), other columns 0
 __global__ void __launch_bounds__(256) gcq_rhs(const double* __restrict__ f, const double* __restrict__ h,
-                                               int L, int n, cpx<double>* __restrict__ B) {
+                                               int kcur, int L, int n, cpx<double>* __restrict__ B) {
   const int64_t total = int64_t(L) * n;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * blockDim.x)
-    B[e] = e < n ? cpx<double>{f[e] - h[e], 0.0} : cpx<double>{0.0, 0.0};
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int col = int(e / n), i = int(e % n);
+    B[e] = col == kcur ? cpx<double>{f[i] - h[i], 0.0} : cpx<double>{0.0, 0.0};
+  }
 }
 
 __global__ void __launch_bounds__(256) gcq_take_real(const cpx<double>* __restrict__ X, int n,
@@ -153,43 +97,117 @@ __global__ void __launch_bounds__(256) gcq_take_real(const cpx<double>* __restri
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) q[i] = X[i].re;
 }
 
-}  // namespace gcq
+// checks shared by the two entry points; kstep[n] = the frequency 1/dt_n,
+// contour points and weights to the device, state x zeroed
+struct GcqRun {
+  int L = 0, n = 0, np = 0, nq = 0;
+  std::vector<int> kstep;
+  DevBuf d_s, d_w, d_x, d_X, d_Y;
+};
 
-extern "C" GCQ_API int gcq_gcq_solve(gcq_context* ctx, double dt, int32_t n_steps, const gcq_c128* w,
-                                     int32_t precision, const double* F, double* Q, double rtol,
-                                     int32_t max_iter, int32_t restart, int32_t* iters_max) {
+static int gcq_prepare(gcq_context* ctx, const double* dt, int n_steps, int n_step_points,
+                       const gcq_c128* w, int precision, GcqRun& R) {
   if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
   GCQ_NEED_DEVICE(ctx);
-  if (!w || !Q || !F) return fail(GCQ_ERR_ARG, "w, F and Q must not be NULL");
+  if (!dt || !w) return fail(GCQ_ERR_ARG, "dt and w must not be NULL");
   if (n_steps < 1) return fail(GCQ_ERR_ARG, "n_steps must be >= 1");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(GCQ_ERR_ARG, "dt must be > 0");
   if (precision != GCQ_C128 && precision != GCQ_C64)
     return fail(GCQ_ERR_ARG, "unknown precision %d", precision);
   if (!ctx->F.valid || ctx->F.precision != precision)
     return fail(GCQ_ERR_STATE, "run gcq_aca3d at this precision first");
-  const int L = ctx->L, n = ctx->n, nq = L - 1;
-  if (L < 2) return fail(GCQ_ERR_STATE, "the frequency set needs 1/dt and at least one contour point");
-  const std::complex<double> s0 = ctx->s[0];
-  if (std::fabs(s0.real() - 1.0 / dt) > 1e-12 / dt || s0.imag() != 0.0)
-    return fail(GCQ_ERR_STATE, "frequency 0 must be 1/dt (the current-step operator)");
+  R.L = ctx->L;
+  R.n = ctx->n;
+  R.np = n_step_points;
+  R.nq = R.L - R.np;
+  if (R.np < 1 || R.nq < 1)
+    return fail(GCQ_ERR_ARG, "need 1 <= n_step_points < n_freq (step points, then contour points)");
+  R.kstep.assign(n_steps, -1);
+  for (int st = 0; st < n_steps; ++st) {
+    if (!(dt[st] > 0.0) || !std::isfinite(dt[st])) return fail(GCQ_ERR_ARG, "dt[%d] must be > 0", st);
+    for (int k = 0; k < R.np && R.kstep[st] < 0; ++k)
+      if (ctx->s[k].imag() == 0.0 && std::fabs(ctx->s[k].real() - 1.0 / dt[st]) <= 1e-12 / dt[st])
+        R.kstep[st] = k;
+    if (R.kstep[st] < 0)
+      return fail(GCQ_ERR_STATE, "no step-point frequency equals 1/dt of step %d", st);
+  }
   GCQ_HIP(hipSetDevice(ctx->device));
-  std::vector<double2> inv1m(nq), wl(nq);
-  for (int l = 0; l < nq; ++l) {
-    const std::complex<double> d = 1.0 - dt * ctx->s[l + 1];
-    if (std::abs(d) == 0.0) return fail(GCQ_ERR_ARG, "contour point %d equals 1/dt", l + 1);
-    const std::complex<double> a = 1.0 / d;
-    inv1m[l] = make_double2(a.real(), a.imag());
+  std::vector<double2> sl(R.nq), wl(R.nq);
+  for (int l = 0; l < R.nq; ++l) {
+    const std::complex<double> z = ctx->s[R.np + l];
+    sl[l] = make_double2(z.real(), z.imag());
     wl[l] = make_double2(w[l].re, w[l].im);
   }
   hipStream_t st = ctx->stream;
+  GCQ_TRY(upload(R.d_s, sl, st));
+  GCQ_TRY(upload(R.d_w, wl, st));
+  GCQ_TRY(R.d_x.ensure(sizeof(double2) * size_t(R.nq) * R.n));
+  GCQ_HIP(hipMemsetAsync(R.d_x.p, 0, sizeof(double2) * size_t(R.nq) * R.n, st));
   const size_t csz = csize(precision);
-  DevBuf d_inv, d_w, d_x, d_X, d_Y, d_zero, d_h, d_B, d_S;
-  GCQ_TRY(upload(d_inv, inv1m, st));
-  GCQ_TRY(upload(d_w, wl, st));
-  GCQ_TRY(d_x.ensure(sizeof(double2) * size_t(nq) * n));
-  GCQ_HIP(hipMemsetAsync(d_x.p, 0, sizeof(double2) * size_t(nq) * n, st));
-  GCQ_TRY(d_X.ensure(csz * size_t(L) * n));
-  GCQ_TRY(d_Y.ensure(csz * size_t(L) * n));
+  GCQ_TRY(R.d_X.ensure(csz * size_t(R.L) * R.n));
+  GCQ_TRY(R.d_Y.ensure(csz * size_t(R.L) * R.n));
+  return GCQ_OK;
+}
+
+// one product over the set and the column sum into h (length n)
+static int gcq_apply_step(gcq_context* ctx, GcqRun& R, int precision, const double* q_prev,
+                          const double* q_cur, int kcur, double dt_prev, double dt_cur, int advance,
+                          double* h) {
+  hipStream_t st = ctx->stream;
+  const int grid = int(std::min<int64_t>((int64_t(R.L) * R.n + 255) / 256, int64_t(ctx->cus) * 16));
+  const int g2 = std::min((R.n + 255) / 256, ctx->cus * 4);
+  if (precision == GCQ_C128)
+    hipLaunchKernelGGL(gcq_columns<double>, dim3(grid), dim3(256), 0, st, q_prev, q_cur, R.d_s.as<double2>(),
+                       R.d_w.as<double2>(), R.np, kcur, R.nq, R.n, dt_prev, dt_cur, advance,
+                       R.d_x.as<double2>(), R.d_X.as<cpx<double>>());
+  else
+    hipLaunchKernelGGL(gcq_columns<float>, dim3(grid), dim3(256), 0, st, q_prev, q_cur, R.d_s.as<double2>(),
+                       R.d_w.as<double2>(), R.np, kcur, R.nq, R.n, dt_prev, dt_cur, advance,
+                       R.d_x.as<double2>(), R.d_X.as<cpx<float>>());
+  GCQ_HIP(hipGetLastError());
+  GCQ_TRY(gcq_compressed_matvec(ctx, GCQ_PER_FREQUENCY, precision, R.d_X.p, R.d_Y.p, R.L));
+  if (precision == GCQ_C128)
+    hipLaunchKernelGGL(sum_columns_real<double>, dim3(g2), dim3(256), 0, st, R.d_Y.as<cpx<double>>(), R.L,
+                       R.n, h);
+  else
+    hipLaunchKernelGGL(sum_columns_real<float>, dim3(g2), dim3(256), 0, st, R.d_Y.as<cpx<float>>(), R.L, R.n,
+                       h);
+  GCQ_HIP(hipGetLastError());
+  return GCQ_OK;
+}
+
+}  // namespace gcq
+
+extern "C" GCQ_API int gcq_gcq_convolve(gcq_context* ctx, const double* dt, int32_t n_steps,
+                                        int32_t n_step_points, const gcq_c128* w, int32_t precision,
+                                        const double* Q, double* F) {
+  GcqRun R;
+  GCQ_TRY(gcq_prepare(ctx, dt, n_steps, n_step_points, w, precision, R));
+  if (!Q || !F) return fail(GCQ_ERR_ARG, "Q and F must not be NULL");
+  const int n = R.n;
+  GCQ_HIP(hipStreamSynchronize(ctx->stream));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int step = 0; step < n_steps; ++step) {
+    const double* qp = step > 0 ? Q + int64_t(step - 1) * n : Q;
+    GCQ_TRY(gcq_apply_step(ctx, R, precision, qp, Q + int64_t(step) * n, R.kstep[step],
+                           step > 0 ? dt[step - 1] : 0.0, dt[step], step > 0 ? 1 : 0,
+                           F + int64_t(step) * n));
+  }
+  GCQ_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->kernel_ms["gcq_convolve"] =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return GCQ_OK;
+}
+
+extern "C" GCQ_API int gcq_gcq_solve(gcq_context* ctx, const double* dt, int32_t n_steps,
+                                     int32_t n_step_points, const gcq_c128* w, int32_t precision,
+                                     const double* F, double* Q, double rtol, int32_t max_iter,
+                                     int32_t restart, int32_t* iters_max) {
+  GcqRun R;
+  GCQ_TRY(gcq_prepare(ctx, dt, n_steps, n_step_points, w, precision, R));
+  if (!Q || !F) return fail(GCQ_ERR_ARG, "F and Q must not be NULL");
+  const int n = R.n, L = R.L;
+  hipStream_t st = ctx->stream;
+  DevBuf d_zero, d_h, d_B, d_S;
   GCQ_TRY(d_zero.ensure(sizeof(double) * n));
   GCQ_HIP(hipMemsetAsync(d_zero.p, 0, sizeof(double) * n, st));
   GCQ_TRY(d_h.ensure(sizeof(double) * n));
@@ -202,36 +220,19 @@ extern "C" GCQ_API int gcq_gcq_solve(gcq_context* ctx, double dt, int32_t n_step
   GCQ_HIP(hipStreamSynchronize(st));
   const auto t0 = std::chrono::steady_clock::now();
   for (int step = 0; step < n_steps; ++step) {
-    if (step > 0) {
-      // history of the earlier steps: the sum over the contour with the
-      // current-step column left out
-      const double* qp = Q + int64_t(step - 1) * n;
-      if (precision == GCQ_C128)
-        hipLaunchKernelGGL(gcq_columns<double>, dim3(grid), dim3(256), 0, st, qp, d_zero.as<double>(),
-                           d_inv.as<double2>(), d_w.as<double2>(), nq, n, dt, 1, d_x.as<double2>(),
-                           d_X.as<cpx<double>>());
-      else
-        hipLaunchKernelGGL(gcq_columns<float>, dim3(grid), dim3(256), 0, st, qp, d_zero.as<double>(),
-                           d_inv.as<double2>(), d_w.as<double2>(), nq, n, dt, 1, d_x.as<double2>(),
-                           d_X.as<cpx<float>>());
-      GCQ_HIP(hipGetLastError());
-      GCQ_TRY(gcq_compressed_matvec(ctx, GCQ_PER_FREQUENCY, precision, d_X.p, d_Y.p, L));
-      if (precision == GCQ_C128)
-        hipLaunchKernelGGL(sum_columns_real<double>, dim3(g2), dim3(256), 0, st, d_Y.as<cpx<double>>(), L,
-                           n, d_h.as<double>());
-      else
-        hipLaunchKernelGGL(sum_columns_real<float>, dim3(g2), dim3(256), 0, st, d_Y.as<cpx<float>>(), L, n,
-                           d_h.as<double>());
-      GCQ_HIP(hipGetLastError());
-    }
-    // V(1/dt) q_n = f_n - history
-    hipLaunchKernelGGL(gcq_rhs, dim3(grid), dim3(256), 0, st, F + int64_t(step) * n, d_h.as<double>(), L,
+    // history of the earlier steps: the contour sum, no step-point column
+    if (step > 0)
+      GCQ_TRY(gcq_apply_step(ctx, R, precision, Q + int64_t(step - 1) * n, d_zero.as<double>(), -1,
+                             dt[step - 1], dt[step], 1, d_h.as<double>()));
+    // V(1/dt_n) q_n = f_n - history
+    const int k = R.kstep[step];
+    hipLaunchKernelGGL(gcq_rhs, dim3(grid), dim3(256), 0, st, F + int64_t(step) * n, d_h.as<double>(), k, L,
                        n, d_B.as<cpx<double>>());
     GCQ_HIP(hipGetLastError());
     gcq_solve_stats ss;
     GCQ_TRY(gcq_solve(ctx, d_B.p, d_S.p, rtol, max_iter, restart, precision, &ss));
     itmax = std::max(itmax, int(ss.iters_max));
-    hipLaunchKernelGGL(gcq_take_real, dim3(g2), dim3(256), 0, st, d_S.as<cpx<double>>(), n,
+    hipLaunchKernelGGL(gcq_take_real, dim3(g2), dim3(256), 0, st, d_S.as<cpx<double>>() + int64_t(k) * n, n,
                        Q + int64_t(step) * n);
     GCQ_HIP(hipGetLastError());
   }

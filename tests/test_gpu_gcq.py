@@ -99,3 +99,36 @@ def test_gcq_solve_recovers_the_density(setup, prec, tola, tol):
     ctx.gcq_convolve(DT, w_lib, Qd, F2, prec)
     f2 = F2.cpu().numpy().reshape(NSTEP, P.n)
     assert np.linalg.norm(f2 - f_or.real) / np.linalg.norm(f_or.real) <= (1e-9 if prec == g.C128 else 1e-5)
+
+
+def test_gcq_variable_steps_match_oracle():
+    """Variable steps (the generalised scheme): three step sizes, the set
+    [1/dt for each, contour points] without conjugate symmetry; the
+    convolution against the oracle's, and the solve recovers the density."""
+    xyz, tri = mesh.icosphere(2)
+    P = Panels(xyz, tri)
+    steps = np.array([0.04, 0.05, 0.06])
+    dt = steps[np.random.default_rng(11).integers(0, 3, 10)]
+    so, wo = contour.contour(NQ, steps.min(), steps.max())
+    s_or = np.concatenate([1.0 / steps, so]).astype(np.complex128)
+    D = entries.dense(P, s_or, 1.0)
+
+    def apply_V(z, X):
+        return D[int(np.argmin(np.abs(s_or - z)))] @ X
+
+    q = np.random.default_rng(12).standard_normal((len(dt), P.n))
+    f_or = gcq.convolve(apply_V, q, dt, s_or[3:], wo).real
+    s_lib, w_lib = g.contour(NQ, steps.min(), steps.max())
+    ctx = make_ctx(xyz, tri, 1.0, np.concatenate([1.0 / steps, s_lib]), 16, 1.0, sym=False)
+    ctx.aca3d(1e-10, 1e-10, 64, g.C128)
+    Q = torch.from_numpy(q.reshape(-1)).cuda()
+    F = torch.full_like(Q, np.nan)
+    ctx.gcq_convolve(dt, w_lib, Q, F, g.C128, n_step_points=3)
+    f = F.cpu().numpy().reshape(len(dt), P.n)
+    assert np.linalg.norm(f - f_or) / np.linalg.norm(f_or) <= 1e-8
+    Q2 = torch.full_like(Q, np.nan)
+    ctx.gcq_solve(dt, w_lib, F, Q2, g.C128, rtol=1e-12, max_iter=400, n_step_points=3)
+    q2 = Q2.cpu().numpy().reshape(len(dt), P.n)
+    assert np.linalg.norm(q2 - q) / np.linalg.norm(q) <= 1e-6
+    with pytest.raises(g.GcqError):   # a step whose 1/dt is not a step point
+        ctx.gcq_convolve(np.full(len(dt), 0.045), w_lib, Q, F, g.C128, n_step_points=3)
