@@ -67,3 +67,70 @@ def solve(apply_V, solve_V, f, dt, s, w):
                 h = h + apply_V(s[l], w[l] * x[l] / (1.0 - dt[n] * s[l]))
         q[n] = solve_V(1.0 / dt[n], f[n] - h)
     return q
+
+
+# ---- Runge-Kutta methods of m stages ------------------------------------------
+# The paper's scheme for an A- and L-stable method (c | A, b^T) with
+# b^T A^{-1} = (0, .., 0, 1): quantities per node carry the m stage values;
+# V((dt A)^{-1}) acts through the eigendecomposition (dt A)^{-1} = P diag(lam) P^{-1}
+# as P diag(V(lam_e)) P^{-1}; b^T A^{-1} x picks the last stage.
+
+def radau_iia(m: int):
+    """Butcher matrix A of the Radau IIA method with m = 1, 2 or 3 stages."""
+    if m == 1:
+        return np.array([[1.0]])
+    if m == 2:
+        return np.array([[5.0 / 12.0, -1.0 / 12.0], [0.75, 0.25]])
+    if m == 3:
+        r = np.sqrt(6.0)
+        return np.array([[(88 - 7 * r) / 360, (296 - 169 * r) / 1800, (-2 + 3 * r) / 225],
+                         [(296 + 169 * r) / 1800, (88 + 7 * r) / 360, (-2 - 3 * r) / 225],
+                         [(16 - r) / 36, (16 + r) / 36, 1.0 / 9.0]])
+    raise ValueError("m must be 1, 2 or 3")
+
+
+def contour_steps(A, dt_min: float, dt_max: float):
+    """Arguments (dt_min, dt_max, stage_ratio) of oracle.contour for method A.
+
+    Reading of App. A for m > 1 stages: q = 5 dt_max max|lambda(A)| /
+    (dt_min min|lambda(A)|) as printed, and the dt_min that scales gamma is the
+    smallest effective step dt_min min|lambda(A)|, so that the contour encloses
+    the poles 1/(dt lambda) of (I - dt s A)^{-1} (with dt_min itself they lie
+    outside for Radau IIA and the scheme fails; with this reading it reproduces
+    Radau IIA, which the tests check).  One stage: (dt_min, dt_max, 1)."""
+    ev = np.abs(np.linalg.eigvals(np.asarray(A, dtype=np.float64)))
+    if len(ev) == 1:
+        return dt_min * ev[0], dt_max * ev[0], 1.0
+    return dt_min * ev.min(), dt_max * ev.max(), 5.0
+
+
+def _matrix_V(apply_V, Z, Qs):
+    lam, P = np.linalg.eig(Z)
+    R = np.linalg.solve(P, Qs)
+    return P @ np.stack([apply_V(lam[e], R[e]) for e in range(len(lam))])
+
+
+def convolve_rk(apply_V, A, q, dt, s, w):
+    """Stage values f (N, m, M) from stage values q (N, m, M): the first step
+    f_1 = V((dt_1 A)^{-1}) q_1, then eq. gCQ_xn and eq. gcq_formula."""
+    A = np.asarray(A, dtype=np.float64)
+    m = A.shape[0]
+    q = np.asarray(q, dtype=np.complex128)
+    dt = np.asarray(dt, dtype=np.float64)
+    N, _, M = q.shape
+    one = np.ones(m)
+    I = np.eye(m)
+    x = np.zeros((len(s), m, M), dtype=np.complex128)
+    f = np.zeros((N, m, M), dtype=np.complex128)
+    f[0] = _matrix_V(apply_V, np.linalg.inv(dt[0] * A), q[0])
+    for n in range(1, N):
+        for l in range(len(s)):
+            rhs = np.outer(one, x[l, m - 1]) + dt[n - 1] * (A @ q[n - 1])
+            x[l] = np.linalg.solve(I - dt[n - 1] * s[l] * A, rhs)
+        acc = _matrix_V(apply_V, np.linalg.inv(dt[n] * A), q[n])
+        for l in range(len(s)):
+            u = np.linalg.solve(I - dt[n] * s[l] * A, one)
+            W = w[l] * np.outer(u, x[l, m - 1])
+            acc = acc + np.stack([apply_V(s[l], W[i]) for i in range(m)])
+        f[n] = acc
+    return f

@@ -91,3 +91,54 @@ def test_solve_and_convolve_are_inverse_for_a_matrix_operator():
     f = gcq.convolve(V, q, dt, s, w)
     q2 = gcq.solve(V, Vinv, f, dt, s, w)
     assert np.max(np.abs(q2 - q)) <= 1e-9 * np.max(np.abs(q))
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_radau_iia_tableaux(m):
+    """Order conditions of Radau IIA (c = A 1, b^T A^{-1} = (0,..,0,1), c_m = 1)
+    and the stage order: A c^{k-1} = c^k / k for k <= m."""
+    A = gcq.radau_iia(m)
+    c = A @ np.ones(m)
+    b = A[-1]
+    assert abs(c[-1] - 1.0) < 1e-14
+    e = np.zeros(m)
+    e[-1] = 1.0
+    assert np.max(np.abs(b @ np.linalg.inv(A) - e)) < 1e-13
+    for k in range(1, m + 1):
+        assert np.max(np.abs(A @ c ** (k - 1) - c ** k / k)) < 1e-13
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_rk_scheme_reproduces_radau_iia(m):
+    """V = 1/(s + lam): the gCQ stage values are those of Radau IIA applied to
+    f' = -lam f + q: F_n = (I + lam dt A)^{-1} (f_{n-1} 1 + dt A Q_n), f_n the
+    last stage; V = s: stage derivatives (dt A)^{-1} (Q_n - q_{n-1} 1)."""
+    A = gcq.radau_iia(m)
+    rng = np.random.default_rng(13)
+    N = 14
+    dt = 0.01 * (1.0 + 3.0 * rng.random(N))
+    s, w = contour.contour(101 if m == 2 else 301, *gcq.contour_steps(A, dt.min(), dt.max()))
+    q = rng.standard_normal((N, m, 3))
+    lam = 40.0
+    f = gcq.convolve_rk(lambda z, X: X / (z + lam), A, q, dt, s, w)
+    prev = np.zeros(3)
+    ref = np.zeros_like(q)
+    for n in range(N):
+        F = np.linalg.solve(np.eye(m) + lam * dt[n] * A, np.outer(np.ones(m), prev) + dt[n] * (A @ q[n]))
+        ref[n] = F
+        prev = F[-1]
+    assert np.max(np.abs(f - ref)) <= 1e-9 * np.max(np.abs(ref))
+    d = gcq.convolve_rk(lambda z, X: z * X, A, q, dt, s, w)
+    qprev = np.zeros(3)
+    for n in range(N):
+        dref = np.linalg.solve(dt[n] * A, q[n] - np.outer(np.ones(m), qprev))
+        assert np.max(np.abs(d[n] - dref)) <= 1e-8 * np.max(np.abs(dref)), n
+        qprev = q[n, -1]
+
+
+def test_rk_one_stage_is_implicit_euler_scheme():
+    dt, s, w, q = _setup(12, seed=14)
+    V = lambda z, X: X / (z + 25.0)
+    f1 = gcq.convolve(V, q, dt, s, w)
+    fr = gcq.convolve_rk(V, gcq.radau_iia(1), q[:, None, :], dt, s, w)[:, 0, :]
+    assert np.max(np.abs(f1 - fr)) <= 1e-12 * np.max(np.abs(f1))
