@@ -232,40 +232,47 @@ GCQ_API int gcq_contour(int32_t n_points, double dt_min, double dt_max, double s
                         gcq_c128* s, gcq_c128* w);
 
 /* gcq_gcq_convolve: the forward gCQ convolution f = V * q (Sec. 3: the first
- *   step, eq. gCQ_xn and eq. gcq_formula) with implicit Euler (A = b = c = 1)
- *   on the operator gcq_aca3d built at `precision`, for n_steps steps of sizes
- *   dt[0..n_steps) (host array; variable steps are what the generalised scheme
- *   is for).  The context's frequency set must be [step points, contour
- *   points]: its first n_step_points frequencies are the distinct values 1/dt_n
- *   (real; every step's 1/dt_n must be among them, GCQ_ERR_STATE otherwise),
- *   the remaining NQ = n_freq - n_step_points are the contour points, whose
- *   weights w (host, NQ complex doubles, as gcq_contour returns them) are
- *   passed here.  One step point and odd NQ give the pairing k <-> n_freq - k
- *   that conjugate symmetry uses; more step points need a set without it.
- *   Per step n:
- *     x_{n-1}(s_l) = (x_{n-2}(s_l) + dt_{n-1} q_{n-1}) / (1 - dt_{n-1} s_l), x_0 = 0,
- *     f_n = V(1/dt_n) q_n + sum_l V(s_l) w_l x_{n-1}(s_l) / (1 - dt_n s_l)
- *   (one product over the set, summed over its columns: f_n is the real
- *   part).  Q (input) and F (output) are device arrays of n_steps x
- *   n_triangles doubles, step-major, triangle order.  The state x (NQ x n
- *   complex doubles) and the product's columns are allocated for the call;
- *   returns after the last step. */
-GCQ_API int gcq_gcq_convolve(gcq_context* ctx, const double* dt, int32_t n_steps,
-                             int32_t n_step_points, const gcq_c128* w, int32_t precision,
-                             const double* Q, double* F);
+ *   step, eq. gCQ_xn and eq. gcq_formula) for an m-stage Runge-Kutta method
+ *   with Butcher matrix A (host, m x m doubles, row-major, 1 <= m <= 4, with
+ *   b^T A^{-1} = (0, .., 0, 1) as for Radau IIA; implicit Euler is m = 1,
+ *   A = (1)) on the operator gcq_aca3d built at `precision`, for n_steps steps
+ *   of sizes dt[0..n_steps) (host array; variable steps are what the
+ *   generalised scheme is for).  The context's frequency set must be [step
+ *   points, contour points]: among its first n_step_points frequencies are the
+ *   values lam_e / dt_n for every eigenvalue lam_e of A^{-1} and every step
+ *   (1/dt_n for implicit Euler; matched to 1e-10 relative, GCQ_ERR_STATE
+ *   otherwise), the remaining NQ = n_freq - n_step_points are the contour
+ *   points, whose weights w (host, NQ complex doubles, as gcq_contour returns
+ *   them) are passed here.  One step point and odd NQ give the pairing
+ *   k <-> n_freq - k that conjugate symmetry uses; more step points need a set
+ *   without it.  With A^{-1} = P diag(lam) P^{-1} and M_l(dt) = (I - dt s_l A)^{-1},
+ *   per step n:
+ *     x_{n-1}(s_l) = M_l(dt_{n-1}) ((x_{n-2}(s_l))_m 1 + dt_{n-1} A q_{n-1}), x_0 = 0,
+ *     f_n = P diag(V(lam_e / dt_n)) P^{-1} q_n + sum_l V(s_l) w_l (x_{n-1}(s_l))_m M_l(dt_n) 1
+ *   (per stage one product over the set, summed over its columns: the stage
+ *   value is the real part).  Q (input) and F (output) are device arrays of
+ *   n_steps x m x n_triangles doubles (step, stage, triangle order).  The
+ *   state (NQ x n complex doubles: only the last stage of x enters) and the
+ *   product's columns are allocated for the call; returns after the last step.
+ *   GCQ_ERR_ARG for a singular A, GCQ_ERR_NUMERIC when A^{-1} is not
+ *   diagonalisable with distinct eigenvalues. */
+GCQ_API int gcq_gcq_convolve(gcq_context* ctx, const double* A, int32_t m, const double* dt,
+                             int32_t n_steps, int32_t n_step_points, const gcq_c128* w,
+                             int32_t precision, const double* Q, double* F);
 
 /* gcq_gcq_solve: the same scheme with (f)_n given and the density unknown
- *   (eq. gcq_formula, "solve the system in case (f)_n is given"): per step the
- *   history h = sum_l V(s_l) w_l x_{n-1}(s_l) / (1 - dt_n s_l) of the densities
- *   found so far, then V(1/dt_n) q_n = f_n - h by GMRES (gcq_solve's batched
- *   solver; the other frequencies' systems have zero right-hand sides and end
- *   at once).  F (input) and Q (output): device doubles, n_steps x n_triangles,
- *   step-major.  rtol, max_iter, restart as in gcq_solve; *iters_max (may be
- *   NULL) receives the largest iteration count of a step. */
-GCQ_API int gcq_gcq_solve(gcq_context* ctx, const double* dt, int32_t n_steps,
-                          int32_t n_step_points, const gcq_c128* w, int32_t precision,
-                          const double* F, double* Q, double rtol, int32_t max_iter,
-                          int32_t restart, int32_t* iters_max);
+ *   (eq. gcq_formula, solved step by step for q_n): per step the history
+ *   h = sum_l V(s_l) w_l (x_{n-1}(s_l))_m M_l(dt_n) 1 of the densities found so
+ *   far, then V((dt_n A)^{-1}) q_n = f_n - h, decoupled by P into the systems
+ *   V(lam_e / dt_n) y_e = (P^{-1} (f_n - h))_e solved by GMRES (gcq_solve's
+ *   batched solver; the other frequencies' systems have zero right-hand sides
+ *   and end at once), q_n = P y.  F (input) and Q (output): device doubles,
+ *   n_steps x m x n_triangles.  rtol, max_iter, restart as in gcq_solve;
+ *   *iters_max (may be NULL) receives the largest iteration count of a step. */
+GCQ_API int gcq_gcq_solve(gcq_context* ctx, const double* A, int32_t m, const double* dt,
+                          int32_t n_steps, int32_t n_step_points, const gcq_c128* w,
+                          int32_t precision, const double* F, double* Q, double rtol,
+                          int32_t max_iter, int32_t restart, int32_t* iters_max);
 
 /* gcq_build_cluster_tree: cluster tree and block cluster tree of Sec. 4
  *   (eq. admissible with parameter eta > 0, leaves of at most leaf_size

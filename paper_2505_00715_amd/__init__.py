@@ -89,8 +89,8 @@ def _load():
         "gcq_upload_mesh": [P, P, I64, P, I64, D],
         "gcq_set_frequencies": [P, P, I32, I32],
         "gcq_contour": [I32, D, D, D, P, P],
-        "gcq_gcq_convolve": [P, P, I32, I32, P, I32, P, P],
-        "gcq_gcq_solve": [P, P, I32, I32, P, I32, P, P, D, I32, I32, P],
+        "gcq_gcq_convolve": [P, P, I32, P, I32, I32, P, I32, P, P],
+        "gcq_gcq_solve": [P, P, I32, P, I32, I32, P, I32, P, P, D, I32, I32, P],
         "gcq_build_cluster_tree": [P, I32, D, P],
         "gcq_get_tree": [P, P, P],
         "gcq_assemble_slices": [P, P, I64, P, I64, P, I32, I32, P],
@@ -312,34 +312,45 @@ class Context:
         _check(_lib.gcq_compressed_matvec(self._h, mode, precision, px, py, self.L))
         return Y
 
-    def gcq_convolve(self, dt, w, Q, F, precision: int = C128, n_step_points: int = 1):
+    def gcq_convolve(self, dt, w, Q, F, precision: int = C128, n_step_points: int = 1, A=None):
         """Forward gCQ convolution (gcq_gcq_convolve): dt the step sizes (a
-        number for constant steps), Q, F device float64 tensors of n_steps x n,
-        w the contour weights (host)."""
+        number for constant steps), A the Butcher matrix (None: implicit
+        Euler), Q, F device float64 tensors of n_steps x m x n, w the contour
+        weights (host)."""
         import torch
-        n_steps = Q.numel() // self.n
+        Ah, pa, m = self._butcher(A)
+        n_steps = Q.numel() // (m * self.n)
         dth, pd = _host(np.broadcast_to(np.asarray(dt, np.float64), (n_steps,)), np.float64)
         wh, pw = _host(w, np.complex128)
-        pq = _dev(Q, torch.float64, n_steps * self.n, "Q")
-        pf = _dev(F, torch.float64, n_steps * self.n, "F")
-        _check(_lib.gcq_gcq_convolve(self._h, pd, int(n_steps), int(n_step_points), pw, precision,
+        pq = _dev(Q, torch.float64, n_steps * m * self.n, "Q")
+        pf = _dev(F, torch.float64, n_steps * m * self.n, "F")
+        _check(_lib.gcq_gcq_convolve(self._h, pa, m, pd, int(n_steps), int(n_step_points), pw, precision,
                                      pq, pf))
         return F
 
     def gcq_solve(self, dt, w, F, Q, precision: int = C128, rtol: float = 1e-8,
-                  max_iter: int = 300, restart: int = 50, n_step_points: int = 1) -> int:
+                  max_iter: int = 300, restart: int = 50, n_step_points: int = 1, A=None) -> int:
         """Densities of the gCQ scheme for given f (gcq_gcq_solve): F, Q device
-        float64 tensors of n_steps x n; returns the largest GMRES count."""
+        float64 tensors of n_steps x m x n; returns the largest GMRES count."""
         import torch
-        n_steps = F.numel() // self.n
+        Ah, pa, m = self._butcher(A)
+        n_steps = F.numel() // (m * self.n)
         dth, pd = _host(np.broadcast_to(np.asarray(dt, np.float64), (n_steps,)), np.float64)
         wh, pw = _host(w, np.complex128)
-        pf = _dev(F, torch.float64, n_steps * self.n, "F")
-        pq = _dev(Q, torch.float64, n_steps * self.n, "Q")
+        pf = _dev(F, torch.float64, n_steps * m * self.n, "F")
+        pq = _dev(Q, torch.float64, n_steps * m * self.n, "Q")
         it = C.c_int32(0)
-        _check(_lib.gcq_gcq_solve(self._h, pd, int(n_steps), int(n_step_points), pw, precision,
+        _check(_lib.gcq_gcq_solve(self._h, pa, m, pd, int(n_steps), int(n_step_points), pw, precision,
                                   pf, pq, float(rtol), int(max_iter), int(restart), C.byref(it)))
         return it.value
+
+    @staticmethod
+    def _butcher(A):
+        A = np.ones((1, 1)) if A is None else np.asarray(A, np.float64)
+        if A.ndim != 2 or A.shape[0] != A.shape[1]:
+            raise ValueError("A must be a square Butcher matrix")
+        Ah, pa = _host(A, np.float64)
+        return Ah, pa, int(A.shape[0])
 
     def solve(self, B, X, rtol: float = 1e-6, max_iter: int = 500, restart: int = 50,
               precision: int = C64) -> SolveStats:

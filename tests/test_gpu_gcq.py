@@ -132,3 +132,67 @@ def test_gcq_variable_steps_match_oracle():
     assert np.linalg.norm(q2 - q) / np.linalg.norm(q) <= 1e-6
     with pytest.raises(g.GcqError):   # a step whose 1/dt is not a step point
         ctx.gcq_convolve(np.full(len(dt), 0.045), w_lib, Q, F, g.C128, n_step_points=3)
+
+
+def _rk_case(m, steps, dt, seed):
+    """Set [lam_e / dt for every step size, contour] for Radau IIA of m stages,
+    the contour of the reading oracle.gcq.contour_steps, dense operators."""
+    xyz, tri = mesh.icosphere(2)
+    P = Panels(xyz, tri)
+    A = gcq.radau_iia(m)
+    lam = np.linalg.eigvals(np.linalg.inv(A))
+    pts = np.concatenate([lam / h for h in steps])
+    args = gcq.contour_steps(A, steps.min(), steps.max())
+    so, wo = contour.contour(NQ, *args)
+    s_or = np.concatenate([pts, so]).astype(np.complex128)
+    D = entries.dense(P, s_or, 1.0)
+
+    def apply_V(z, X):
+        return D[int(np.argmin(np.abs(s_or - z)))] @ X
+
+    q = np.random.default_rng(seed).standard_normal((len(dt), m, P.n))
+    f_or = gcq.convolve_rk(apply_V, A, q, dt, so, wo)
+    assert np.max(np.abs(f_or.imag)) <= 1e-9 * np.max(np.abs(f_or.real))
+    s_lib, w_lib = g.contour(NQ, *args)
+    ctx = make_ctx(xyz, tri, 1.0, np.concatenate([pts, s_lib]), 16, 1.0, sym=False)
+    ctx.aca3d(1e-10, 1e-10, 64, g.C128)
+    return ctx, A, P, q, f_or.real, w_lib, len(pts)
+
+
+@pytest.mark.parametrize("m,steps", [(2, np.array([0.05])), (3, np.array([0.04, 0.06]))])
+def test_gcq_runge_kutta_matches_oracle(m, steps):
+    """Radau IIA with 2 stages (constant steps) and 3 stages (two step sizes):
+    the stage values of the convolution against the oracle's scheme, and the
+    solve recovers the stage densities."""
+    dt = steps[np.random.default_rng(21).integers(0, len(steps), 8)]
+    ctx, A, P, q, f_or, w_lib, npts = _rk_case(m, steps, dt, 22)
+    Q = torch.from_numpy(q.reshape(-1)).cuda()
+    F = torch.full_like(Q, np.nan)
+    ctx.gcq_convolve(dt, w_lib, Q, F, g.C128, n_step_points=npts, A=A)
+    f = F.cpu().numpy().reshape(len(dt), m, P.n)
+    err = np.linalg.norm(f - f_or) / np.linalg.norm(f_or)
+    assert err <= 1e-8, err
+    per = np.linalg.norm(f - f_or, axis=2) / np.linalg.norm(f_or, axis=2)   # every step and stage
+    assert np.all(per <= 1e-7), per
+    Q2 = torch.full_like(Q, np.nan)
+    ctx.gcq_solve(dt, w_lib, F, Q2, g.C128, rtol=1e-12, max_iter=400, n_step_points=npts, A=A)
+    q2 = Q2.cpu().numpy().reshape(len(dt), m, P.n)
+    assert np.linalg.norm(q2 - q) / np.linalg.norm(q) <= 1e-6
+
+
+def test_gcq_runge_kutta_rejects_bad_methods():
+    steps = np.array([0.05])
+    dt = np.full(4, 0.05)
+    ctx, A, P, q, f_or, w_lib, npts = _rk_case(2, steps, dt, 23)
+    Q = torch.zeros(len(dt) * 2 * P.n, dtype=torch.float64, device="cuda")
+    F = torch.zeros_like(Q)
+    with pytest.raises(g.GcqError):   # singular A
+        ctx.gcq_convolve(dt, w_lib, Q, F, g.C128, n_step_points=npts, A=np.zeros((2, 2)))
+    with pytest.raises(g.GcqError):   # another method: its step points are not in the set
+        ctx.gcq_convolve(dt, w_lib, Q, F, g.C128, n_step_points=npts, A=np.array([[0.3, 0.1], [0.6, 0.4]]))
+    with pytest.raises(g.GcqError):   # A^{-1} with a repeated eigenvalue (not diagonalisable)
+        ctx.gcq_convolve(dt, w_lib, Q, F, g.C128, n_step_points=npts, A=np.array([[0.6, 0.0], [0.5, 0.6]]))
+    with pytest.raises(g.GcqError):   # m > 4
+        ctx.gcq_convolve(dt, w_lib, torch.zeros(len(dt) * 5 * P.n, dtype=torch.float64, device="cuda"),
+                         torch.zeros(len(dt) * 5 * P.n, dtype=torch.float64, device="cuda"), g.C128,
+                         n_step_points=npts, A=np.eye(5))
