@@ -231,6 +231,14 @@ GCQ_API int gcq_set_frequencies(gcq_context* ctx, const gcq_c128* s, int32_t n_f
 GCQ_API int gcq_contour(int32_t n_points, double dt_min, double dt_max, double stage_ratio,
                         gcq_c128* s, gcq_c128* w);
 
+/* gcq_contour_points: the number N_Q of contour points for n_steps >= 2 steps
+ *   of a method with `stages` stages (Sec. 3, cost estimate after
+ *   eq. gcq_formula, and App. A): N log N for one stage, N (log N)^2 for more,
+ *   natural logarithm, as twice the rounded half (the points pair up by
+ *   conjugation; the half is what Sec. 5.1 tabulates).  GCQ_ERR_ARG for
+ *   n_steps < 2, stages < 1 or a count beyond int32. */
+GCQ_API int gcq_contour_points(int32_t n_steps, int32_t stages, int32_t* n_points);
+
 /* gcq_gcq_convolve: the forward gCQ convolution f = V * q (Sec. 3: the first
  *   step, eq. gCQ_xn and eq. gcq_formula) for an m-stage Runge-Kutta method
  *   with Butcher matrix A (host, m x m doubles, row-major, 1 <= m <= 4, with

@@ -42,6 +42,19 @@ import numpy as np
 from scipy import special
 
 
+def n_points(n_steps: int, stages: int) -> int:
+    """Number N_Q of contour points for N = n_steps steps (Sec. 3, cost estimate
+    after eq. gcq_formula, and App. A): N log N for one stage, N (log N)^2 for
+    m > 1 stages, natural logarithm.  Reading: the points come in conjugate
+    pairs and only half of them are computed (Sec. 5.1), so N_Q is taken as
+    twice the rounded half, 2 round(N (log N)^p / 2); the half N_Q / 2 is what
+    the table of the unit-cube meshes (Sec. 5.1) lists for 2-stage Radau IIA."""
+    if n_steps < 2 or stages < 1:
+        raise ValueError("need n_steps >= 2 and stages >= 1")
+    p = 1 if stages == 1 else 2
+    return 2 * int(round(n_steps * np.log(n_steps) ** p / 2.0))
+
+
 def modulus(q: float) -> float:
     r = np.sqrt(2.0 * q - 1.0)
     return (q - r) / (q + r)

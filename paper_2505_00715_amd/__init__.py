@@ -89,6 +89,7 @@ def _load():
         "gcq_upload_mesh": [P, P, I64, P, I64, D],
         "gcq_set_frequencies": [P, P, I32, I32],
         "gcq_contour": [I32, D, D, D, P, P],
+        "gcq_contour_points": [I32, I32, P],
         "gcq_gcq_convolve": [P, P, I32, P, I32, I32, P, I32, P, P],
         "gcq_gcq_solve": [P, P, I32, P, I32, I32, P, I32, P, P, D, I32, I32, P],
         "gcq_build_cluster_tree": [P, I32, D, P],
@@ -152,6 +153,13 @@ def contour(n_points: int, dt_min: float, dt_max: float, stage_ratio: float = 1.
     _check(_lib.gcq_contour(int(n_points), float(dt_min), float(dt_max), float(stage_ratio),
                             s.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p)))
     return s, w
+
+
+def contour_points(n_steps: int, stages: int = 2) -> int:
+    """Number of contour points for n_steps steps (gcq_contour_points)."""
+    n = C.c_int32(0)
+    _check(_lib.gcq_contour_points(int(n_steps), int(stages), C.byref(n)))
+    return n.value
 
 
 class Context:

@@ -109,3 +109,13 @@ extern "C" GCQ_API int gcq_contour(int32_t n_points, double dt_min, double dt_ma
   }
   return GCQ_OK;
 }
+
+extern "C" GCQ_API int gcq_contour_points(int32_t n_steps, int32_t stages, int32_t* n_points) {
+  if (!n_points) return fail(GCQ_ERR_ARG, "n_points must not be NULL");
+  if (n_steps < 2 || stages < 1) return fail(GCQ_ERR_ARG, "need n_steps >= 2 and stages >= 1");
+  const double lg = std::log(double(n_steps));
+  const double half = 0.5 * n_steps * (stages == 1 ? lg : lg * lg);
+  if (!(half < 1e9)) return fail(GCQ_ERR_ARG, "n_steps too large");
+  *n_points = 2 * int32_t(std::llround(half));
+  return GCQ_OK;
+}

@@ -42,3 +42,33 @@ def test_contour_argument_errors():
                  (8, 0.01, 0.02, 0.5), (8, 0.01, 0.01, 1.0)):
         with pytest.raises(g.GcqError):
             g.contour(*args)
+
+
+def _cube_rows():
+    import os
+    rows = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "cube_refinement.txt")):
+        if line.strip() and not line.startswith("#"):
+            rows.append([float(x) for x in line.split()])
+    return rows
+
+
+@pytest.mark.parametrize("row", _cube_rows(), ids=lambda r: f"level{int(r[0])}")
+def test_contour_points_match_cube_table(row):
+    """N_Q of the unit-cube table (Sec. 5.1, 2-stage Radau IIA) is the half of
+    N (ln N)^2 points: the oracle's rule and the library's both give it."""
+    N, half = int(row[5]), int(row[6])
+    assert C.n_points(N, 2) == 2 * half
+    assert g.contour_points(N, 2) == 2 * half
+
+
+def test_contour_points_one_stage_and_errors():
+    for N in (2, 10, 64, 1000, 12345):
+        assert g.contour_points(N, 1) == C.n_points(N, 1)
+        assert g.contour_points(N, 3) == C.n_points(N, 3)
+    assert C.n_points(100, 1) == 2 * round(100 * np.log(100) / 2)
+    for bad in ((1, 1), (0, 2), (10, 0)):
+        with pytest.raises(g.GcqError):
+            g.contour_points(*bad)
+        with pytest.raises(ValueError):
+            C.n_points(*bad)
