@@ -305,6 +305,17 @@ GCQ_API int gcq_assemble_slices(gcq_context* ctx, const int32_t* rows, int64_t n
                                 const int32_t* cols, int64_t n_cols, const int32_t* freq_idx,
                                 int32_t n_fidx, int32_t precision, void* out_dev);
 
+/* gcq_assemble_dlp_slices: dense double-layer entries K(s_f)[rows[a], cols[b]]
+ *   (Sec. 2, eq. dlp, transformed as in Sec. 3): the integral over panel
+ *   cols[b] of the normal derivative in y (outward unit normal of the panel,
+ *   from its vertex order) of exp(-s r / c) / (4 pi r), collocated at the
+ *   centroid of panel rows[a] with piecewise-constant densities; self entries
+ *   are 0 (flat panels), near and far tiers as in gcq_assemble_slices (near
+ *   always in float64).  Arguments, layout and errors as gcq_assemble_slices. */
+GCQ_API int gcq_assemble_dlp_slices(gcq_context* ctx, const int32_t* rows, int64_t n_rows,
+                                    const int32_t* cols, int64_t n_cols, const int32_t* freq_idx,
+                                    int32_t n_fidx, int32_t precision, void* out_dev);
+
 /* ---- H-matrix faces per frequency (Sec. 4) --------------------------------
  * gcq_aca_blocks: ACA (partial pivoting, relative tolerance tol, at most
  *   max_rank terms) of every admissible block at every frequency of K (or of

@@ -95,6 +95,7 @@ def _load():
         "gcq_build_cluster_tree": [P, I32, D, P],
         "gcq_get_tree": [P, P, P],
         "gcq_assemble_slices": [P, P, I64, P, I64, P, I32, I32, P],
+        "gcq_assemble_dlp_slices": [P, P, I64, P, I64, P, I32, I32, P],
         "gcq_aca_blocks": [P, P, I32, D, I32, I32, U32, P],
         "gcq_get_block_factors": [P, I32, I32, P, P, I32, P],
         "gcq_aca3d": [P, D, D, I32, I32, U32, P],
@@ -256,6 +257,18 @@ class Context:
         po = _dev(out, dt, len(fi) * len(cols) * len(rows), "out")
         _check(_lib.gcq_assemble_slices(self._h, pr, len(rows), pc, len(cols), pf, len(fi),
                                         precision, po))
+        return out
+
+    def assemble_dlp_slices(self, rows, cols, freq_idx, precision, out):
+        """Dense double-layer entries (gcq_assemble_dlp_slices), layout as assemble_slices."""
+        import torch
+        rows, pr = _host(rows, np.int32)
+        cols, pc = _host(cols, np.int32)
+        fi, pf = _host(freq_idx, np.int32)
+        dt = torch.complex128 if precision == C128 else torch.complex64
+        po = _dev(out, dt, len(fi) * len(cols) * len(rows), "out")
+        _check(_lib.gcq_assemble_dlp_slices(self._h, pr, len(rows), pc, len(cols), pf, len(fi),
+                                            precision, po))
         return out
 
     # ---- per-frequency H-matrices
