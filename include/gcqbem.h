@@ -90,7 +90,10 @@ enum {
 enum {
   GCQ_FLAG_RECOMPRESS = 1u,      /* QR/SVD recompression after ACA (Sec. 4)          */
   GCQ_FLAG_USE_PREDICTOR = 2u,   /* size work tiles from the trained rank model      */
-  GCQ_FLAG_PER_FREQ_LAUNCH = 4u  /* one launch per frequency, no batching (baseline)  */
+  GCQ_FLAG_PER_FREQ_LAUNCH = 4u, /* one launch per frequency, no batching (baseline)  */
+  GCQ_FLAG_DOUBLE_LAYER = 8u     /* faces of the double layer K (Sec. 2 eq. dlp) with
+                                    the entries of gcq_assemble_dlp_slices; not with
+                                    GCQ_FLAG_USE_PREDICTOR (GCQ_ERR_ARG)            */
 };
 
 /* Launch configuration (gcq_set_tuning / gcq_get_tuning).

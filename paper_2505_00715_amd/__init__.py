@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgcqbem.so")
 
 C128, C64 = 0, 1
 PER_FREQUENCY, WEIGHTED_SUM, PLAIN_H = 0, 1, 2
-FLAG_RECOMPRESS, FLAG_USE_PREDICTOR, FLAG_PER_FREQ_LAUNCH = 1, 2, 4
+FLAG_RECOMPRESS, FLAG_USE_PREDICTOR, FLAG_PER_FREQ_LAUNCH, FLAG_DOUBLE_LAYER = 1, 2, 4, 8
 OK, NOT_CONVERGED, RANK_CAPPED = 0, 1, 2
 N_MODEL_PARAMS = 4609
 

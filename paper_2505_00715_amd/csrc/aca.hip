@@ -12,7 +12,7 @@
 namespace gcq {
 
 // ---- 2D ACA kernels: one wave per (block, frequency) pair ------------------------
-template <typename T, bool ALLFAR>
+template <typename T, bool ALLFAR, bool DLP>
 struct PlainEntry {
   const Tab* tab;
   int rb, cb;
@@ -21,14 +21,14 @@ struct PlainEntry {
   __device__ void prep_row(int) {}
   __device__ void prep_col(int) {}
   __device__ cpx<T> part(int i, int j, int p, int P) const {
-    return entry_part<T, ALLFAR>(*tab, rb + i, cb + j, sr, si, all_far, p, P);
+    return op_entry_part<T, ALLFAR, DLP>(*tab, rb + i, cb + j, sr, si, all_far, p, P);
   }
 };
 
 // ALLFAR = true serves the pairs of blocks without self/near-tier entries,
 // ALLFAR = false the others; each instance skips the pairs of the other kind.
-// NW waves work on one pair together.
-template <typename T, bool ALLFAR, int NW>
+// NW waves work on one pair together; DLP: entries of the double layer.
+template <typename T, bool ALLFAR, int NW, bool DLP>
 __global__ void __launch_bounds__(NW * 64) aca_kernel(Tab tab, const PairDesc* __restrict__ pairs,
                                                       const int* __restrict__ order, int npairs,
                                                       unsigned char* __restrict__ ws, double tol,
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(NW * 64) aca_kernel(Tab tab, const PairDesc* _
     cpx<T>* U = reinterpret_cast<cpx<T>*>(ws + d.ws);
     cpx<T>* W = U + int64_t(d.cap) * d.m;
     cpx<double>* GU = reinterpret_cast<cpx<double>*>(ws + d.ws + ws_gram_off<T>(d.cap, d.m, d.n));
-    PlainEntry<T, ALLFAR> ent{&tab, d.rb, d.cb, d.sr, d.si, d.all_far != 0};
+    PlainEntry<T, ALLFAR, DLP> ent{&tab, d.rb, d.cb, d.sr, d.si, d.all_far != 0};
     int status = 0;
     const int k = aca_grp<NW, (NW > 1), T>(ent, d.m, d.n, d.cap, max_rank, tol, 0.0, U, W, GU,
                                            GU + d.cap * d.cap, sm, status);
@@ -69,13 +69,20 @@ __global__ void __launch_bounds__(NW * 64) aca_kernel(Tab tab, const PairDesc* _
   }
 }
 
-template <typename T, bool AF, typename... Args>
-static void launch_aca(int nw, int grid, hipStream_t st, Args... args) {
+template <typename T, bool AF, bool DLP, typename... Args>
+static void launch_aca_op(int nw, int grid, hipStream_t st, Args... args) {
   switch (nw) {
-    case 1: hipLaunchKernelGGL((aca_kernel<T, AF, 1>), dim3(grid), dim3(64), 0, st, args...); break;
-    case 2: hipLaunchKernelGGL((aca_kernel<T, AF, 2>), dim3(grid), dim3(128), 0, st, args...); break;
-    default: hipLaunchKernelGGL((aca_kernel<T, AF, 4>), dim3(grid), dim3(256), 0, st, args...); break;
+    case 1: hipLaunchKernelGGL((aca_kernel<T, AF, 1, DLP>), dim3(grid), dim3(64), 0, st, args...); break;
+    case 2: hipLaunchKernelGGL((aca_kernel<T, AF, 2, DLP>), dim3(grid), dim3(128), 0, st, args...); break;
+    default: hipLaunchKernelGGL((aca_kernel<T, AF, 4, DLP>), dim3(grid), dim3(256), 0, st, args...); break;
   }
+}
+template <typename T, bool AF, typename... Args>
+static void launch_aca(bool dlp, int nw, int grid, hipStream_t st, Args... args) {
+  if (dlp)
+    launch_aca_op<T, AF, true>(nw, grid, st, args...);
+  else
+    launch_aca_op<T, AF, false>(nw, grid, st, args...);
 }
 
 template <typename T>
@@ -180,11 +187,11 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
     const int nw = ctx->tune.aca_waves;
     const int grid = std::min(nc, dev_cus * 32 / nw);
     GCQ_TRY(timed_begin(ctx));
-    launch_aca<T, true>(nw, grid, st, ctx->tab(), (const PairDesc*)ctx->scratchB.as<PairDesc>(),
+    launch_aca<T, true>(ctx->H.dlp, nw, grid, st, ctx->tab(), (const PairDesc*)ctx->scratchB.as<PairDesc>(),
                         (const int*)nullptr, nc, ctx->scratchA.as<unsigned char>(), tol, max_rank,
                         d_rank, d_status, d_counter);
     if (nnf > 0)
-      launch_aca<T, false>(nw, std::min(grid, nnf), st, ctx->tab(),
+      launch_aca<T, false>(ctx->H.dlp, nw, std::min(grid, nnf), st, ctx->tab(),
                            (const PairDesc*)ctx->scratchB.as<PairDesc>(), (const int*)nullptr, nc,
                            ctx->scratchA.as<unsigned char>(), tol, max_rank, d_rank, d_status,
                            d_counter + 1);
@@ -266,6 +273,17 @@ static std::vector<int> order_desc_stable(const std::vector<uint64_t>& key) {
   return order;
 }
 
+// dense near-field blocks of every slot: far-tier entries, then self/near-tier ones
+template <typename T, bool DLP>
+static void launch_near(gcq_context* ctx, dim3 g1, dim3 g2, int nnear, const double2* sig, int nslot,
+                        cpx<T>* out, int64_t stride) {
+  hipLaunchKernelGGL((near_far_tier<T, DLP>), g1, dim3(256), 0, ctx->stream, ctx->tab(), ctx->d_blk.as<int>(),
+                     ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(), 0, nnear, int64_t(0), sig, nslot,
+                     out, stride);
+  hipLaunchKernelGGL((near_sing<T, DLP>), g2, dim3(256), 0, ctx->stream, ctx->tab(), ctx->d_sing.as<SingEntry>(),
+                     int64_t(0), ctx->n_sing, int64_t(0), sig, nslot, out, stride);
+}
+
 int rank_predict_device(gcq_context* ctx, const float* d_x, int m, float* d_out);
 void rank_features_host(gcq_context* ctx, const std::vector<int>& freqs, std::vector<float>& feat);
 }  // namespace gcq
@@ -288,6 +306,9 @@ GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_
   GCQ_HIP(hipSetDevice(ctx->device));
   HFaces& H = ctx->H;
   H.valid = false;
+  H.dlp = (flags & GCQ_FLAG_DOUBLE_LAYER) != 0;
+  if (H.dlp && (flags & GCQ_FLAG_USE_PREDICTOR))
+    return fail(GCQ_ERR_ARG, "the rank model is trained on the single layer; no predictor with the double layer");
   // representatives to approximate
   std::vector<int> fr;
   if (freq_idx && n_fidx > 0) {
@@ -339,21 +360,15 @@ GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_
   if (nnear > 0) {
     const dim3 g1(std::min(nnear, 65536)), g2(4096);
     if (precision == GCQ_C128) {
-      hipLaunchKernelGGL(near_far_tier<double>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
-                         ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(),
-                         0, nnear, int64_t(0), H.d_sig.as<double2>(), nslot,
-                         H.near.as<cpx<double>>(), acc_near);
-      hipLaunchKernelGGL(near_sing<double>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
-                         ctx->d_sing.as<SingEntry>(), int64_t(0), ctx->n_sing, int64_t(0),
-                         H.d_sig.as<double2>(), nslot, H.near.as<cpx<double>>(), acc_near);
+      if (H.dlp)
+        launch_near<double, true>(ctx, g1, g2, nnear, H.d_sig.as<double2>(), nslot, H.near.as<cpx<double>>(), acc_near);
+      else
+        launch_near<double, false>(ctx, g1, g2, nnear, H.d_sig.as<double2>(), nslot, H.near.as<cpx<double>>(), acc_near);
     } else {
-      hipLaunchKernelGGL(near_far_tier<float>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
-                         ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(),
-                         0, nnear, int64_t(0), H.d_sig.as<double2>(), nslot,
-                         H.near.as<cpx<float>>(), acc_near);
-      hipLaunchKernelGGL(near_sing<float>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
-                         ctx->d_sing.as<SingEntry>(), int64_t(0), ctx->n_sing, int64_t(0),
-                         H.d_sig.as<double2>(), nslot, H.near.as<cpx<float>>(), acc_near);
+      if (H.dlp)
+        launch_near<float, true>(ctx, g1, g2, nnear, H.d_sig.as<double2>(), nslot, H.near.as<cpx<float>>(), acc_near);
+      else
+        launch_near<float, false>(ctx, g1, g2, nnear, H.d_sig.as<double2>(), nslot, H.near.as<cpx<float>>(), acc_near);
     }
   }
   GCQ_HIP(hipGetLastError());

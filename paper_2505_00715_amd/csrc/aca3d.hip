@@ -907,7 +907,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   // the dense near-field entries at every frequency of K, as the per-frequency
   // H-matrix of the same frequencies and precision holds them ([k][near
   // storage]), are reused instead of evaluated again
-  const bool reuse_near = ctx->H.valid && ctx->H.precision == precision && ctx->H.freqs == ctx->K &&
+  const bool reuse_near = ctx->H.valid && !ctx->H.dlp && ctx->H.precision == precision && ctx->H.freqs == ctx->K &&
                           ctx->H.near_slot_elems == ctx->near_total && ctx->H.near.p != nullptr;
   std::vector<int> opos(nb);
   for (int i = 0; i < nb; ++i) opos[order[i]] = i;

@@ -464,6 +464,117 @@ __device__ __forceinline__ cpx<T> entry_part(const Tab& t, int pi, int pj, doubl
   return far_entry_part<T>(t, c[pi], c[n + pi], c[2 * n + pi], pj, T(sr), T(si), p, P);
 }
 
+// ---- double layer: the normal derivative in y of exp(-sigma r) / (4 pi r) -------
+// d/dn_y = (d . n_y) (1 + sigma r) exp(-sigma r) / (4 pi r^3), d = x - y; the
+// 1/(4 pi) sits in the quadrature weights as for the single layer
+
+// (1 + sigma r) exp(-sigma r) for sigma = sr + i si
+__device__ __forceinline__ cpx<float> dlp_radial(float r, float sr, float si) {
+  const float e = expf(-sr * r);
+  float sn, cs;
+  sincosf(si * r, &sn, &cs);
+  const float a = 1.f + sr * r, b = si * r;
+  return {e * (a * cs + b * sn), e * (b * cs - a * sn)};
+}
+__device__ __forceinline__ cpx<double> dlp_radial(double r, double sr, double si) {
+  const double e = exp(-sr * r);
+  double sn, cs;
+  sincos(si * r, &sn, &cs);
+  const double a = 1.0 + sr * r, b = si * r;
+  return {e * (a * cs + b * sn), e * (b * cs - a * sn)};
+}
+
+// unit normal of panel p from its vertices, (v1 - v0) x (v2 - v0) / |.|
+__device__ __forceinline__ void panel_normal(const Tab& t, int p, double nrm[3]) {
+  const int n = t.n;
+  double v[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) v[c] = t.vert[c * n + p];
+  const double ax = v[3] - v[0], ay = v[4] - v[1], az = v[5] - v[2];
+  const double bx = v[6] - v[0], by = v[7] - v[1], bz = v[8] - v[2];
+  const double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+  const double inv = 1.0 / sqrt(cx * cx + cy * cy + cz * cz);
+  nrm[0] = cx * inv;
+  nrm[1] = cy * inv;
+  nrm[2] = cz * inv;
+}
+
+// near tier of the double layer: 112-point rule, double
+__device__ __forceinline__ cpx<double> dlp_near_entry(const Tab& t, int pi, int pj, double sr, double si) {
+  const int n = t.n;
+  double nrm[3];
+  panel_normal(t, pj, nrm);
+  const double xi = t.cen[pi], yi = t.cen[n + pi], zi = t.cen[2 * n + pi];
+  double v[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) v[c] = t.vert[c * n + pj];
+  const double wa = t.area[pj] * INV4PI;
+  double ar = 0.0, ai = 0.0;
+  for (int a = 0; a < NQ_NEAR; ++a) {
+    const double b0 = t.K->nb[a][0], b1 = t.K->nb[a][1], b2 = t.K->nb[a][2];
+    const double dx = xi - (b0 * v[0] + b1 * v[3] + b2 * v[6]);
+    const double dy = yi - (b0 * v[1] + b1 * v[4] + b2 * v[7]);
+    const double dz = zi - (b0 * v[2] + b1 * v[5] + b2 * v[8]);
+    const double r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2);
+    const double f = t.K->nw[a] * wa * (dx * nrm[0] + dy * nrm[1] + dz * nrm[2]) / (r2 * r);
+    const cpx<double> g = dlp_radial(r, sr, si);
+    ar += f * g.re;
+    ai += f * g.im;
+  }
+  return {ar, ai};
+}
+
+// far tier of the double layer, quadrature points a = p, p + P, ... in T
+template <typename T>
+__device__ __forceinline__ cpx<T> dlp_far_entry_part(const Tab& t, int pi, int pj, T sr, T si, int p, int P) {
+  const int n = t.n;
+  double nrm[3];
+  panel_normal(t, pj, nrm);
+  const T* q = FarData<T>::q(t);
+  const T* c = FarData<T>::c(t);
+  const T xi = c[pi], yi = c[n + pi], zi = c[2 * n + pi];
+  const T nx = T(nrm[0]), ny = T(nrm[1]), nz = T(nrm[2]);
+  T ar = T(0), ai = T(0);
+  for (int a = p; a < NQ_FAR; a += P) {
+    const T dx = xi - q[a * n + pj];
+    const T dy = yi - q[(7 + a) * n + pj];
+    const T dz = zi - q[(14 + a) * n + pj];
+    const T w = q[(21 + a) * n + pj];
+    const T r2 = dx * dx + dy * dy + dz * dz, r = sqrt(r2);
+    const T f = w * (dx * nx + dy * ny + dz * nz) / (r2 * r);
+    const cpx<T> g = dlp_radial(r, sr, si);
+    ar += f * g.re;
+    ai += f * g.im;
+  }
+  return {ar, ai};
+}
+
+// part p of P of a double-layer entry (as entry_part): self 0 (the centroid
+// lies in its flat panel's plane), near tier whole by part 0 in double
+template <typename T, bool ALLFAR = false>
+__device__ __forceinline__ cpx<T> dlp_entry_part(const Tab& t, int pi, int pj, double sr, double si,
+                                                 bool all_far, int p, int P) {
+  if (!ALLFAR && !all_far) {
+    if (pi == pj) return {T(0), T(0)};
+    if (is_near(t, pi, pj)) {
+      if (p != 0) return {T(0), T(0)};
+      const cpx<double> e = dlp_near_entry(t, pi, pj, sr, si);
+      return {T(e.re), T(e.im)};
+    }
+  }
+  return dlp_far_entry_part<T>(t, pi, pj, T(sr), T(si), p, P);
+}
+
+// entry part of the single (DLP = false) or double layer
+template <typename T, bool ALLFAR, bool DLP>
+__device__ __forceinline__ cpx<T> op_entry_part(const Tab& t, int pi, int pj, double sr, double si,
+                                                bool all_far, int p, int P) {
+  if constexpr (DLP)
+    return dlp_entry_part<T, ALLFAR>(t, pi, pj, sr, si, all_far, p, P);
+  else
+    return entry_part<T, ALLFAR>(t, pi, pj, sr, si, all_far, p, P);
+}
+
 // threadIdx.x hidden from loop-invariant code motion: address arithmetic
 // derived from it stays next to its use instead of holding a register across
 // an enclosing persistent loop (the empty asm emits no instruction)

@@ -87,6 +87,7 @@ struct Block {
 // ---- per-frequency H-matrices (aca_blocks) ---------------------------------------------
 struct HFaces {
   bool valid = false;
+  bool dlp = false;              // faces of the double layer (GCQ_FLAG_DOUBLE_LAYER)
   int precision = GCQ_C128;
   std::vector<int> freqs;        // representative frequencies held (positions in K order)
   std::vector<int> fslot;        // L -> slot in freqs or -1

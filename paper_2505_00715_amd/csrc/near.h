@@ -8,6 +8,7 @@
 //     self and near-tier entries are skipped;
 //   near_sing: one thread per (self/near-tier entry, frequency), float64
 //     (polar-coordinate self rule or 112-point rule).
+// DLP: the double layer's entries (normal derivative in y; self entries 0).
 // The list of self/near-tier entries is built once with the block tree.
 #pragma once
 #include "device_common.h"
@@ -19,7 +20,7 @@ struct SingEntry {
   int pi, pj;    // internal positions
 };
 
-template <typename T>
+template <typename T, bool DLP = false>
 __global__ void __launch_bounds__(256) near_far_tier(Tab tab, const int* __restrict__ blk,
                                                      const int* __restrict__ near_ids,
                                                      const int64_t* __restrict__ near_off,
@@ -40,19 +41,29 @@ __global__ void __launch_bounds__(256) near_far_tier(Tab tab, const int* __restr
       const int nn = tab.n;
       const T xi = cen[pi], yi = cen[nn + pi], zi = cen[2 * nn + pi];
       T rr[NQ_FAR], ww[NQ_FAR];
+      T nrm[3] = {T(0), T(0), T(0)};
+      if constexpr (DLP) {
+        double nd[3];
+        panel_normal(tab, pj, nd);
+        nrm[0] = T(nd[0]);
+        nrm[1] = T(nd[1]);
+        nrm[2] = T(nd[2]);
+      }
 #pragma unroll
       for (int a = 0; a < NQ_FAR; ++a) {
         const T dx = xi - qp[a * nn + pj], dy = yi - qp[(7 + a) * nn + pj];
         const T dz = zi - qp[(14 + a) * nn + pj];
-        rr[a] = sqrt(dx * dx + dy * dy + dz * dz);
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        rr[a] = sqrt(r2);
         ww[a] = qp[(21 + a) * nn + pj];
+        if constexpr (DLP) ww[a] *= (dx * nrm[0] + dy * nrm[1] + dz * nrm[2]) / (r2 * rr[a]);
       }
       for (int f = 0; f < F; ++f) {
         const double2 s = sig[f];
         cpx<T> acc = {T(0), T(0)};
 #pragma unroll
         for (int a = 0; a < NQ_FAR; ++a) {
-          const cpx<T> gg = green(rr[a], T(s.x), T(s.y));
+          const cpx<T> gg = DLP ? dlp_radial(rr[a], T(s.x), T(s.y)) : green(rr[a], T(s.x), T(s.y));
           acc.re += ww[a] * gg.re;
           acc.im += ww[a] * gg.im;
         }
@@ -62,7 +73,7 @@ __global__ void __launch_bounds__(256) near_far_tier(Tab tab, const int* __restr
   }
 }
 
-template <typename T>
+template <typename T, bool DLP = false>
 __global__ void __launch_bounds__(256) near_sing(Tab tab, const SingEntry* __restrict__ list,
                                                  int64_t s0, int64_t s1, int64_t base0,
                                                  const double2* __restrict__ sig, int F,
@@ -74,8 +85,11 @@ __global__ void __launch_bounds__(256) near_sing(Tab tab, const SingEntry* __res
     const int f = int(x % F);
     const SingEntry se = list[a];
     const double2 s = sig[f];
-    const cpx<double> v = se.pi == se.pj ? self_entry(tab, se.pi, s.x, s.y)
-                                         : near_entry(tab, se.pi, se.pj, s.x, s.y);
+    cpx<double> v;
+    if constexpr (DLP)
+      v = se.pi == se.pj ? cpx<double>{0.0, 0.0} : dlp_near_entry(tab, se.pi, se.pj, s.x, s.y);
+    else
+      v = se.pi == se.pj ? self_entry(tab, se.pi, s.x, s.y) : near_entry(tab, se.pi, se.pj, s.x, s.y);
     out[int64_t(f) * stride + se.off - base0] = {T(v.re), T(v.im)};
   }
 }

@@ -102,3 +102,57 @@ def test_housing_sampled_dlp_entries_full_size():
     A32 = _assemble(ctx, rows, cols, fidx, g.C64)
     err = np.linalg.norm((A32 - ref).reshape(len(fidx), -1), axis=1) / np.linalg.norm(ref.reshape(len(fidx), -1), axis=1)
     assert err.max() < 1e-5, err
+
+
+@pytest.fixture(scope="module")
+def sphere1280():
+    from synth import mesh
+    xyz, tri = mesh.icosphere(3)
+    P = Panels(xyz, tri)
+    s = np.array([1.0, 2.0 + 1.0j, 5.0 - 3.0j])
+    return xyz, tri, P, s, dlp.dense(P, s, 1.0)
+
+
+@pytest.mark.parametrize("prec,tol,bound", [(g.C128, 1e-8, 1e-6), (g.C64, 1e-5, 1e-4)])
+def test_dlp_h_matrix_product(sphere1280, prec, tol, bound):
+    """Per-frequency ACA faces of the double layer (gcq_aca_blocks with
+    GCQ_FLAG_DOUBLE_LAYER) applied by the H-matrix product against the
+    oracle's dense double layer, on 1280 triangles at three frequencies."""
+    xyz, tri, P, s, K = sphere1280
+    ctx = g.Context(0)
+    ctx.upload_mesh(xyz, tri, 1.0)
+    ctx.set_frequencies(s, False)
+    ctx.build_cluster_tree(32, 1.0)
+    st = ctx.aca_blocks(tol, 64, prec, g.FLAG_RECOMPRESS | g.FLAG_DOUBLE_LAYER)
+    assert st.n_pairs > 0 and st.n_capped == 0
+    X = np.random.default_rng(8).standard_normal((len(s), P.n)) + 1j * np.random.default_rng(9).standard_normal((len(s), P.n))
+    dt = torch.complex128 if prec == g.C128 else torch.complex64
+    Y = torch.zeros(len(s) * P.n, dtype=dt, device="cuda")
+    ctx.compressed_matvec(g.PLAIN_H, prec, torch.from_numpy(X.reshape(-1)).to(dt).cuda(), Y)
+    torch.cuda.synchronize()
+    Yg = Y.cpu().numpy().astype(np.complex128).reshape(len(s), P.n)
+    ref = np.stack([K[k] @ X[k] for k in range(len(s))])
+    err = np.linalg.norm(Yg - ref) / np.linalg.norm(ref)
+    assert err <= bound, err
+    with pytest.raises(g.GcqError):   # the rank model is the single layer's
+        ctx.aca_blocks(tol, 64, prec, g.FLAG_DOUBLE_LAYER | g.FLAG_USE_PREDICTOR)
+
+
+def test_single_layer_3d_aca_after_double_layer_faces(sphere1280):
+    """A 3D-ACA after double-layer faces rebuilds its near field with the single
+    layer (the faces' near blocks are not reused)."""
+    xyz, tri, P, s, _ = sphere1280
+    ctx = g.Context(0)
+    ctx.upload_mesh(xyz, tri, 1.0)
+    ctx.set_frequencies(s, False)
+    ctx.build_cluster_tree(32, 1.0)
+    ctx.aca_blocks(1e-8, 64, g.C128, g.FLAG_RECOMPRESS | g.FLAG_DOUBLE_LAYER)
+    ctx.aca3d(1e-8, 1e-8, 64, g.C128)
+    X = np.random.default_rng(10).standard_normal((len(s), P.n)).astype(np.complex128)
+    Y = torch.zeros(len(s) * P.n, dtype=torch.complex128, device="cuda")
+    ctx.compressed_matvec(g.PER_FREQUENCY, g.C128, torch.from_numpy(X.reshape(-1)).cuda(), Y)
+    torch.cuda.synchronize()
+    V = entries.dense(P, s, 1.0)
+    ref = np.stack([V[k] @ X[k] for k in range(len(s))])
+    Yg = Y.cpu().numpy().reshape(len(s), P.n)
+    assert np.linalg.norm(Yg - ref) / np.linalg.norm(ref) <= 1e-6
