@@ -342,7 +342,10 @@ GCQ_API int gcq_get_block_factors(gcq_context* ctx, int32_t block, int32_t freq,
 /* ---- 3D-ACA (Sec. 4, Alg. 1, eq. norm) ------------------------------------
  * gcq_aca3d: per block of the partition, the 3D-ACA over the frequencies of K
  *   with slice tolerance tol_aca (ACA + recompression of far slices) and
- *   frequency tolerance tol, at most max_freq_rank terms per block. */
+ *   frequency tolerance tol, at most max_freq_rank terms per block.  flags:
+ *   GCQ_FLAG_DOUBLE_LAYER compresses the double layer K(s) (entries of
+ *   gcq_assemble_dlp_slices) instead of V(s); the products and the gCQ
+ *   stepping then apply K.  Other flag bits are ignored. */
 GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol, int32_t max_freq_rank,
                       int32_t precision, uint32_t flags, gcq_aca3d_stats* stats);
 

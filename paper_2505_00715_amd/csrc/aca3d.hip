@@ -103,7 +103,7 @@ __device__ inline int64_t pool_alloc(unsigned long long* cursor, int64_t cnt, in
 // A row (column) evaluation first forms the coefficients f_d[k] Ubar[i][x]
 // (f_d[k] conj(Vbar[j][x])) in LDS; each entry then subtracts
 // sum_x coef[x] conj(Vbar[j][x]) (sum_x Ubar[i][x] coef[x]).
-template <typename T, bool ALLFAR, int NW>
+template <typename T, bool ALLFAR, int NW, bool DLP>
 struct ResidualEntry {
   const Tab* tab;
   int rb, cb, m, n;
@@ -131,7 +131,7 @@ struct ResidualEntry {
   // part p of P of the residual entry (i, j): quadrature points and stacked
   // columns x = p, p + P, ...
   __device__ cpx<T> part(int i, int j, int p, int P) const {
-    cpx<T> a = entry_part<T, ALLFAR>(*tab, rb + i, cb + j, sr, si, all_far, p, P);
+    cpx<T> a = op_entry_part<T, ALLFAR, DLP>(*tab, rb + i, cb + j, sr, si, all_far, p, P);
     T ar = 0, ai = 0;
     const cpx<T>* q = sh->coef;
     if (rowmode) {
@@ -356,7 +356,7 @@ __device__ inline void stack_inner(const cpx<T>* __restrict__ Us, const cpx<T>* 
 // 3D-ACA of admissible blocks, NW waves per block.  ALLFAR = true: blocks
 // without self/near-tier entries (the float64 quadrature tiers are not
 // compiled in); ALLFAR = false: admissible blocks that contain some.
-template <typename T, bool ALLFAR, int NW>
+template <typename T, bool ALLFAR, int NW, bool DLP>
 __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
     Tab tab, const BlockDesc3* __restrict__ blocks, const int* __restrict__ order, int nblocks,
     const double2* __restrict__ sigK, int nK, double tol_aca, double tol, int rmax, int aca_cap,
@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       }
       const double nu = unid(sqrt(fmax(grp_sum<NW>(nu2), 0.0)));
       // ---- residual slice at k_cur: ACA, then recompression
-      ResidualEntry<T, ALLFAR, NW> ent{&tab, B.rb, B.cb, m, n, sg.x, sg.y, B.all_far != 0, nres, &sh,
+      ResidualEntry<T, ALLFAR, NW, DLP> ent{&tab, B.rb, B.cb, m, n, sg.x, sg.y, B.all_far != 0, nres, &sh,
                                        Us, Vs, true};
       int ast = 0;
       const int k = uni(aca_grp<NW, true, T>(ent, m, n, cap, aca_cap, tol_aca, nu, U, W, GU, GV, sh.aca, ast));
@@ -502,7 +502,11 @@ __global__ void __launch_bounds__(NW * 64) aca3d_kernel(
       double nf2 = 0.0;
       for (int kk = tid; kk < nK; kk += NT) {
         const double2 s2 = sigK[kk];
-        cpx<T> a = entry<T, ALLFAR>(tab, B.rb + ip, B.cb + jp, s2.x, s2.y, B.all_far != 0);
+        cpx<T> a;
+        if constexpr (DLP)
+          a = dlp_entry_part<T, ALLFAR>(tab, B.rb + ip, B.cb + jp, s2.x, s2.y, B.all_far != 0, 0, 1);
+        else
+          a = entry<T, ALLFAR>(tab, B.rb + ip, B.cb + jp, s2.x, s2.y, B.all_far != 0);
         for (int d = 0; d < ell; ++d) {
           cpx<T> p = cmul(sh.hp[d], pool[sh.term[d].fiber + kk]);
           a.re -= p.re;
@@ -765,15 +769,33 @@ static __global__ void build_cols(const int* __restrict__ blk, const int* __rest
   }
 }
 
-// launch of the far kernel with NW waves per block
-template <typename T, bool AF, typename... Args>
-static void launch_far(int nw, int grid, hipStream_t st, Args... args) {
+// launch of the far kernel with NW waves per block, single or double layer
+template <typename T, bool AF, bool DLP, typename... Args>
+static void launch_far_op(int nw, int grid, hipStream_t st, Args... args) {
   switch (nw) {
-    case 1: hipLaunchKernelGGL((aca3d_kernel<T, AF, 1>), dim3(grid), dim3(64), 0, st, args...); break;
-    case 2: hipLaunchKernelGGL((aca3d_kernel<T, AF, 2>), dim3(grid), dim3(128), 0, st, args...); break;
-    case 4: hipLaunchKernelGGL((aca3d_kernel<T, AF, 4>), dim3(grid), dim3(256), 0, st, args...); break;
-    default: hipLaunchKernelGGL((aca3d_kernel<T, AF, 8>), dim3(grid), dim3(512), 0, st, args...); break;
+    case 1: hipLaunchKernelGGL((aca3d_kernel<T, AF, 1, DLP>), dim3(grid), dim3(64), 0, st, args...); break;
+    case 2: hipLaunchKernelGGL((aca3d_kernel<T, AF, 2, DLP>), dim3(grid), dim3(128), 0, st, args...); break;
+    case 4: hipLaunchKernelGGL((aca3d_kernel<T, AF, 4, DLP>), dim3(grid), dim3(256), 0, st, args...); break;
+    default: hipLaunchKernelGGL((aca3d_kernel<T, AF, 8, DLP>), dim3(grid), dim3(512), 0, st, args...); break;
   }
+}
+template <typename T, bool AF, typename... Args>
+static void launch_far(bool dlp, int nw, int grid, hipStream_t st, Args... args) {
+  if (dlp)
+    launch_far_op<T, AF, true>(nw, grid, st, args...);
+  else
+    launch_far_op<T, AF, false>(nw, grid, st, args...);
+}
+
+// dense near-field tensor of the blocks [q0, q1): far-tier entries, then self/near-tier ones
+template <typename T, bool DLP>
+static void launch_near3(gcq_context* ctx, dim3 g1, dim3 g2, int q0, int q1, int64_t base0, int64_t s0,
+                         int64_t s1, int nK, cpx<T>* out, int64_t span) {
+  hipLaunchKernelGGL((near_far_tier<T, DLP>), g1, dim3(256), 0, ctx->stream, ctx->tab(), ctx->d_blk.as<int>(),
+                     ctx->d_near_ids.as<int>(), ctx->d_near_off.as<int64_t>(), q0, q1, base0,
+                     ctx->scratchC.as<double2>(), nK, out, span);
+  hipLaunchKernelGGL((near_sing<T, DLP>), g2, dim3(256), 0, ctx->stream, ctx->tab(), ctx->d_sing.as<SingEntry>(),
+                     s0, s1, base0, ctx->scratchC.as<double2>(), nK, out, span);
 }
 
 // side streams and fork/join events of the context, created on first use
@@ -793,7 +815,7 @@ using namespace gcq;
 extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
                                  int32_t max_freq_rank, int32_t precision, uint32_t flags,
                                  gcq_aca3d_stats* stats) {
-  (void)flags;
+  const bool dlp = (flags & GCQ_FLAG_DOUBLE_LAYER) != 0;
   if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
   GCQ_NEED_DEVICE(ctx);
   if (!ctx->have_tree || !ctx->have_freq)
@@ -810,6 +832,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   F.valid = false;
   F.graphs.clear();   // they refer to the tables rebuilt below
   F.precision = precision;
+  F.dlp = dlp;
   F.nK = nK;
   const int nb = int(ctx->blocks.size());
   std::vector<BlockDesc3> bd(nb);
@@ -907,7 +930,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   // the dense near-field entries at every frequency of K, as the per-frequency
   // H-matrix of the same frequencies and precision holds them ([k][near
   // storage]), are reused instead of evaluated again
-  const bool reuse_near = ctx->H.valid && !ctx->H.dlp && ctx->H.precision == precision && ctx->H.freqs == ctx->K &&
+  const bool reuse_near = ctx->H.valid && ctx->H.dlp == dlp && ctx->H.precision == precision && ctx->H.freqs == ctx->K &&
                           ctx->H.near_slot_elems == ctx->near_total && ctx->H.near.p != nullptr;
   std::vector<int> opos(nb);
   for (int i = 0; i < nb; ++i) opos[order[i]] = i;
@@ -963,7 +986,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
       if (precision == GCQ_C128) {
         auto go = [&](auto tag) {
           launch_far<double, decltype(tag)::value>(
-              nw, lgrid[l], st, ctx->tab(), (const BlockDesc3*)ctx->scratchB.as<BlockDesc3>(),
+              dlp, nw, lgrid[l], st, ctx->tab(), (const BlockDesc3*)ctx->scratchB.as<BlockDesc3>(),
               (const int*)(d_order + loff[l]), cnt, (const double2*)ctx->scratchC.as<double2>(), nK,
               tol_aca, tol, int(max_freq_rank), aca_cap, wsp, lstride[l], F.slices.as<cpx<double>>(),
               d_cursor, capacity, d_terms, d_rank, d_stat, d_counter + l, d_work);
@@ -972,7 +995,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
       } else {
         auto go = [&](auto tag) {
           launch_far<float, decltype(tag)::value>(
-              nw, lgrid[l], st, ctx->tab(), (const BlockDesc3*)ctx->scratchB.as<BlockDesc3>(),
+              dlp, nw, lgrid[l], st, ctx->tab(), (const BlockDesc3*)ctx->scratchB.as<BlockDesc3>(),
               (const int*)(d_order + loff[l]), cnt, (const double2*)ctx->scratchC.as<double2>(), nK,
               tol_aca, tol, int(max_freq_rank), aca_cap, wsp, lstride[l], F.slices.as<cpx<float>>(),
               d_cursor, capacity, d_terms, d_rank, d_stat, d_counter + l, d_work);
@@ -1012,21 +1035,15 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
         GCQ_TRY(timed_begin(ctx));
         const dim3 g1(std::min(q1 - q0, 65536)), g2(4096);
         if (precision == GCQ_C128) {
-          hipLaunchKernelGGL(near_far_tier<double>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
-                             ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(),
-                             ctx->d_near_off.as<int64_t>(), q0, q1, base0,
-                             ctx->scratchC.as<double2>(), nK, tensor.as<cpx<double>>(), span);
-          hipLaunchKernelGGL(near_sing<double>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
-                             ctx->d_sing.as<SingEntry>(), s0, s1, base0, ctx->scratchC.as<double2>(),
-                             nK, tensor.as<cpx<double>>(), span);
+          if (dlp)
+            launch_near3<double, true>(ctx, g1, g2, q0, q1, base0, s0, s1, nK, tensor.as<cpx<double>>(), span);
+          else
+            launch_near3<double, false>(ctx, g1, g2, q0, q1, base0, s0, s1, nK, tensor.as<cpx<double>>(), span);
         } else {
-          hipLaunchKernelGGL(near_far_tier<float>, g1, dim3(256), 0, ctx->stream, ctx->tab(),
-                             ctx->d_blk.as<int>(), ctx->d_near_ids.as<int>(),
-                             ctx->d_near_off.as<int64_t>(), q0, q1, base0,
-                             ctx->scratchC.as<double2>(), nK, tensor.as<cpx<float>>(), span);
-          hipLaunchKernelGGL(near_sing<float>, g2, dim3(256), 0, ctx->stream, ctx->tab(),
-                             ctx->d_sing.as<SingEntry>(), s0, s1, base0, ctx->scratchC.as<double2>(),
-                             nK, tensor.as<cpx<float>>(), span);
+          if (dlp)
+            launch_near3<float, true>(ctx, g1, g2, q0, q1, base0, s0, s1, nK, tensor.as<cpx<float>>(), span);
+          else
+            launch_near3<float, false>(ctx, g1, g2, q0, q1, base0, s0, s1, nK, tensor.as<cpx<float>>(), span);
         }
         GCQ_HIP(hipGetLastError());
         ms_tensor += timed_end(ctx, "aca3d_tensor_batch");

@@ -128,6 +128,7 @@ struct ProductGraphs {
 };
 
 struct Faces3D {
+  bool dlp = false;              // built for the double layer (GCQ_FLAG_DOUBLE_LAYER)
   bool valid = false;
   int precision = GCQ_C128;
   int nK = 0;

@@ -156,3 +156,36 @@ def test_single_layer_3d_aca_after_double_layer_faces(sphere1280):
     ref = np.stack([V[k] @ X[k] for k in range(len(s))])
     Yg = Y.cpu().numpy().reshape(len(s), P.n)
     assert np.linalg.norm(Yg - ref) / np.linalg.norm(ref) <= 1e-6
+
+
+@pytest.mark.parametrize("prec,tol,bound", [(g.C128, 1e-8, 1e-6), (g.C64, 1e-5, 1e-4)])
+def test_dlp_3d_aca_product(sphere1280, prec, tol, bound):
+    """3D-ACA of the double layer (gcq_aca3d with GCQ_FLAG_DOUBLE_LAYER) and the
+    per-frequency product against the oracle's dense double layer; after it, a
+    single-layer 3D-ACA on the same context is the single layer again."""
+    xyz, tri, P, s, K = sphere1280
+    ctx = g.Context(0)
+    ctx.upload_mesh(xyz, tri, 1.0)
+    ctx.set_frequencies(s, False)
+    ctx.build_cluster_tree(32, 1.0)
+    st = ctx.aca3d(tol, tol, 64, prec, g.FLAG_DOUBLE_LAYER)
+    assert st.n_blocks > 0 and st.n_capped == 0
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((len(s), P.n)) + 1j * rng.standard_normal((len(s), P.n))
+    dt = torch.complex128 if prec == g.C128 else torch.complex64
+    Xd = torch.from_numpy(X.reshape(-1)).to(dt).cuda()
+    Y = torch.zeros(len(s) * P.n, dtype=dt, device="cuda")
+    ctx.compressed_matvec(g.PER_FREQUENCY, prec, Xd, Y)
+    torch.cuda.synchronize()
+    Yg = Y.cpu().numpy().astype(np.complex128).reshape(len(s), P.n)
+    ref = np.stack([K[k] @ X[k] for k in range(len(s))])
+    err = np.linalg.norm(Yg - ref) / np.linalg.norm(ref)
+    assert err <= bound, err
+    if prec == g.C128:
+        ctx.aca3d(tol, tol, 64, prec)
+        ctx.compressed_matvec(g.PER_FREQUENCY, prec, Xd, Y)
+        torch.cuda.synchronize()
+        V = entries.dense(P, s, 1.0)
+        refv = np.stack([V[k] @ X[k] for k in range(len(s))])
+        Yv = Y.cpu().numpy().reshape(len(s), P.n)
+        assert np.linalg.norm(Yv - refv) / np.linalg.norm(refv) <= bound
