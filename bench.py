@@ -289,7 +289,7 @@ def main():
                   "compression_rate": s3.compression_rate, "storage_GB": s3.storage_bytes / 1e9},
         "plain": plain,
         "tuning": tuning,
-        "roofline": {"bound": "alu", "kernel": "aca3d_kernel<float, true, 4>",
+        "roofline": {"bound": "alu", "kernel": "aca3d_kernel<float, true, 4, false>",
                      "achieved": far_tflops, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": far_tflops / FP32_VALU_PEAK_TFLOPS, "traffic": traffic,
                      "launch_ms": far_ms, "flops_per_launch": s3.far_flops,
