@@ -203,6 +203,8 @@ struct Tab {
   const float* c32;    // 3n
   const float* q32;    // 28n
   const float4* q4;    // 7n: (x, y, z, w) of point a of panel p at a n + p
+  const double* n64;   // 3n: unit normals nx[], ny[], nz[] ((v1 - v0) x (v2 - v0) / |.|)
+  const float* n32;    // 3n: the same in float
   const Consts* K;
 };
 
@@ -484,19 +486,23 @@ __device__ __forceinline__ cpx<double> dlp_radial(double r, double sr, double si
   return {e * (a * cs + b * sn), e * (b * cs - a * sn)};
 }
 
-// unit normal of panel p from its vertices, (v1 - v0) x (v2 - v0) / |.|
-__device__ __forceinline__ void panel_normal(const Tab& t, int p, double nrm[3]) {
-  const int n = t.n;
-  double v[9];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) v[c] = t.vert[c * n + p];
-  const double ax = v[3] - v[0], ay = v[4] - v[1], az = v[5] - v[2];
-  const double bx = v[6] - v[0], by = v[7] - v[1], bz = v[8] - v[2];
-  const double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
-  const double inv = 1.0 / sqrt(cx * cx + cy * cy + cz * cz);
-  nrm[0] = cx * inv;
-  nrm[1] = cy * inv;
-  nrm[2] = cz * inv;
+// unit normal of panel p (table built with the panel tables)
+template <typename T>
+struct NrmData;
+template <>
+struct NrmData<float> {
+  static __device__ __forceinline__ const float* n(const Tab& t) { return t.n32; }
+};
+template <>
+struct NrmData<double> {
+  static __device__ __forceinline__ const double* n(const Tab& t) { return t.n64; }
+};
+template <typename T>
+__device__ __forceinline__ void panel_normal(const Tab& t, int p, T nrm[3]) {
+  const T* nn = NrmData<T>::n(t);
+  nrm[0] = nn[p];
+  nrm[1] = nn[t.n + p];
+  nrm[2] = nn[2 * t.n + p];
 }
 
 // near tier of the double layer: 112-point rule, double
@@ -528,12 +534,12 @@ __device__ __forceinline__ cpx<double> dlp_near_entry(const Tab& t, int pi, int 
 template <typename T>
 __device__ __forceinline__ cpx<T> dlp_far_entry_part(const Tab& t, int pi, int pj, T sr, T si, int p, int P) {
   const int n = t.n;
-  double nrm[3];
+  T nrm[3];
   panel_normal(t, pj, nrm);
   const T* q = FarData<T>::q(t);
   const T* c = FarData<T>::c(t);
   const T xi = c[pi], yi = c[n + pi], zi = c[2 * n + pi];
-  const T nx = T(nrm[0]), ny = T(nrm[1]), nz = T(nrm[2]);
+  const T nx = nrm[0], ny = nrm[1], nz = nrm[2];
   T ar = T(0), ai = T(0);
   for (int a = p; a < NQ_FAR; a += P) {
     const T dx = xi - q[a * n + pj];
@@ -545,6 +551,38 @@ __device__ __forceinline__ cpx<T> dlp_far_entry_part(const Tab& t, int pi, int p
     const cpx<T> g = dlp_radial(r, sr, si);
     ar += f * g.re;
     ai += f * g.im;
+  }
+  return {ar, ai};
+}
+
+// float far tier of the double layer on the hardware transcendental units, as
+// far_entry<float>: exp(-sr r) as 2^(-sr log2(e) r), the phase reduced to
+// [-1/2, 1/2] revolutions, 1/r from the reciprocal square root
+template <>
+__device__ __forceinline__ cpx<float> dlp_far_entry_part<float>(const Tab& t, int pi, int pj, float sr, float si,
+                                                                int p, int P) {
+  const int n = t.n;
+  const float4* q = t.q4;
+  const float xi = t.c32[pi], yi = t.c32[n + pi], zi = t.c32[2 * n + pi];
+  const float nx = t.n32[pj], ny = t.n32[n + pj], nz = t.n32[2 * n + pj];
+  const float a2 = -sr * 1.44269504088896340736f;   // -sr log2(e)
+  const float rv = si * 0.159154943091895335769f;   // si / (2 pi)
+  float ar = 0.f, ai = 0.f;
+  for (int a = p; a < NQ_FAR; a += P) {
+    const float4 qa = q[a * n + pj];
+    const float dx = xi - qa.x;
+    const float dy = yi - qa.y;
+    const float dz = zi - qa.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * ri;
+    const float f = __builtin_amdgcn_exp2f(a2 * r) * qa.w * (dx * nx + dy * ny + dz * nz) * (ri * ri * ri);
+    float rev = rv * r;
+    rev -= rintf(rev);
+    const float cs = __builtin_amdgcn_cosf(rev), sn = __builtin_amdgcn_sinf(rev);
+    const float b = 1.f + sr * r, c = si * r;
+    ar += f * (b * cs + c * sn);
+    ai += f * (c * cs - b * sn);
   }
   return {ar, ai};
 }

@@ -483,7 +483,8 @@ GCQ_API int gcq_build_cluster_tree(gcq_context* ctx, int32_t leaf_size, double e
   // ---- device panel tables in permuted order
   std::vector<double> cen_p(3 * size_t(n)), h2_p(n), vert_p(9 * size_t(n)), area_p(n),
       q64(28 * size_t(n));
-  std::vector<float> c32(3 * size_t(n)), q32(28 * size_t(n)), q4(28 * size_t(n));
+  std::vector<float> c32(3 * size_t(n)), q32(28 * size_t(n)), q4(28 * size_t(n)), n32(3 * size_t(n));
+  std::vector<double> n64(3 * size_t(n));
   double rb[7][3], rw[7];
   radon7(rb, rw);
   for (int p = 0; p < n; ++p) {
@@ -496,6 +497,16 @@ GCQ_API int gcq_build_cluster_tree(gcq_context* ctx, int32_t leaf_size, double e
     h2_p[p] = ctx->h2[t];
     area_p[p] = ctx->area[t];
     const double* v = &vert[9 * t];
+    {   // unit normal (v1 - v0) x (v2 - v0) / |.|, outward for outward-oriented meshes
+      const double ax = v[3] - v[0], ay = v[4] - v[1], az = v[5] - v[2];
+      const double bx = v[6] - v[0], by = v[7] - v[1], bz = v[8] - v[2];
+      const double cr[3] = {ay * bz - az * by, az * bx - ax * bz, ax * by - ay * bx};
+      const double inv = 1.0 / std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      for (int k = 0; k < 3; ++k) {
+        n64[k * size_t(n) + p] = cr[k] * inv;
+        n32[k * size_t(n) + p] = float(cr[k] * inv);
+      }
+    }
     for (int a = 0; a < 7; ++a) {
       for (int k = 0; k < 3; ++k) {
         double x = rb[a][0] * v[k] + rb[a][1] * v[3 + k] + rb[a][2] * v[6 + k];
@@ -528,6 +539,8 @@ GCQ_API int gcq_build_cluster_tree(gcq_context* ctx, int32_t leaf_size, double e
   GCQ_TRY(upload(ctx->d_c32, c32, st));
   GCQ_TRY(upload(ctx->d_q32, q32, st));
   GCQ_TRY(upload(ctx->d_q4, q4, st));
+  GCQ_TRY(upload(ctx->d_n64, n64, st));
+  GCQ_TRY(upload(ctx->d_n32, n32, st));
   std::vector<int32_t> perm32(ctx->perm.begin(), ctx->perm.end());
   std::vector<int32_t> iperm32(ctx->iperm.begin(), ctx->iperm.end());
   GCQ_TRY(upload(ctx->d_perm, perm32, st));

@@ -212,7 +212,7 @@ struct gcq_context {
   gcq::DevBuf d_near_off, d_near_ids, d_sing;
 
   // device tables (permuted order)
-  gcq::DevBuf d_cen, d_h2, d_vert, d_area, d_q64, d_c32, d_q32, d_q4, d_consts, d_perm, d_iperm;
+  gcq::DevBuf d_cen, d_h2, d_vert, d_area, d_q64, d_c32, d_q32, d_q4, d_n64, d_n32, d_consts, d_perm, d_iperm;
   gcq::DevBuf d_blk;                         // per block: rb, re, cb, ce, flags (int32 x 5)
 
   gcq::HFaces H;
@@ -234,6 +234,8 @@ struct gcq_context {
     t.c32 = d_c32.as<float>();
     t.q32 = d_q32.as<float>();
     t.q4 = reinterpret_cast<const float4*>(d_q4.as<float>());
+    t.n64 = d_n64.as<double>();
+    t.n32 = d_n32.as<float>();
     t.K = d_consts.as<gcq::Consts>();
     return t;
   }

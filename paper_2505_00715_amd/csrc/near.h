@@ -42,13 +42,7 @@ __global__ void __launch_bounds__(256) near_far_tier(Tab tab, const int* __restr
       const T xi = cen[pi], yi = cen[nn + pi], zi = cen[2 * nn + pi];
       T rr[NQ_FAR], ww[NQ_FAR];
       T nrm[3] = {T(0), T(0), T(0)};
-      if constexpr (DLP) {
-        double nd[3];
-        panel_normal(tab, pj, nd);
-        nrm[0] = T(nd[0]);
-        nrm[1] = T(nd[1]);
-        nrm[2] = T(nd[2]);
-      }
+      if constexpr (DLP) panel_normal(tab, pj, nrm);
 #pragma unroll
       for (int a = 0; a < NQ_FAR; ++a) {
         const T dx = xi - qp[a * nn + pj], dy = yi - qp[(7 + a) * nn + pj];
