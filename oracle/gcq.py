@@ -89,19 +89,45 @@ def radau_iia(m: int):
     raise ValueError("m must be 1, 2 or 3")
 
 
+def stability_end(A) -> float:
+    """Right end x* of the interval (0, x*) of the positive real axis on which
+    the method's stability function R(x) = e_m^T (I - x A)^{-1} 1 exceeds 1 in
+    modulus (x* = 2 for implicit Euler, 6 for 2-stage Radau IIA): a grid search
+    for the last sign change of |R| - 1, refined by bisection."""
+    A = np.asarray(A, dtype=np.float64)
+    m = A.shape[0]
+    one = np.ones(m)
+    g = lambda x: abs(np.linalg.solve(np.eye(m) - x * A, one)[-1]) - 1.0
+    xs = np.linspace(1e-6, 200.0, 20001)
+    vals = np.array([g(x) for x in xs])
+    i = int(np.nonzero(vals > 0)[0].max())
+    lo, hi = xs[i], xs[i + 1]
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if g(mid) > 0 else (lo, mid)
+    return 0.5 * (lo + hi)
+
+
 def contour_steps(A, dt_min: float, dt_max: float):
     """Arguments (dt_min, dt_max, stage_ratio) of oracle.contour for method A.
 
-    Reading of App. A for m > 1 stages: q = 5 dt_max max|lambda(A)| /
-    (dt_min min|lambda(A)|) as printed, and the dt_min that scales gamma is the
-    smallest effective step dt_min min|lambda(A)|, so that the contour encloses
-    the poles 1/(dt lambda) of (I - dt s A)^{-1} (with dt_min itself they lie
-    outside for Radau IIA and the scheme fails; with this reading it reproduces
-    Radau IIA, which the tests check).  One stage: (dt_min, dt_max, 1)."""
-    ev = np.abs(np.linalg.eigvals(np.asarray(A, dtype=np.float64)))
-    if len(ev) == 1:
-        return dt_min * ev[0], dt_max * ev[0], 1.0
-    return dt_min * ev.min(), dt_max * ev.max(), 5.0
+    Reading of App. A for m > 1 stages.  The printed q = 5 dt_max max|lambda(A)| /
+    (dt_min min|lambda(A)|) is kept (stage_ratio = 5 max|lambda| / min|lambda|).
+    The contour always crosses the real axis at 0 and 2 / (dt_min scale); the
+    printed scale (the step itself) puts the crossing inside the interval
+    (0, x*/dt_min) where the stability function grows (|R(dt s)| > 1), and the
+    states at those points grow step by step until rounding swamps the
+    quadrature (Radau IIA with 3 stages diverges within 100 steps).  The
+    reading scales gamma by dt_min / x* instead, so the crossing is at
+    2 x* / dt_min, twice the end of that interval; with N_Q = N (log N)^2 points
+    it reproduces Radau IIA over long runs (tests).  One stage (implicit Euler):
+    the printed contour, (dt_min, dt_max, 1)."""
+    A = np.asarray(A, dtype=np.float64)
+    if A.shape[0] == 1:
+        return dt_min * A[0, 0], dt_max * A[0, 0], 1.0
+    ev = np.abs(np.linalg.eigvals(A))
+    x = stability_end(A)
+    return dt_min / x, dt_max / x, 5.0 * ev.max() / ev.min()
 
 
 def _matrix_V(apply_V, Z, Qs):

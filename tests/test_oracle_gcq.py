@@ -136,9 +136,51 @@ def test_rk_scheme_reproduces_radau_iia(m):
         qprev = q[n, -1]
 
 
+@pytest.mark.parametrize("m", [2, 3])
+def test_rk_long_run_with_the_papers_point_count(m):
+    """60 variable steps with N_Q = N (ln N)^2 points (App. A): the stage values
+    of Radau IIA for V = 1/(s + lam).  On this contour |R(dt s)| exceeds 1 at some
+    points (2.9 for two stages), so the quadrature must resolve the cancellation:
+    with a fixed, small N_Q long runs diverge, with the paper's count they do not."""
+    A = gcq.radau_iia(m)
+    rng = np.random.default_rng(17)
+    N = 60
+    dt = 0.01 * (1.0 + 3.0 * rng.random(N))
+    s, w = contour.contour(contour.n_points(N, m) + 1, *gcq.contour_steps(A, dt.min(), dt.max()))
+    q = rng.standard_normal((N, m, 2))
+    lam = 40.0
+    f = gcq.convolve_rk(lambda z, X: X / (z + lam), A, q, dt, s, w)
+    prev = np.zeros(2)
+    ref = np.zeros_like(q)
+    for n in range(N):
+        ref[n] = np.linalg.solve(np.eye(m) + lam * dt[n] * A, np.outer(np.ones(m), prev) + dt[n] * (A @ q[n]))
+        prev = ref[n, -1]
+    assert np.max(np.abs(f - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
 def test_rk_one_stage_is_implicit_euler_scheme():
     dt, s, w, q = _setup(12, seed=14)
     V = lambda z, X: X / (z + 25.0)
     f1 = gcq.convolve(V, q, dt, s, w)
     fr = gcq.convolve_rk(V, gcq.radau_iia(1), q[:, None, :], dt, s, w)[:, 0, :]
     assert np.max(np.abs(f1 - fr)) <= 1e-12 * np.max(np.abs(f1))
+
+
+def test_stability_interval_ends():
+    """x* of R(x) = e_m^T (I - x A)^{-1} 1: implicit Euler 1/(1 - x) has |R| > 1
+    on (0, 2); 2-stage Radau IIA (1 + x/3) / (1 - 2x/3 + x^2/6) on (0, 6)."""
+    assert abs(gcq.stability_end(gcq.radau_iia(1)) - 2.0) < 1e-9
+    assert abs(gcq.stability_end(gcq.radau_iia(2)) - 6.0) < 1e-9
+    x3 = gcq.stability_end(gcq.radau_iia(3))
+    R = lambda x: np.linalg.solve(np.eye(3) - x * gcq.radau_iia(3), np.ones(3))[-1]
+    assert abs(abs(R(x3)) - 1.0) < 1e-9 and abs(R(x3 * 1.01)) < 1.0 < abs(R(x3 * 0.99))
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_rk_contour_keeps_the_growth_small(m):
+    """On the contour of the reading, |R(dt_min s_l)| stays below 1.5 (the
+    printed scaling reaches 2.9 for two stages and 9 for three)."""
+    A = gcq.radau_iia(m)
+    s, _ = contour.contour(401, *gcq.contour_steps(A, 0.01, 0.03))
+    R = [abs(np.linalg.solve(np.eye(m) - 0.01 * z * A, np.ones(m))[-1]) for z in s]
+    assert max(R) < 1.5
