@@ -229,6 +229,11 @@ GCQ_API int gcq_set_frequencies(gcq_context* ctx, const gcq_c128* s, int32_t n_f
  *   sum_l w_l f(s_l) approximates -(1 / 2 pi i) times the counter-clockwise
  *   integral of f.  The points come in conjugate pairs s_{n+1-l} = conj(s_l);
  *   for odd n_points the middle point is real.  All points have Re s > 0.
+ *   The curve crosses the real axis at 0 and 2 / dt_min: for a Runge-Kutta
+ *   method of several stages pass dt_min / x* and dt_max / x*, x* the end of
+ *   the interval (0, x*) on which the method's stability function exceeds 1
+ *   in modulus (6 for 2-stage Radau IIA), so that the states of the stepping
+ *   do not grow on the contour.
  *   GCQ_ERR_ARG for n_points < 1, NULL arrays, dt_min <= 0, dt_max < dt_min,
  *   stage_ratio < 1, or q <= 1 (constant steps: the appendix perturbs q). */
 GCQ_API int gcq_contour(int32_t n_points, double dt_min, double dt_max, double stage_ratio,
