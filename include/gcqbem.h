@@ -239,6 +239,19 @@ GCQ_API int gcq_set_frequencies(gcq_context* ctx, const gcq_c128* s, int32_t n_f
 GCQ_API int gcq_contour(int32_t n_points, double dt_min, double dt_max, double stage_ratio,
                         gcq_c128* s, gcq_c128* w);
 
+/* gcq_contour_steps: the arguments (dt_min', dt_max', stage_ratio) of
+ *   gcq_contour for an m-stage Runge-Kutta method with Butcher matrix A (host,
+ *   m x m doubles, row-major, 1 <= m <= 4) and steps between dt_min and dt_max
+ *   (App. A, q = 5 dt_max max|lambda(A)| / (dt_min min|lambda(A)|)): for m > 1,
+ *   args = (dt_min / x*, dt_max / x*, 5 max|lambda(A)| / min|lambda(A)|) with x*
+ *   the end of the interval (0, x*) of the positive real axis on which the
+ *   stability function R(x) = e_m^T (I - x A)^{-1} 1 exceeds 1 in modulus (the
+ *   contour then crosses the real axis at 2 x* / dt_min); for m = 1,
+ *   (dt_min A, dt_max A, 1).  args: host, 3 doubles.  GCQ_ERR_ARG for invalid
+ *   sizes or steps, a singular A, or no such interval within (0, 200];
+ *   GCQ_ERR_NUMERIC when A is not diagonalisable. */
+GCQ_API int gcq_contour_steps(const double* A, int32_t m, double dt_min, double dt_max, double* args);
+
 /* gcq_contour_points: the number N_Q of contour points for n_steps >= 2 steps
  *   of a method with `stages` stages (Sec. 3, cost estimate after
  *   eq. gcq_formula, and App. A): N log N for one stage, N (log N)^2 for more,

@@ -90,6 +90,7 @@ def _load():
         "gcq_set_frequencies": [P, P, I32, I32],
         "gcq_contour": [I32, D, D, D, P, P],
         "gcq_contour_points": [I32, I32, P],
+        "gcq_contour_steps": [P, I32, D, D, P],
         "gcq_gcq_convolve": [P, P, I32, P, I32, I32, P, I32, P, P],
         "gcq_gcq_solve": [P, P, I32, P, I32, I32, P, I32, P, P, D, I32, I32, P],
         "gcq_build_cluster_tree": [P, I32, D, P],
@@ -154,6 +155,17 @@ def contour(n_points: int, dt_min: float, dt_max: float, stage_ratio: float = 1.
     _check(_lib.gcq_contour(int(n_points), float(dt_min), float(dt_max), float(stage_ratio),
                             s.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p)))
     return s, w
+
+
+def contour_steps(A, dt_min: float, dt_max: float):
+    """(dt_min', dt_max', stage_ratio) of the contour for Butcher matrix A (gcq_contour_steps)."""
+    Ah, pa = _host(np.atleast_2d(np.asarray(A, np.float64)), np.float64)
+    if Ah.shape[0] != Ah.shape[1]:
+        raise ValueError("A must be square")
+    out = np.zeros(3, np.float64)
+    _check(_lib.gcq_contour_steps(pa, int(Ah.shape[0]), float(dt_min), float(dt_max),
+                                  out.ctypes.data_as(C.c_void_p)))
+    return float(out[0]), float(out[1]), float(out[2])
 
 
 def contour_points(n_steps: int, stages: int = 2) -> int:

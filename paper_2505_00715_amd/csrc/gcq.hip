@@ -405,6 +405,59 @@ static int advance_state(gcq_context* ctx, GcqRun& R, int step, const double* q_
 
 using namespace gcq;
 
+extern "C" GCQ_API int gcq_contour_steps(const double* A, int32_t m, double dt_min, double dt_max,
+                                         double* args) {
+  if (!A || !args) return fail(GCQ_ERR_ARG, "A and args must not be NULL");
+  if (m < 1 || m > GCQ_MAX_STAGES) return fail(GCQ_ERR_ARG, "m must be in 1..%d", GCQ_MAX_STAGES);
+  if (!(dt_min > 0.0) || !(dt_max >= dt_min) || !std::isfinite(dt_max))
+    return fail(GCQ_ERR_ARG, "need 0 < dt_min <= dt_max");
+  for (int i = 0; i < m * m; ++i)
+    if (!std::isfinite(A[i])) return fail(GCQ_ERR_ARG, "A holds a non-finite entry");
+  if (m == 1) {
+    if (!(A[0] > 0.0)) return fail(GCQ_ERR_ARG, "a one-stage method needs A > 0");
+    args[0] = dt_min * A[0];
+    args[1] = dt_max * A[0];
+    args[2] = 1.0;
+    return GCQ_OK;
+  }
+  // |lambda(A)|
+  std::vector<double> Ar(A, A + m * m);
+  std::vector<zd> lam, P, Pinv;
+  if (!eigen_small(Ar, m, lam, P, Pinv)) return fail(GCQ_ERR_NUMERIC, "A is not diagonalisable");
+  double lmin = 1e300, lmax = 0.0;
+  for (const zd& l : lam) {
+    lmin = std::min(lmin, std::abs(l));
+    lmax = std::max(lmax, std::abs(l));
+  }
+  if (!(lmin > 0.0)) return fail(GCQ_ERR_ARG, "A is singular");
+  // x*: end of the interval (0, x*) where |R(x)| = |e_m^T (I - x A)^{-1} 1| > 1;
+  // the last grid point with |R| > 1 on (0, 200], then bisection
+  auto growth = [&](double x) {
+    std::vector<zd> M(m * m), u(m, 1.0);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) M[i * m + j] = (i == j ? 1.0 : 0.0) - x * A[i * m + j];
+    if (!zsolve(M, u, m, 1)) return 1e300;   // a pole: unbounded growth
+    return std::abs(u[m - 1]) - 1.0;
+  };
+  const int ngrid = 20000;
+  const double h = 200.0 / ngrid;
+  int last = -1;
+  for (int g = 1; g <= ngrid; ++g)
+    if (growth(g * h) > 0.0) last = g;
+  if (last < 0) return fail(GCQ_ERR_ARG, "the stability function does not exceed 1 on (0, 200]");
+  if (last == ngrid) return fail(GCQ_ERR_ARG, "the stability function exceeds 1 beyond x = 200");
+  double lo = last * h, hi = (last + 1) * h;
+  for (int it = 0; it < 100 && hi - lo > 1e-15 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (growth(mid) > 0.0) lo = mid; else hi = mid;
+  }
+  const double xs = 0.5 * (lo + hi);
+  args[0] = dt_min / xs;
+  args[1] = dt_max / xs;
+  args[2] = 5.0 * lmax / lmin;
+  return GCQ_OK;
+}
+
 extern "C" GCQ_API int gcq_gcq_convolve(gcq_context* ctx, const double* A, int32_t m, const double* dt,
                                         int32_t n_steps, int32_t n_step_points, const gcq_c128* w,
                                         int32_t precision, const double* Q, double* F) {

@@ -72,3 +72,23 @@ def test_contour_points_one_stage_and_errors():
             g.contour_points(*bad)
         with pytest.raises(ValueError):
             C.n_points(*bad)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_contour_steps_match_oracle(m):
+    from oracle import gcq as G
+    A = G.radau_iia(m)
+    got = g.contour_steps(A, 0.01, 0.035)
+    ref = G.contour_steps(A, 0.01, 0.035)
+    np.testing.assert_allclose(got, ref, rtol=1e-10)
+
+
+def test_contour_steps_errors():
+    with pytest.raises(g.GcqError):
+        g.contour_steps(np.zeros((2, 2)), 0.01, 0.02)          # singular
+    with pytest.raises(g.GcqError):
+        g.contour_steps(np.eye(5), 0.01, 0.02)                 # m > 4
+    with pytest.raises(g.GcqError):
+        g.contour_steps(np.array([[1.0]]), 0.02, 0.01)         # dt_max < dt_min
+    with pytest.raises(g.GcqError):
+        g.contour_steps(np.array([[-1.0, 0.0], [0.0, -2.0]]), 0.01, 0.02)   # no growth interval
