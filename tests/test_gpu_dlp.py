@@ -189,3 +189,25 @@ def test_dlp_3d_aca_product(sphere1280, prec, tol, bound):
         refv = np.stack([V[k] @ X[k] for k in range(len(s))])
         Yv = Y.cpu().numpy().reshape(len(s), P.n)
         assert np.linalg.norm(Yv - refv) / np.linalg.norm(refv) <= bound
+
+
+def test_dlp_3d_aca_with_conjugate_symmetry():
+    """The double layer's 3D-ACA over the 32-point BDF2 set with conjugate
+    symmetry (K(conj s) = conj K(s): only 17 frequencies approximated), every
+    frequency's product against the oracle's dense double layer."""
+    cfg = configs.get("sphere320")
+    P = Panels(cfg["xyz"], cfg["tri"])
+    K = dlp.dense(P, cfg["s"], cfg["c"])
+    ctx = _ctx(cfg, leaf=16)
+    st = ctx.aca3d(1e-8, 1e-8, 64, g.C128, g.FLAG_DOUBLE_LAYER)
+    assert st.n_blocks > 0
+    L = len(cfg["s"])
+    rng = np.random.default_rng(14)
+    X = rng.standard_normal((L, P.n)) + 1j * rng.standard_normal((L, P.n))
+    Y = torch.zeros(L * P.n, dtype=torch.complex128, device="cuda")
+    ctx.compressed_matvec(g.PER_FREQUENCY, g.C128, torch.from_numpy(X.reshape(-1)).cuda(), Y)
+    torch.cuda.synchronize()
+    Yg = Y.cpu().numpy().reshape(L, P.n)
+    ref = np.stack([K[k] @ X[k] for k in range(L)])
+    err = np.linalg.norm(Yg - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert err.max() <= 1e-6, err.max()
