@@ -326,13 +326,14 @@ __device__ inline int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, do
 // sequential rotations.  Rotations of one round commute (disjoint pairs), so the
 // result equals the cyclic sweep in that pair order.  A round is two phases:
 // the rotation parameters, then G^H A G by 2 x 2 blocks (rows of pair i,
-// columns of pair j) together with Q G.
+// columns of pair j) together with Q G.  Sweeps stop when the off-diagonal
+// squared Frobenius norm is at most `thr` times the diagonal's.
 // Always inlined: callers pass A and Q either in LDS or in global memory, and
 // the accesses compile to LDS instructions only where the pointer's origin is
 // visible.
 template <int NW>
 __device__ __attribute__((always_inline)) inline void jacobi_grp(cpx<double>* A, cpx<double>* Q,
-                                                                 int k, RecompShared& rs) {
+                                                                 int k, RecompShared& rs, double thr) {
   constexpr int NT = NW * WAVE;
   const int tid = threadIdx.x;
   for (int r = tid; r < k * k; r += NT) Q[r] = {(r / k == r % k) ? 1.0 : 0.0, 0.0};
@@ -353,7 +354,7 @@ __device__ __attribute__((always_inline)) inline void jacobi_grp(cpx<double>* A,
       else off += v;
     }
     grp_sum2<NW>(off, dg);
-    if (off <= 1e-30 * dg || off == 0.0) break;
+    if (off <= thr * dg || off == 0.0) break;
     for (int round = 0; round < ke - 1; ++round) {
       if (tid < np) {
         // circle method: position 0 fixed, positions 1..ke-1 rotate
@@ -591,7 +592,11 @@ __device__ __attribute__((always_inline)) inline int recompress_grp(
     }
   }
   __syncthreads();
-  jacobi_grp<NW>(B, Z, r, rs);
+  // B's eigenvalues s_i^2 decide the truncation at relative tol: a relative
+  // off-diagonal norm of 0.1 tol^2 leaves them far more accurate than that
+  // (full float64, 1e-15, for tol <= 1e-7)
+  const double rel_off = fmax(0.1 * tol * tol, 1e-15);
+  jacobi_grp<NW>(B, Z, r, rs, rel_off * rel_off);
   if (tid < r) rs.sg[tid] = fmax(B[tid * r + tid].re, 0.0);
   __syncthreads();
   if (tid < r) {  // descending order, ties by index
