@@ -593,9 +593,9 @@ __device__ __attribute__((always_inline)) inline int recompress_grp(
   }
   __syncthreads();
   // B's eigenvalues s_i^2 decide the truncation at relative tol: a relative
-  // off-diagonal norm of 0.1 tol^2 leaves them far more accurate than that
-  // (full float64, 1e-15, for tol <= 1e-7)
-  const double rel_off = fmax(0.1 * tol * tol, 1e-15);
+  // off-diagonal norm of tol^2 leaves them, and the kept directions, accurate
+  // to far below that (full float64, 1e-15, for tol <= 3e-8)
+  const double rel_off = fmax(tol * tol, 1e-15);
   jacobi_grp<NW>(B, Z, r, rs, rel_off * rel_off);
   if (tid < r) rs.sg[tid] = fmax(B[tid * r + tid].re, 0.0);
   __syncthreads();
