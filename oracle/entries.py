@@ -130,3 +130,27 @@ def block(P, rows, cols, s, c: float):
 def dense(P, s, c: float):
     idx = np.arange(P.n)
     return block(P, idx, idx, s, c)
+
+
+def galerkin_far(P, rows, cols, s, c: float):
+    """Far-field Galerkin entries, shape (len(s), len(rows), len(cols)):
+        A^G(s)[i, j] = int_{tau_i} int_{tau_j} U(|x - y|, s) dy dx
+    with the 7-point rule on both panels, sum_p sum_q w_ip w_jq U(|y_ip - y_jq|).
+    Not the collocation path's operator: the Galerkin variant of the same far
+    tier (Sec. 3 names both discretisations; Sec. 2's Galerkin form is
+    symmetric), kept for the pin that the far tier's points and weights enter
+    both panels alike, A^G = (A^G)^T exactly, and that collocation at the
+    centroid is the one-point outer rule of it, |tau_i| V[i, j] ~ A^G[i, j].
+    Only meaningful for far pairs (no singular treatment)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    s = np.atleast_1d(np.asarray(s, dtype=np.complex128))
+    out = np.zeros((len(s), len(rows), len(cols)), dtype=np.complex128)
+    for a, i in enumerate(rows):
+        # |y_ip - y_jq| for all p (7), all j, all q (7)
+        d = P.qp[i][:, None, None, :] - P.qp[cols][None, :, :, :]  # (7, n, 7, 3)
+        r = np.sqrt((d * d).sum(-1))
+        w = P.qw[i][:, None, None] * P.qw[cols][None, :, :]        # (7, n, 7)
+        for f, sf in enumerate(s):
+            out[f, a, :] = (kernel(r, sf, c) * w).sum(axis=(0, 2))
+    return out

@@ -189,3 +189,53 @@ def test_far_reciprocity_weighted_by_area():
         b = P.area[j] * entries.entry(P, j, i, [s], 1.0)[0]
         d = np.linalg.norm(P.centroid[i] - P.centroid[j])
         assert abs(a - b) / abs(a) < 2.0 * (P.h.max() / d) ** 2
+
+
+def _far_set(P, count, seed):
+    """Panels whose pairs are all far (both directions of the tier test)."""
+    rng = np.random.default_rng(seed)
+    chosen = []
+    for i in rng.permutation(P.n):
+        if all(entries.tier(P, int(i), j) == entries.FAR and entries.tier(P, j, int(i)) == entries.FAR
+               for j in chosen):
+            chosen.append(int(i))
+        if len(chosen) == count:
+            break
+    return np.array(chosen)
+
+
+def test_galerkin_far_is_complex_symmetric():
+    """The Galerkin variant of the far tier is exactly complex-symmetric
+    (not Hermitian): A^G(s) = A^G(s)^T to rounding, for complex s; a weight
+    taken from the wrong panel, or a point set used on one side only, breaks
+    this."""
+    xyz, tri = mesh.icosphere(3)
+    P = Panels(xyz, tri)
+    idx = _far_set(P, 40, 1)
+    S = np.array([0.5 + 0.0j, 3.0 + 4.0j, 12.0 - 9.0j])
+    A = entries.galerkin_far(P, idx, idx, S, 1.0)
+    off = ~np.eye(len(idx), dtype=bool)
+    for f in range(len(S)):
+        Af = A[f]
+        assert np.abs(Af - Af.T)[off].max() <= 1e-15 * np.abs(Af[off]).max()
+        # complex-symmetric, not Hermitian
+        assert np.abs(Af - np.conj(Af.T))[off].max() > 1e-3 * np.abs(Af[off]).max() or S[f].imag == 0
+
+
+def test_collocation_is_the_centroid_rule_of_galerkin():
+    """Collocation at the centroid is the one-point outer rule of the Galerkin
+    double integral: |tau_i| V[i, j] = A^G[i, j] + O((h / d)^2) relative (the
+    centroid rule is exact for linear integrands)."""
+    xyz, tri = mesh.icosphere(3)
+    P = Panels(xyz, tri)
+    idx = _far_set(P, 30, 2)
+    S = np.array([1.0 + 2.0j])
+    G = entries.galerkin_far(P, idx, idx, S, 1.0)[0]
+    V = entries.block(P, idx, idx, S, 1.0)[0]
+    for a in range(len(idx)):
+        for b in range(len(idx)):
+            if a == b:
+                continue
+            d = np.linalg.norm(P.centroid[idx[a]] - P.centroid[idx[b]])
+            lhs = P.area[idx[a]] * V[a, b]
+            assert abs(lhs - G[a, b]) <= 2.0 * (P.h.max() / d) ** 2 * abs(G[a, b])

@@ -60,14 +60,38 @@ def test_split_axis_and_order():
 
 
 def test_box_distance_brute_force():
+    """dist(a, b) is the smallest distance between a point of box a and a point
+    of box b (found here by bound-constrained minimisation from random starts,
+    not by the gap formula), a lower bound of every vertex-to-vertex distance
+    of the two clusters; diam(c) is the box diagonal, an upper bound of every
+    vertex-to-vertex distance inside cluster c."""
+    from scipy.optimize import minimize
     xyz, tri = mesh.icosphere(3)
     P = Panels(xyz, tri)
     T = ClusterTree(P, 64)
     rng = np.random.default_rng(0)
+
+    def verts(c):
+        idx = T.indices(c)
+        return np.concatenate([P.v0[idx], P.v1[idx], P.v2[idx]])
+
     for _ in range(50):
         a, b = rng.integers(0, len(T.begin), 2)
-        # distance between boxes = min over box points: clamp one box's corners
-        lo1, hi1, lo2, hi2 = T.bmin[a], T.bmax[a], T.bmin[b], T.bmax[b]
-        gap = np.array([max(0.0, lo1[k] - hi2[k], lo2[k] - hi1[k]) for k in range(3)])
-        assert abs(T.dist(a, b) - np.sqrt((gap ** 2).sum())) < 1e-15
-        assert abs(T.diam(a) - np.linalg.norm(hi1 - lo1)) < 1e-15
+        bounds = [(T.bmin[a][k], T.bmax[a][k]) for k in range(3)] + \
+                 [(T.bmin[b][k], T.bmax[b][k]) for k in range(3)]
+        best = np.inf
+        for _ in range(4):
+            z0 = np.array([rng.uniform(lo, hi) for lo, hi in bounds])
+            r = minimize(lambda z: ((z[:3] - z[3:]) ** 2).sum(), z0,
+                         jac=lambda z: np.concatenate([2 * (z[:3] - z[3:]), -2 * (z[:3] - z[3:])]),
+                         bounds=bounds, method="L-BFGS-B", options={"ftol": 1e-15, "gtol": 1e-12})
+            best = min(best, r.fun)
+        assert abs(T.dist(a, b) - np.sqrt(max(best, 0.0))) <= 1e-6
+        va, vb = verts(a), verts(b)
+        dmin = np.sqrt(((va[:, None, :] - vb[None, :, :]) ** 2).sum(-1).min())
+        assert T.dist(a, b) <= dmin + 1e-15
+        dmax = np.sqrt(((va[:, None, :] - va[None, :, :]) ** 2).sum(-1).max())
+        assert dmax <= T.diam(a) + 1e-15
+        # the diagonal joins two corners of the box: it is attained by a pair of
+        # box points, so it is the box's own diameter
+        assert abs(T.diam(a) - np.linalg.norm(T.bmax[a] - T.bmin[a])) <= 1e-15
