@@ -61,8 +61,20 @@ typedef struct {
  *   GCQ_C128: complex128 throughout.
  *   GCQ_C64:  complex64 far-field entries, low-rank factors and products with
  *             float accumulation; the self and near-singular quadrature and
- *             every stopping-criterion norm stay in float64. */
-enum { GCQ_C128 = 0, GCQ_C64 = 1 };
+ *             every stopping-criterion norm stay in float64.
+ *   GCQ_C64_SPLIT_BF16: products only (gcq_compressed_matvec in
+ *             GCQ_PER_FREQUENCY mode, gcq_solve) with an operator built at
+ *             GCQ_C64, complex64 vectors, on the bf16 matrix cores with float
+ *             accumulation: the operator's float values a are split into two
+ *             bf16 planes (ha = bf16(a), la = bf16(a - ha); a fixed relative
+ *             perturbation <= 2^-18 of the operator), the vectors' values x
+ *             into three (hx, mx, lx; <= 2^-27), and each real product is
+ *             ha hx + ha mx + ha lx + la hx + la mx, which is linear in x up
+ *             to 2^-26 |a| |x| (so GMRES converges as with complex64).  The
+ *             split copy of the operator (as many bytes as its complex64
+ *             slices) is made on the first such product and kept with the
+ *             operator. */
+enum { GCQ_C128 = 0, GCQ_C64 = 1, GCQ_C64_SPLIT_BF16 = 2 };
 
 /* Product modes of gcq_compressed_matvec.
  *   GCQ_PER_FREQUENCY: Y[k] = V(s_k) X[k] for every frequency k, V(s_k)
@@ -280,7 +292,8 @@ GCQ_API int gcq_contour_points(int32_t n_steps, int32_t stages, int32_t* n_point
  *     f_n = P diag(V(lam_e / dt_n)) P^{-1} q_n + sum_l V(s_l) w_l (x_{n-1}(s_l))_m M_l(dt_n) 1
  *   (per stage one product over the set, summed over its columns: the stage
  *   value is the real part).  Q (input) and F (output) are device arrays of
- *   n_steps x m x n_triangles doubles (step, stage, triangle order).  The
+ *   n_steps x m x n_triangles doubles (step, stage, triangle order), checked
+ *   to be device memory (GCQ_ERR_ARG otherwise).  The
  *   state (NQ x n complex doubles: only the last stage of x enters) and the
  *   product's columns are allocated for the call; returns after the last step.
  *   GCQ_ERR_ARG for a singular A, GCQ_ERR_NUMERIC when A^{-1} is not
@@ -297,7 +310,11 @@ GCQ_API int gcq_gcq_convolve(gcq_context* ctx, const double* A, int32_t m, const
  *   batched solver; the other frequencies' systems have zero right-hand sides
  *   and end at once), q_n = P y.  F (input) and Q (output): device doubles,
  *   n_steps x m x n_triangles.  rtol, max_iter, restart as in gcq_solve;
- *   *iters_max (may be NULL) receives the largest iteration count of a step. */
+ *   *iters_max (may be NULL) receives the largest iteration count of a step.
+ *   Returns GCQ_NOT_CONVERGED (after the last step) if the solve of some step
+ *   ended above rtol: its density, inaccurate, then also entered the history
+ *   of every later step.  F and Q must be device memory (GCQ_ERR_ARG
+ *   otherwise), as for gcq_gcq_convolve. */
 GCQ_API int gcq_gcq_solve(gcq_context* ctx, const double* A, int32_t m, const double* dt,
                           int32_t n_steps, int32_t n_step_points, const gcq_c128* w,
                           int32_t precision, const double* F, double* Q, double rtol,
@@ -309,10 +326,42 @@ GCQ_API int gcq_gcq_solve(gcq_context* ctx, const double* A, int32_t m, const do
 GCQ_API int gcq_build_cluster_tree(gcq_context* ctx, int32_t leaf_size, double eta,
                                    gcq_tree_info* info);
 
+/* gcq_upload_cluster_tree: a cluster tree and block cluster tree made by the
+ *   caller (Sec. 4: cluster tree, block cluster tree, eq. admissible), used
+ *   instead of gcq_build_cluster_tree's own, so that another implementation's
+ *   partition (an oracle's, a PCA split as the paper's) can be injected.  All
+ *   arrays are host memory, copied:
+ *     perm (n_triangles): cluster position -> caller's triangle index, a
+ *       permutation;
+ *     cl_begin, cl_end (n_clusters): each cluster is positions [begin, end),
+ *       non-empty; cluster 0 is the root [0, n_triangles);
+ *     cl_son (2 x n_clusters): the two sons of a cluster, which split its range
+ *       in two (first son first) and have larger indices than it, or (-1, -1)
+ *       for a leaf; every cluster but the root is the son of exactly one;
+ *     blk_row, blk_col, blk_admissible (n_blocks): the leaves of the block
+ *       tree as cluster pairs and their admissibility (0 or 1).  They must be
+ *       the leaves of a block tree over this cluster tree: from (root, root),
+ *       each pair that is not a block is split through the sons of the
+ *       clusters that have them, and every block must be reached; so the blocks
+ *       cover every (row, column) pair exactly once.  An admissible block's
+ *       clusters need vertex boxes at positive distance (eq. admissible with
+ *       some eta); the library does not test the eta condition itself.
+ *   The blocks keep the caller's order (block indices of gcq_get_tree,
+ *   gcq_get_block_factors and gcq_get_aca3d_block are positions in it).
+ *   info may be NULL.  GCQ_ERR_ARG for any violation (nothing is changed);
+ *   GCQ_ERR_STATE without a mesh.  Like gcq_build_cluster_tree, it
+ *   invalidates faces and operators built on an earlier tree. */
+GCQ_API int gcq_upload_cluster_tree(gcq_context* ctx, const int32_t* perm, int32_t n_clusters,
+                                    const int32_t* cl_begin, const int32_t* cl_end,
+                                    const int32_t* cl_son, int32_t n_blocks, const int32_t* blk_row,
+                                    const int32_t* blk_col, const uint8_t* blk_admissible,
+                                    gcq_tree_info* info);
+
 /* gcq_get_tree: copies the partition to host arrays: perm (n_triangles:
  *   internal position -> caller index) and blocks (n_blocks x 5 int32:
  *   row_begin, row_end, col_begin, col_end in internal positions, admissible),
- *   in depth-first order.  Either pointer may be NULL. */
+ *   in depth-first order (an uploaded tree: the caller's block order).
+ *   Either pointer may be NULL. */
 GCQ_API int gcq_get_tree(gcq_context* ctx, int32_t* perm, int32_t* blocks);
 
 /* ---- entries (Sec. 3) -----------------------------------------------------
@@ -374,12 +423,26 @@ GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol, int32_t max_
 GCQ_API int gcq_get_aca3d_block(gcq_context* ctx, int32_t block, int32_t cap, int32_t* rank,
                                 int32_t* freqs, gcq_c128* fibers, gcq_c128* slices);
 
+/* gcq_sample_rows: rows of the compressed 3D array at frequency `freq`
+ *   (0..n_freq-1): out[a][j] = V~(s_freq)[rows[a], j] for every column j,
+ *   V~(s) = sum_b sum_d f_{b,d}(s) H_{b,d} the approximant of Alg. 1 that the
+ *   products of eq. product apply (conjugated for a frequency represented by
+ *   its conjugate partner).  rows: host, n_rows caller indices (repeats
+ *   allowed); out_dev: device, n_rows x n_triangles complex values, row-major,
+ *   columns in the caller's order, complex128 or complex64 as the operator was
+ *   built; caller-owned.  Returns after the rows are written.  GCQ_ERR_STATE
+ *   before gcq_aca3d; GCQ_ERR_ARG for indices out of range or host memory
+ *   as out_dev. */
+GCQ_API int gcq_sample_rows(gcq_context* ctx, const int32_t* rows, int32_t n_rows, int32_t freq,
+                            void* out_dev);
+
 /* ---- products (eq. product) -----------------------------------------------
  * gcq_compressed_matvec: X_dev, Y_dev are device arrays of n_cols vectors of
  *   length n_triangles, vector-major (torch shape (n_cols, n), contiguous);
- *   complex128 for GCQ_C128, complex64 for GCQ_C64.  n_cols must equal
- *   n_freq.  For GCQ_WEIGHTED_SUM, Y_dev holds one vector.  Enqueued on the
- *   context stream without synchronisation. */
+ *   complex128 for GCQ_C128, complex64 for GCQ_C64 and GCQ_C64_SPLIT_BF16
+ *   (GCQ_PER_FREQUENCY only; GCQ_ERR_UNSUPPORTED for the other modes).
+ *   n_cols must equal n_freq.  For GCQ_WEIGHTED_SUM, Y_dev holds one vector.
+ *   Enqueued on the context stream without synchronisation. */
 GCQ_API int gcq_compressed_matvec(gcq_context* ctx, int32_t mode, int32_t precision,
                                   const void* X_dev, void* Y_dev, int32_t n_cols);
 
@@ -388,7 +451,8 @@ GCQ_API int gcq_compressed_matvec(gcq_context* ctx, int32_t mode, int32_t precis
  *   restarted GMRES(restart) on the 3D-ACA operator, orthogonalisation in
  *   float64 (classical Gram-Schmidt twice), until |b - A x| <= rtol |b| or
  *   max_iter iterations.  B_dev, X_dev: complex128 device arrays shaped like
- *   the products' X.  The product inside uses `precision`.  Returns
+ *   the products' X.  The product inside uses `precision` (GCQ_C64_SPLIT_BF16
+ *   with an operator built at GCQ_C64).  Returns
  *   GCQ_NOT_CONVERGED if some system missed the tolerance. */
 GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_dev, double rtol,
                       int32_t max_iter, int32_t restart, int32_t precision,

@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgcqbem.so")
 
-C128, C64 = 0, 1
+C128, C64, C64_SPLIT_BF16 = 0, 1, 2
 PER_FREQUENCY, WEIGHTED_SUM, PLAIN_H = 0, 1, 2
 FLAG_RECOMPRESS, FLAG_USE_PREDICTOR, FLAG_PER_FREQ_LAUNCH, FLAG_DOUBLE_LAYER = 1, 2, 4, 8
 OK, NOT_CONVERGED, RANK_CAPPED = 0, 1, 2
@@ -95,6 +95,7 @@ def _load():
         "gcq_gcq_solve": [P, P, I32, P, I32, I32, P, I32, P, P, D, I32, I32, P],
         "gcq_build_cluster_tree": [P, I32, D, P],
         "gcq_get_tree": [P, P, P],
+        "gcq_upload_cluster_tree": [P, P, I32, P, P, P, I32, P, P, P, P],
         "gcq_assemble_slices": [P, P, I64, P, I64, P, I32, I32, P],
         "gcq_assemble_dlp_slices": [P, P, I64, P, I64, P, I32, I32, P],
         "gcq_aca_blocks": [P, P, I32, D, I32, I32, U32, P],
@@ -102,6 +103,7 @@ def _load():
         "gcq_aca3d": [P, D, D, I32, I32, U32, P],
         "gcq_get_aca3d_block": [P, I32, I32, P, P, P, P],
         "gcq_compressed_matvec": [P, I32, I32, P, P, I32],
+        "gcq_sample_rows": [P, P, I32, I32, P],
         "gcq_solve": [P, P, P, D, I32, I32, I32, P],
         "gcq_rank_features": [P, P, I32, P],
         "gcq_rank_model_train": [P, P, P, I64, P, P],
@@ -251,6 +253,26 @@ class Context:
         self.tree_info = info
         return info
 
+    def upload_cluster_tree(self, perm, cl_begin, cl_end, cl_son, blk_row, blk_col,
+                            blk_admissible) -> TreeInfo:
+        """Use a caller-made partition (gcq_upload_cluster_tree): perm (n),
+        cl_begin, cl_end (n_clusters), cl_son (n_clusters x 2, -1 for leaves),
+        blk_row, blk_col, blk_admissible (n_blocks)."""
+        pp, p0 = _host(perm, np.int32)
+        cb, p1 = _host(cl_begin, np.int32)
+        ce, p2 = _host(cl_end, np.int32)
+        cs, p3 = _host(np.asarray(cl_son).reshape(-1), np.int32)
+        br, p4 = _host(blk_row, np.int32)
+        bc, p5 = _host(blk_col, np.int32)
+        ba, p6 = _host(blk_admissible, np.uint8)
+        if len(ce) != len(cb) or len(cs) != 2 * len(cb) or len(bc) != len(br) or len(ba) != len(br):
+            raise ValueError("tree arrays of inconsistent lengths")
+        info = TreeInfo()
+        _check(_lib.gcq_upload_cluster_tree(self._h, p0, len(cb), p1, p2, p3, len(br), p4, p5, p6,
+                                            C.byref(info)))
+        self.tree_info = info
+        return info
+
     def get_tree(self):
         nb = self.tree_info.n_blocks
         perm = np.zeros(self.n, np.int32)
@@ -316,6 +338,7 @@ class Context:
         st = Aca3dStats()
         code = _check(_lib.gcq_aca3d(self._h, float(tol_aca), float(tol), int(max_freq_rank),
                                      precision, flags, C.byref(st)))
+        self.F_precision = precision
         st.status = code
         return st
 
@@ -337,6 +360,17 @@ class Context:
         return freqs[:r].copy(), fib[:r].copy(), np.transpose(sl[:r], (0, 2, 1)).copy()
 
     # ---- products and solve
+    def sample_rows(self, rows, freq: int, out):
+        """Rows of the compressed operator at frequency ``freq`` into ``out``
+        (device tensor of len(rows) x n complex values, the operator's
+        precision) -- gcq_sample_rows."""
+        import torch
+        rh, pr = _host(rows, np.int32)
+        dt = torch.complex128 if self.F_precision == C128 else torch.complex64
+        po = _dev(out, dt, len(rh) * self.n, "out")
+        _check(_lib.gcq_sample_rows(self._h, pr, len(rh), int(freq), po))
+        return out
+
     def compressed_matvec(self, mode: int, precision: int, X, Y):
         import torch
         dt = torch.complex128 if precision == C128 else torch.complex64
@@ -354,7 +388,7 @@ class Context:
         Ah, pa, m = self._butcher(A)
         n_steps = Q.numel() // (m * self.n)
         dth, pd = _host(np.broadcast_to(np.asarray(dt, np.float64), (n_steps,)), np.float64)
-        wh, pw = _host(w, np.complex128)
+        wh, pw = self._weights(w, n_step_points)
         pq = _dev(Q, torch.float64, n_steps * m * self.n, "Q")
         pf = _dev(F, torch.float64, n_steps * m * self.n, "F")
         _check(_lib.gcq_gcq_convolve(self._h, pa, m, pd, int(n_steps), int(n_step_points), pw, precision,
@@ -364,18 +398,33 @@ class Context:
     def gcq_solve(self, dt, w, F, Q, precision: int = C128, rtol: float = 1e-8,
                   max_iter: int = 300, restart: int = 50, n_step_points: int = 1, A=None) -> int:
         """Densities of the gCQ scheme for given f (gcq_gcq_solve): F, Q device
-        float64 tensors of n_steps x m x n; returns the largest GMRES count."""
+        float64 tensors of n_steps x m x n; returns the largest GMRES count.
+        The call's status is kept in ``last_status`` (NOT_CONVERGED, with a
+        RuntimeWarning, when some step's solve ended above rtol)."""
         import torch
         Ah, pa, m = self._butcher(A)
         n_steps = F.numel() // (m * self.n)
         dth, pd = _host(np.broadcast_to(np.asarray(dt, np.float64), (n_steps,)), np.float64)
-        wh, pw = _host(w, np.complex128)
+        wh, pw = self._weights(w, n_step_points)
         pf = _dev(F, torch.float64, n_steps * m * self.n, "F")
         pq = _dev(Q, torch.float64, n_steps * m * self.n, "Q")
         it = C.c_int32(0)
-        _check(_lib.gcq_gcq_solve(self._h, pa, m, pd, int(n_steps), int(n_step_points), pw, precision,
-                                  pf, pq, float(rtol), int(max_iter), int(restart), C.byref(it)))
+        code = _check(_lib.gcq_gcq_solve(self._h, pa, m, pd, int(n_steps), int(n_step_points), pw,
+                                         precision, pf, pq, float(rtol), int(max_iter), int(restart),
+                                         C.byref(it)))
+        self.last_status = code
+        if code == NOT_CONVERGED:
+            import warnings
+            warnings.warn("gcq_gcq_solve: the solve of some step ended above rtol", RuntimeWarning)
         return it.value
+
+    def _weights(self, w, n_step_points):
+        # one contour weight per frequency after the step points
+        wh, pw = _host(np.asarray(w).reshape(-1), np.complex128)
+        if wh.size != self.L - int(n_step_points):
+            raise ValueError(f"w holds {wh.size} weights; the set has {self.L - int(n_step_points)} "
+                             f"contour points after {int(n_step_points)} step points")
+        return wh, pw
 
     @staticmethod
     def _butcher(A):

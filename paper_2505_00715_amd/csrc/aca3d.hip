@@ -830,7 +830,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   GCQ_HIP(hipSetDevice(ctx->device));
   Faces3D& F = ctx->F;
   F.valid = false;
-  F.graphs.clear();   // they refer to the tables rebuilt below
+  F.drop_product_state();   // graphs and tables refer to the operator rebuilt below
   F.precision = precision;
   F.dlp = dlp;
   F.nK = nK;

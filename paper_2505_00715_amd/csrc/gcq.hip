@@ -464,7 +464,8 @@ extern "C" GCQ_API int gcq_gcq_convolve(gcq_context* ctx, const double* A, int32
   const auto t0 = std::chrono::steady_clock::now();
   GcqRun R;
   GCQ_TRY(gcq_prepare(ctx, A, m, dt, n_steps, n_step_points, w, precision, R));
-  if (!Q || !F) return fail(GCQ_ERR_ARG, "Q and F must not be NULL");
+  GCQ_TRY(check_device_ptr(ctx, Q, "Q"));
+  GCQ_TRY(check_device_ptr(ctx, F, "F"));
   const int64_t stride = int64_t(m) * R.n;   // one step: m stages of n values
   for (int step = 0; step < n_steps; ++step) {
     if (step > 0) GCQ_TRY(advance_state(ctx, R, step, Q + (step - 1) * stride));
@@ -484,7 +485,8 @@ extern "C" GCQ_API int gcq_gcq_solve(gcq_context* ctx, const double* A, int32_t 
   const auto t0 = std::chrono::steady_clock::now();
   GcqRun R;
   GCQ_TRY(gcq_prepare(ctx, A, m, dt, n_steps, n_step_points, w, precision, R));
-  if (!Q || !F) return fail(GCQ_ERR_ARG, "F and Q must not be NULL");
+  GCQ_TRY(check_device_ptr(ctx, F, "F"));
+  GCQ_TRY(check_device_ptr(ctx, Q, "Q"));
   const int n = R.n, L = R.L;
   const int64_t stride = int64_t(m) * n;
   hipStream_t st = ctx->stream;
@@ -496,6 +498,7 @@ extern "C" GCQ_API int gcq_gcq_solve(gcq_context* ctx, const double* A, int32_t 
   const int grid = int(std::min<int64_t>((int64_t(L) * n + 255) / 256, int64_t(ctx->cus) * 16));
   const int g3 = int(std::min<int64_t>((stride + 255) / 256, int64_t(ctx->cus) * 16));
   int itmax = 0;
+  bool missed = false;   // some step's GMRES ended above rtol
   for (int step = 0; step < n_steps; ++step) {
     // history of the earlier steps per stage: the contour sum, no step-point column
     if (step > 0) {
@@ -508,7 +511,9 @@ extern "C" GCQ_API int gcq_gcq_solve(gcq_context* ctx, const double* A, int32_t 
                        R.ce(step), R.pinv(), d_B.as<cpx<double>>());
     GCQ_HIP(hipGetLastError());
     gcq_solve_stats ss;
-    GCQ_TRY(gcq_solve(ctx, d_B.p, d_S.p, rtol, max_iter, restart, precision, &ss));
+    const int rs = gcq_solve(ctx, d_B.p, d_S.p, rtol, max_iter, restart, precision, &ss);
+    if (rs < 0) return rs;
+    if (rs == GCQ_NOT_CONVERGED || ss.n_converged < ss.n_systems) missed = true;
     itmax = std::max(itmax, int(ss.iters_max));
     hipLaunchKernelGGL(gcq_take, dim3(g3), dim3(256), 0, st, d_S.as<cpx<double>>(), m, n, R.ke(step), R.P(),
                        Q + step * stride);
@@ -518,5 +523,5 @@ extern "C" GCQ_API int gcq_gcq_solve(gcq_context* ctx, const double* A, int32_t 
   ctx->kernel_ms["gcq_solve"] =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (iters_max) *iters_max = itmax;
-  return GCQ_OK;
+  return missed ? GCQ_NOT_CONVERGED : GCQ_OK;
 }

@@ -141,7 +141,7 @@ struct Solver {
     hipStream_t st = ctx->stream;
     if (precision == GCQ_C128) return run_compressed(ctx, GCQ_PER_FREQUENCY, GCQ_C128, x, y);
     hipLaunchKernelGGL(gm_to32, dim3(2048), dim3(256), 0, st, x, t32, total);
-    GCQ_TRY(run_compressed(ctx, GCQ_PER_FREQUENCY, GCQ_C64, t32, t32 + total));
+    GCQ_TRY(run_compressed(ctx, GCQ_PER_FREQUENCY, precision, t32, t32 + total));
     hipLaunchKernelGGL(gm_from32, dim3(2048), dim3(256), 0, st, t32 + total, y, total);
     return GCQ_OK;
   }
@@ -165,7 +165,7 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
   if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
   GCQ_NEED_DEVICE(ctx);
   if (!ctx->F.valid) return fail(GCQ_ERR_STATE, "run gcq_aca3d first");
-  if (precision != ctx->F.precision)
+  if (storage_precision(precision) != ctx->F.precision)
     return fail(GCQ_ERR_ARG, "precision differs from the one the 3D-ACA was built in");
   if (!(rtol > 0.0) || restart < 1 || restart > 200 || max_iter < 0)
     return fail(GCQ_ERR_ARG, "bad solver parameters");

@@ -147,7 +147,21 @@ struct Faces3D {
   // the product's own buffers: frequency-major copies of X and Y, frequency
   // tables (position in K, conjugation flag); fixed while the operator lives
   DevBuf pxy, pmeta;
+  bool meta_valid = false;       // pmeta holds the current frequency set's tables
+  // the operator's slices split into bf16 planes for GCQ_C64_SPLIT_BF16
+  // products (built on first use, per block table d_bfblk)
+  DevBuf bfpool, bftbuf, d_bfblk, d_bfitems, d_bfrowblk, d_bfbig, d_bfmask;
+  bool bf_valid = false;
+  int bf_items = 0, bf_big = 0, bf_levels = 0;
+  int64_t bf_bytes = 0;
   ProductGraphs graphs;
+  // the operator or the frequency set changed: captured products, the
+  // product's frequency tables and the bf16 copy no longer apply
+  void drop_product_state() {
+    graphs.clear();
+    meta_valid = false;
+    bf_valid = false;
+  }
   int n_mvblocks = 0;
   int64_t storage_bytes = 0;
   int64_t dense_bytes = 0;
@@ -249,4 +263,8 @@ int check_device_ptr(gcq_context* ctx, const void* p, const char* what);
 int timed_begin(gcq_context* ctx);
 double timed_end(gcq_context* ctx, const char* name);
 inline int csize(int precision) { return precision == GCQ_C128 ? 16 : 8; }
+// storage precision of a call's precision (split-bf16 products use complex64 data)
+inline int storage_precision(int precision) {
+  return precision == GCQ_C64_SPLIT_BF16 ? GCQ_C64 : precision;
+}
 }  // namespace gcq

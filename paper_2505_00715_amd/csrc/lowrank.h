@@ -3,11 +3,13 @@
 //
 // aca_wave: partially pivoted ACA of an entry function (one wave64).
 // recompress_wave: QR/SVD recompression of the ACA factors, carried out
-//   through their Gram matrices: with G_V = V^H V = Q L Q^H and
-//   B = L^{1/2} Q^H G_U Q L^{1/2} = Z S^2 Z^H, the truncated SVD of U V^H is
-//   (U Q L^{1/2} Z_t)(V Q L^{-1/2} Z_t)^H, because R_V = L^{1/2} Q^H satisfies
-//   R_V^H R_V = G_V (it plays the role of the triangular QR factor) and
-//   B = M^H M for the core M = R_U R_V^H.
+//   through their Gram matrices: G_V = V^H V = R^H R by Cholesky with
+//   diagonal pivoting (R, upper triangular on its pivot order, plays the role
+//   of the QR factor of V; a remaining diagonal below 1e-14 of the largest
+//   ends it at numerical rank r), then B = R G_U R^H = Z S^2 Z^H by Hermitian
+//   Jacobi, so that S holds the singular values of U V^H; the truncated
+//   factors are Ubar = U R^H Z_t and Vbar = V R^+ Z_t, R^+ the right inverse
+//   of R on its pivot rows (a triangular solve).
 // apply_factors: forms the recompressed factors from the coefficients.
 #pragma once
 #include "device_common.h"

@@ -6,4 +6,10 @@
 namespace gcq {
 // mode GCQ_PER_FREQUENCY or GCQ_WEIGHTED_SUM; X, Y in the caller's layout
 int run_compressed(gcq_context* ctx, int mode, int precision, const void* X, void* Y);
+// split-bf16 per-frequency product (matvec_bf16.hip): the operator's bf16
+// copy (once per operator), the size of the product's buffers (ctx->F.pxy),
+// and the product's kernels on a stream (capturable: no allocation)
+int bf16_setup(gcq_context* ctx);
+size_t bf16_buffer_bytes(gcq_context* ctx);
+void enqueue_perfreq_bf16(gcq_context* ctx, hipStream_t st, const void* X, void* Y);
 }  // namespace gcq

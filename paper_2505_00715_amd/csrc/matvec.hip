@@ -175,7 +175,7 @@ extern "C" GCQ_API int gcq_compressed_matvec(gcq_context* ctx, int32_t mode, int
                                              const void* X_dev, void* Y_dev, int32_t n_cols) {
   if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
   GCQ_NEED_DEVICE(ctx);
-  if (precision != GCQ_C128 && precision != GCQ_C64)
+  if (precision != GCQ_C128 && precision != GCQ_C64 && precision != GCQ_C64_SPLIT_BF16)
     return fail(GCQ_ERR_ARG, "unknown precision %d", precision);
   if (!ctx->have_tree || !ctx->have_freq) return fail(GCQ_ERR_STATE, "no operator built");
   if (n_cols != ctx->L) return fail(GCQ_ERR_ARG, "n_cols must equal the number of frequencies");
@@ -185,7 +185,8 @@ extern "C" GCQ_API int gcq_compressed_matvec(gcq_context* ctx, int32_t mode, int
   if (mode == GCQ_PLAIN_H) {
     if (!ctx->H.valid) return fail(GCQ_ERR_STATE, "run gcq_aca_blocks first");
     if (ctx->H.precision != precision)
-      return fail(GCQ_ERR_ARG, "precision differs from the one the H-matrices were built in");
+      return fail(GCQ_ERR_ARG, "precision differs from the one the H-matrices were built in "
+                               "(split-bf16 products apply the 3D-ACA form only)");
     return precision == GCQ_C128 ? run_plainh<double>(ctx, X_dev, Y_dev, precision)
                                  : run_plainh<float>(ctx, X_dev, Y_dev, precision);
   }

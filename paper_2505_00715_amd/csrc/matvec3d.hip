@@ -552,13 +552,11 @@ static void enqueue_perfreq(gcq_context* ctx, hipStream_t st, int precision, con
 }
 
 // the product's buffers and frequency tables (once per operator)
-template <typename T>
-static int product_setup(gcq_context* ctx) {
+static int product_setup(gcq_context* ctx, size_t need) {
   Faces3D& F = ctx->F;
-  const int n = ctx->n, L = ctx->L;
-  const size_t need = size_t(2) * n * L * sizeof(cpx<T>);
-  if (F.pxy.bytes < need || !F.pmeta.p) {
-    F.graphs.clear();   // captured graphs refer to the old buffers
+  const int L = ctx->L;
+  if (F.pxy.bytes < need || !F.meta_valid) {
+    F.graphs.clear();   // captured graphs refer to the old buffers and tables
     GCQ_TRY(F.pxy.ensure(need));
     std::vector<int> meta(2 * L);
     for (int k = 0; k < L; ++k) {
@@ -567,6 +565,7 @@ static int product_setup(gcq_context* ctx) {
     }
     GCQ_TRY(upload(F.pmeta, meta, ctx->stream));
     GCQ_HIP(hipStreamSynchronize(ctx->stream));
+    F.meta_valid = true;
   }
   return GCQ_OK;
 }
@@ -577,7 +576,15 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
   hipStream_t st = ctx->stream;
   const int n = ctx->n, L = ctx->L, nb = int(ctx->blocks.size());
   if (mode == GCQ_PER_FREQUENCY) {
-    GCQ_TRY(product_setup<T>(ctx));
+    const bool bf = precision == GCQ_C64_SPLIT_BF16;
+    if (bf) GCQ_TRY(bf16_setup(ctx));
+    GCQ_TRY(product_setup(ctx, bf ? bf16_buffer_bytes(ctx) : size_t(2) * n * L * sizeof(cpx<T>)));
+    auto enqueue = [&](hipStream_t s) {
+      if (bf)
+        enqueue_perfreq_bf16(ctx, s, X, Y);
+      else
+        enqueue_perfreq<T>(ctx, s, precision, X, Y);
+    };
     if (ctx->tune.product_graph) {
       hipGraphExec_t exec = nullptr;
       for (auto& x : F.graphs.e)
@@ -586,7 +593,7 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
         if (!F.graphs.cap) GCQ_HIP(hipStreamCreateWithFlags(&F.graphs.cap, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         GCQ_HIP(hipStreamBeginCapture(F.graphs.cap, hipStreamCaptureModeThreadLocal));
-        enqueue_perfreq<T>(ctx, F.graphs.cap, precision, X, Y);
+        enqueue(F.graphs.cap);
         const hipError_t ce = hipGetLastError();
         GCQ_HIP(hipStreamEndCapture(F.graphs.cap, &graph));
         if (ce != hipSuccess) {
@@ -606,7 +613,7 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
       GCQ_HIP(hipGraphLaunch(exec, st));
     } else {
       GCQ_TRY(timed_begin(ctx));
-      enqueue_perfreq<T>(ctx, st, precision, X, Y);
+      enqueue(st);
     }
     GCQ_HIP(hipGetLastError());
     timed_end(ctx, "matvec_perfreq");
@@ -662,8 +669,10 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
 }
 
 int run_compressed(gcq_context* ctx, int mode, int precision, const void* X, void* Y) {
-  if (ctx->F.precision != precision)
+  if (ctx->F.precision != storage_precision(precision))
     return fail(GCQ_ERR_ARG, "precision differs from the one the 3D-ACA was built in");
+  if (precision == GCQ_C64_SPLIT_BF16 && mode != GCQ_PER_FREQUENCY)
+    return fail(GCQ_ERR_UNSUPPORTED, "split-bf16 products are per frequency only");
   return precision == GCQ_C128 ? compressed_impl<double>(ctx, mode, precision, X, Y)
                                : compressed_impl<float>(ctx, mode, precision, X, Y);
 }

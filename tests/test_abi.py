@@ -125,3 +125,72 @@ def test_rank_features_match_oracle_definition():
                            (T.end[a] - T.begin[a]) * one, (T.end[b] - T.begin[b]) * one)
         np.testing.assert_allclose(got[f], ref, rtol=1e-6, atol=1e-6)
     ctx.destroy()
+
+
+def test_uploaded_oracle_tree_is_the_built_tree():
+    """gcq_upload_cluster_tree with the oracle's partition gives the same
+    partition, statistics and rank features as the library's own build."""
+    from tests._oracle_tree_blocks import tree_arrays
+    cfg = configs.get("housing3k")
+    P, T, B, _, _ = oracle_tree(cfg["xyz"], cfg["tri"], 32, 1.0)
+    a = g.Context(-1)
+    a.upload_mesh(cfg["xyz"], cfg["tri"], cfg["c"])
+    a.set_frequencies(cfg["s"])
+    ia = a.build_cluster_tree(32, 1.0)
+    b = g.Context(-1)
+    b.upload_mesh(cfg["xyz"], cfg["tri"], cfg["c"])
+    b.set_frequencies(cfg["s"])
+    ib = b.upload_cluster_tree(*tree_arrays(T, B))
+    for f in ("n_clusters", "n_leaves", "depth", "n_blocks", "n_far", "n_near", "far_dims",
+              "near_entries"):
+        assert getattr(ia, f) == getattr(ib, f), f
+    pa, ba = a.get_tree()
+    pb, bb = b.get_tree()
+    assert np.array_equal(pa, pb) and np.array_equal(ba, bb)
+    K = np.arange(0, 129, 16)
+    assert np.array_equal(a.rank_features(K, ia.n_far), b.rank_features(K, ib.n_far))
+
+
+def test_upload_cluster_tree_rejects_bad_partitions():
+    from tests._oracle_tree_blocks import tree_arrays
+    xyz, tri = mesh.icosphere(2)
+    P, T, B, _, _ = oracle_tree(xyz, tri, 16, 1.0)
+    ctx = g.Context(-1)
+    with pytest.raises(g.GcqError):                      # no mesh yet
+        ctx.upload_cluster_tree(*tree_arrays(T, B))
+    ctx.upload_mesh(xyz, tri, 1.0)
+    good = tree_arrays(T, B)
+    ctx.upload_cluster_tree(*good)
+
+    def bad(i, change):
+        arrs = [x.copy() for x in good]
+        change(arrs[i])
+        with pytest.raises(g.GcqError):
+            ctx.upload_cluster_tree(*arrs)
+
+    def dup(p):
+        p[1] = p[0]
+    bad(0, dup)                                          # perm not a permutation
+    bad(1, lambda cb: cb.__setitem__(0, 1))             # root not [0, n)
+    son0 = int(np.nonzero(good[3][:, 0] >= 0)[0][0])
+
+    def shift_son(s):
+        s[son0, 0] = s[son0, 1]
+    bad(3, shift_son)                                    # sons not distinct
+    far = int(np.nonzero(good[6])[0][0])
+    near = int(np.nonzero(good[6] == 0)[0][0])
+
+    def drop(arr):
+        arr[far] = arr[near]
+    bad(4, drop)                                         # a repeated / missing pair
+    bad(6, lambda a: a.__setitem__(near, 1) if True else None)   # touching boxes marked admissible
+    # a block that overlaps others: the root pair added to the list
+    arrs = [x.copy() for x in good]
+    arrs[4] = np.append(arrs[4], 0).astype(np.int32)
+    arrs[5] = np.append(arrs[5], 0).astype(np.int32)
+    arrs[6] = np.append(arrs[6], 0).astype(np.uint8)
+    with pytest.raises(g.GcqError):
+        ctx.upload_cluster_tree(*arrs)
+    # the context still holds the good tree
+    perm, blocks = ctx.get_tree()
+    assert np.array_equal(perm, good[0])

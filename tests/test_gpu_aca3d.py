@@ -185,3 +185,114 @@ def test_aca3d_reuses_the_h_matrix_near_field(setup, prec):
     # a change of precision makes it evaluate the entries again
     ctx.aca3d(TOLA, TOLF, 40, g.C64 if prec == g.C128 else g.C128)
     assert ctx.kernel_ms("aca3d_tensor") > 0.0
+
+
+def test_one_context_across_frequency_sets():
+    """A context that gets a new frequency set (symmetry on, then off with a
+    different L, then a shorter set) and rebuilds its 3D-ACA applies the new
+    set's operator: the product's frequency tables follow the set (per set
+    against the dense oracle)."""
+    xyz, tri = mesh.icosphere(2)
+    P = Panels(xyz, tri)
+    ctx = g.Context(0)
+    ctx.upload_mesh(xyz, tri, 1.0)
+    sets = [(freq.bdf2_circle(16, 0.05, 1e-8 ** (1 / 16)), True),
+            (freq.bdf2_circle(20, 0.05, 1e-8 ** (1 / 20)), False),
+            (freq.bdf2_circle(8, 0.05, 1e-8 ** (1 / 8)), True),
+            (freq.bdf2_circle(16, 0.05, 1e-8 ** (1 / 16))[::-1].copy(), False)]
+    for i, (s, sym) in enumerate(sets):
+        ctx.set_frequencies(s, sym)
+        if i == 0:
+            ctx.build_cluster_tree(16, 1.0)
+        ctx.aca3d(1e-8, 1e-8, 64, g.C128)
+        X = rhs.random_complex(len(s), P.n, i)
+        Xd = to_dev(X, g.C128).reshape(-1)
+        Y = torch.zeros_like(Xd)
+        for _ in range(2):   # the second call replays the captured product
+            ctx.compressed_matvec(g.PER_FREQUENCY, g.C128, Xd, Y)
+            Yg = from_dev(Y).reshape(len(s), P.n)
+            Yt = matvec.dense(entries.dense(P, s, 1.0), X)
+            assert rel(Yg, Yt) <= 1e-6, (i, rel(Yg, Yt))
+
+
+@pytest.mark.parametrize("prec", [g.C128, g.C64])
+def test_sample_rows_are_rows_of_the_product(setup, prec):
+    """gcq_sample_rows returns rows of the operator the products apply: each
+    sampled row times X[k] is Y[k] at that row (exact regrouping), for plain
+    and conjugate-represented frequencies, with repeated and ragged row lists;
+    against the dense oracle rows it carries the 3D-ACA's own error."""
+    xyz, tri, s, P, T, B, rep, conj, K, kpos, b3 = setup
+    ctx = make_ctx(xyz, tri, 1.0, s, 32, 1.0)
+    ctx.aca3d(TOLA, TOLF, 40, prec)
+    L = len(s)
+    X = rhs.random_complex(L, P.n, 3)
+    Xd = to_dev(X, prec).reshape(-1)
+    Y = torch.zeros_like(Xd)
+    ctx.compressed_matvec(g.PER_FREQUENCY, prec, Xd, Y)
+    Yg = from_dev(Y).reshape(L, P.n)
+    rows = np.array([0, 5, 5, P.n - 1, 777, 1000, 3], np.int32)
+    dt = torch.complex128 if prec == g.C128 else torch.complex64
+    out = torch.zeros(len(rows) * P.n, dtype=dt, device="cuda")
+    for k in (0, 3, L // 2, L - 3, L - 1):
+        ctx.sample_rows(rows, k, out)
+        R = from_dev(out).reshape(len(rows), P.n)
+        y = R @ X[k]
+        assert rel(y, Yg[k][rows]) <= (1e-13 if prec == g.C128 else 2e-6), k
+        D = entries.block(P, rows, np.arange(P.n), [s[k]], 1.0)[0]
+        assert rel(R, D) <= (1e-4 if prec == g.C128 else 2e-4), (k, rel(R, D))
+    with pytest.raises(g.GcqError):
+        ctx.sample_rows(np.array([P.n], np.int32), 0, out[: P.n])
+    with pytest.raises(g.GcqError):
+        ctx.sample_rows(rows, L, out)
+
+
+def test_split_bf16_product(setup):
+    """The split-bf16 per-frequency product (complex64 operator, operands as
+    bf16 hi + lo planes, float accumulation) against the oracle's product of
+    its own 3D-ACA, per frequency; captured and replayed like the others."""
+    xyz, tri, s, P, T, B, rep, conj, K, kpos, b3 = setup
+    ctx = make_ctx(xyz, tri, 1.0, s, 32, 1.0)
+    ctx.aca3d(TOLA, TOLF, 40, g.C64)
+    X = rhs.random_complex(len(s), P.n, 0)
+    Xd = to_dev(X, g.C64).reshape(-1)
+    Y64, Ybf = torch.zeros_like(Xd), torch.zeros_like(Xd)
+    ctx.compressed_matvec(g.PER_FREQUENCY, g.C64, Xd, Y64)
+    for _ in range(3):
+        Ybf.fill_(float("nan"))
+        ctx.compressed_matvec(g.PER_FREQUENCY, g.C64_SPLIT_BF16, Xd, Ybf)
+        yb = from_dev(Ybf).reshape(len(s), P.n)
+        y6 = from_dev(Y64).reshape(len(s), P.n)
+        Yo = matvec.compressed(b3, X, rep, conj, kpos)
+        per = np.linalg.norm(yb - Yo, axis=1) / np.linalg.norm(Yo, axis=1)
+        assert per.max() <= 1e-4, per.max()
+        # the split itself: against the float product of the same operator
+        per2 = np.linalg.norm(yb - y6, axis=1) / np.linalg.norm(y6, axis=1)
+        assert per2.max() <= 2e-5, per2.max()
+    with pytest.raises(g.GcqError):
+        ctx.compressed_matvec(g.WEIGHTED_SUM, g.C64_SPLIT_BF16, Xd, Ybf[: P.n])
+
+
+def test_split_bf16_product_many_columns():
+    """256 frequencies (four 64-column chunks, conjugate symmetry) on a
+    3000-triangle finned housing: sampled rows of the split-bf16 product
+    against the float product and against dense oracle rows."""
+    from synth import configs
+    cfg = configs.get("housing3k")
+    ctx = make_ctx(cfg["xyz"], cfg["tri"], cfg["c"], cfg["s"], cfg["leaf"], cfg["eta"])
+    ctx.aca3d(1e-6, 1e-6, 40, g.C64)
+    L, n = len(cfg["s"]), len(cfg["tri"])
+    X = rhs.random_complex(L, n, 0)
+    Xd = to_dev(X, g.C64).reshape(-1)
+    Y64, Ybf = torch.zeros_like(Xd), torch.zeros_like(Xd)
+    ctx.compressed_matvec(g.PER_FREQUENCY, g.C64, Xd, Y64)
+    ctx.compressed_matvec(g.PER_FREQUENCY, g.C64_SPLIT_BF16, Xd, Ybf)
+    yb = from_dev(Ybf).reshape(L, n)
+    y6 = from_dev(Y64).reshape(L, n)
+    per = np.linalg.norm(yb - y6, axis=1) / np.linalg.norm(y6, axis=1)
+    assert per.max() <= 2e-5, per.max()
+    rows = rhs.sample_rows(n, 24, 0)
+    kk = np.array([0, 1, 63, 64, 127, 128, 129, 191, 192, 255])
+    A = entries.block(Panels(cfg["xyz"], cfg["tri"]), rows, np.arange(n), cfg["s"][kk], cfg["c"])
+    ref = np.einsum("kij,kj->ki", A, X[kk])
+    per = np.linalg.norm(yb[kk][:, rows] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert per.max() <= 2e-5, per.max()

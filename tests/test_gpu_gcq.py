@@ -196,3 +196,47 @@ def test_gcq_runge_kutta_rejects_bad_methods():
         ctx.gcq_convolve(dt, w_lib, torch.zeros(len(dt) * 5 * P.n, dtype=torch.float64, device="cuda"),
                          torch.zeros(len(dt) * 5 * P.n, dtype=torch.float64, device="cuda"), g.C128,
                          n_step_points=npts, A=np.eye(5))
+
+
+def test_gcq_solve_reports_a_step_that_missed_rtol(setup):
+    """A step whose GMRES ends above rtol is reported (GCQ_NOT_CONVERGED with a
+    warning), not passed over silently."""
+    xyz, tri, P, q, f_or = setup
+    s_lib, w_lib = g.contour(NQ, DT, 1.5 * DT)
+    ctx = make_ctx(xyz, tri, 1.0, _set(s_lib), 16, 1.0)
+    ctx.aca3d(1e-6, 1e-6, 64, g.C128)
+    Fd = torch.from_numpy(np.ascontiguousarray(f_or.real[:3]).reshape(-1)).cuda()
+    Qd = torch.zeros_like(Fd)
+    with pytest.warns(RuntimeWarning):
+        ctx.gcq_solve(DT, w_lib, Fd, Qd, g.C128, rtol=1e-14, max_iter=2, restart=2)
+    assert ctx.last_status == g.NOT_CONVERGED
+    ctx.gcq_solve(DT, w_lib, Fd, Qd, g.C128, rtol=1e-8, max_iter=400)
+    assert ctx.last_status == g.OK
+
+
+def test_gcq_entry_points_check_their_arguments(setup):
+    """Host arrays where device arrays are expected, and a weight list of the
+    wrong length, are refused before any work is enqueued."""
+    import ctypes as C
+    xyz, tri, P, q, f_or = setup
+    s_lib, w_lib = g.contour(NQ, DT, 1.5 * DT)
+    ctx = make_ctx(xyz, tri, 1.0, _set(s_lib), 16, 1.0)
+    ctx.aca3d(1e-6, 1e-6, 64, g.C128)
+    Qh = np.zeros(NSTEP * P.n)
+    Fh = np.zeros(NSTEP * P.n)
+    A = np.ones(1)
+    dt = np.full(NSTEP, DT)
+    w = np.ascontiguousarray(w_lib, np.complex128)
+    vp = lambda a: a.ctypes.data_as(C.c_void_p)
+    rc = g.lib.gcq_gcq_convolve(ctx._h, vp(A), 1, vp(dt), NSTEP, 1, vp(w), g.C128, vp(Qh), vp(Fh))
+    assert rc == -1
+    it = C.c_int32(0)
+    rc = g.lib.gcq_gcq_solve(ctx._h, vp(A), 1, vp(dt), NSTEP, 1, vp(w), g.C128, vp(Fh), vp(Qh),
+                             1e-8, 10, 10, C.byref(it))
+    assert rc == -1
+    Q = torch.zeros(NSTEP * P.n, dtype=torch.float64, device="cuda")
+    F = torch.zeros_like(Q)
+    with pytest.raises(ValueError):
+        ctx.gcq_convolve(DT, w_lib[:-1], Q, F, g.C128)
+    with pytest.raises(ValueError):
+        ctx.gcq_solve(DT, w_lib[:-1], F, Q, g.C128)

@@ -15,12 +15,13 @@ from tests._gpu_common import from_dev, kpos_map, make_ctx, rel, to_dev
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("prec,rtol", [(g.C128, 1e-9), (g.C64, 1e-6)])
+@pytest.mark.parametrize("prec,rtol", [(g.C128, 1e-9), (g.C64, 1e-6), (g.C64_SPLIT_BF16, 1e-6)])
 def test_gmres_all_frequencies(prec, rtol):
     xyz, tri = mesh.icosphere(2)
     s = freq.bdf2_circle(8, 0.05, 1e-8 ** (1 / 8))
     ctx = make_ctx(xyz, tri, 1.0, s, 16, 1.0)
-    ctx.aca3d(1e-10, 1e-10, 40, prec)
+    # split-bf16 products apply an operator built in complex64
+    ctx.aca3d(1e-10, 1e-10, 40, g.C64 if prec == g.C64_SPLIT_BF16 else prec)
     Bh = rhs.random_complex(len(s), 320, 1)
     B = to_dev(Bh, g.C128).reshape(-1)
     X = torch.zeros_like(B)
@@ -34,7 +35,12 @@ def test_gmres_all_frequencies(prec, rtol):
         # 3D-ACA tolerance 1e-10 and the GMRES tolerance bound the difference
         assert rel(x[k], xs) <= 1e3 * max(rtol, 1e-10) * 10
         res = np.linalg.norm(A[k] @ x[k] - Bh[k]) / np.linalg.norm(Bh[k])
-        assert res <= 2 * rtol + 1e-8
+        # split-bf16 solves with the operator's two-plane copy, a fixed relative
+        # perturbation of at most 2^-18 per entry: its residual against A holds
+        # that perturbation times |A| |x| / |b| on top of rtol
+        pert = 0.0 if prec != g.C64_SPLIT_BF16 else \
+            2.0 ** -18 * np.linalg.norm(np.abs(A[k]), 2) * np.linalg.norm(x[k]) / np.linalg.norm(Bh[k])
+        assert res <= 2 * rtol + 1e-8 + pert, (res, pert)
 
 
 def test_gmres_not_converged_flag():
@@ -72,13 +78,15 @@ def test_mlp_forward_backward_vs_oracle():
 
 
 def test_mlp_training_reduces_loss():
+    # 100 epochs: the float64 oracle's own Adam training on these samples ends
+    # at 0.115-0.144 var(t) after 40 epochs (seeds 0-2), at 0.020-0.030 after 100
     ctx = g.Context(0)
     X, t = _samples(4096, 5)
-    st = ctx.rank_model_train(X.astype(np.float32), t.astype(np.float32), epochs=40, batch=256,
+    st = ctx.rank_model_train(X.astype(np.float32), t.astype(np.float32), epochs=100, batch=256,
                               lr=3e-3)
     assert st.loss_last < 0.2 * st.loss_first
     pred = ctx.rank_model_predict(X.astype(np.float32))
-    assert np.mean((pred - t) ** 2) < 0.2 * np.var(t)
+    assert np.mean((pred - t) ** 2) < 0.1 * np.var(t) + 1e-3
 
 
 def test_predictor_ablation_same_result():
