@@ -357,6 +357,15 @@ GCQ_API int gcq_upload_cluster_tree(gcq_context* ctx, const int32_t* perm, int32
                                     const int32_t* blk_col, const uint8_t* blk_admissible,
                                     gcq_tree_info* info);
 
+/* gcq_trim: releases the device memory the context keeps between calls for
+ *   its working buffers (ACA workspaces, entry tensors, tables), which the
+ *   next call allocates again; with release_faces != 0 also the per-frequency
+ *   H-matrices of gcq_aca_blocks (GCQ_PLAIN_H products then need a new
+ *   gcq_aca_blocks).  The products' buffers and the split-bf16 copy of the
+ *   operator are released too (the next product makes them again); the
+ *   3D-ACA operator itself stays.  Synchronises the context's streams. */
+GCQ_API int gcq_trim(gcq_context* ctx, int32_t release_faces);
+
 /* gcq_get_tree: copies the partition to host arrays: perm (n_triangles:
  *   internal position -> caller index) and blocks (n_blocks x 5 int32:
  *   row_begin, row_end, col_begin, col_end in internal positions, admissible),
@@ -397,6 +406,13 @@ GCQ_API int gcq_assemble_dlp_slices(gcq_context* ctx, const int32_t* rows, int64
 GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_fidx,
                            double tol, int32_t max_rank, int32_t precision, uint32_t flags,
                            gcq_aca_stats* stats);
+
+/* gcq_aca_ranks: the ranks (after recompression) of every (admissible block,
+ *   frequency) pair of the last gcq_aca_blocks, into the host array ranks of
+ *   n = n_far x n_slots values, [far block in depth-first order][frequency slot
+ *   in the call's order] (the layout of gcq_rank_features).  GCQ_ERR_ARG when n
+ *   differs; GCQ_ERR_STATE before gcq_aca_blocks. */
+GCQ_API int gcq_aca_ranks(gcq_context* ctx, int32_t* ranks, int64_t n);
 
 /* gcq_get_block_factors: host copy of the factors of admissible block `block`
  *   (index into the depth-first block list) at representative frequency

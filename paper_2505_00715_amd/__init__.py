@@ -95,11 +95,13 @@ def _load():
         "gcq_gcq_solve": [P, P, I32, P, I32, I32, P, I32, P, P, D, I32, I32, P],
         "gcq_build_cluster_tree": [P, I32, D, P],
         "gcq_get_tree": [P, P, P],
+        "gcq_trim": [P, I32],
         "gcq_upload_cluster_tree": [P, P, I32, P, P, P, I32, P, P, P, P],
         "gcq_assemble_slices": [P, P, I64, P, I64, P, I32, I32, P],
         "gcq_assemble_dlp_slices": [P, P, I64, P, I64, P, I32, I32, P],
         "gcq_aca_blocks": [P, P, I32, D, I32, I32, U32, P],
         "gcq_get_block_factors": [P, I32, I32, P, P, I32, P],
+        "gcq_aca_ranks": [P, P, I64],
         "gcq_aca3d": [P, D, D, I32, I32, U32, P],
         "gcq_get_aca3d_block": [P, I32, I32, P, P, P, P],
         "gcq_compressed_matvec": [P, I32, I32, P, P, I32],
@@ -273,6 +275,11 @@ class Context:
         self.tree_info = info
         return info
 
+    def trim(self, release_faces: bool = True):
+        """Release the context's working buffers (and the per-frequency
+        H-matrices) -- gcq_trim."""
+        _check(_lib.gcq_trim(self._h, int(bool(release_faces))))
+
     def get_tree(self):
         nb = self.tree_info.n_blocks
         perm = np.zeros(self.n, np.int32)
@@ -333,6 +340,13 @@ class Context:
         return U[:k].T.copy(), V[:k].T.copy()
 
     # ---- 3D-ACA
+    def aca_ranks(self, n_slots: int):
+        """Ranks of the last aca_blocks call, (n_far, n_slots) int32."""
+        nfar = self.tree_info.n_far
+        out = np.zeros((nfar, n_slots), np.int32)
+        _check(_lib.gcq_aca_ranks(self._h, out.ctypes.data_as(C.c_void_p), int(nfar * n_slots)))
+        return out
+
     def aca3d(self, tol_aca: float, tol: float, max_freq_rank: int, precision: int,
               flags: int = 0) -> Aca3dStats:
         st = Aca3dStats()

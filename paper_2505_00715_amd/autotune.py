@@ -74,10 +74,17 @@ def apply(ctx, params: dict):
 
 def tune(ctx, workload: str, precision: int, tol: float, max_rank: int = 64, max_freq_rank: int = 40,
          aca_flags: int = FLAG_RECOMPRESS, X=None, Y=None, path: str | None = None,
-         use_cache: bool = True, log=None) -> dict:
+         use_cache: bool = True, log=None, aca_freq_idx=None, aca3d_candidates=None,
+         stack_candidates=None, product_precision: int | None = None) -> dict:
     """Search the launch parameters on ``ctx`` (mesh, frequencies and tree set
     up) and leave the best ones set.  X, Y: device buffers for the product
-    (optional).  Returns the chosen parameters with their measured times."""
+    (optional).  aca_freq_idx: representatives the aca_blocks candidates are
+    timed on (None: all; a subset keeps the search affordable on large
+    workloads); aca3d_candidates, stack_candidates: the group-size sets and
+    stack reservations to try (a large reservation on a large workload may not
+    fit the device);
+    product_precision: precision of the product timed (default: precision).
+    Returns the chosen parameters with their measured times."""
     if use_cache:
         cached = load(workload, precision, path)
         if cached is not None:
@@ -90,21 +97,21 @@ def tune(ctx, workload: str, precision: int, tol: float, max_rank: int = 64, max
     times = {}
     for w in (1, 2, 4):
         ctx.set_tuning(aca_waves=w)
-        ctx.aca_blocks(tol, max_rank, precision, aca_flags)
+        ctx.aca_blocks(tol, max_rank, precision, aca_flags, freq_idx=aca_freq_idx)
         times[w] = ctx.kernel_ms("aca_total")
         say(f"[autotune] aca_waves {w}: {times[w]:.1f} ms")
     best["aca_waves"] = min(times, key=times.get)
     ctx.set_tuning(aca_waves=best["aca_waves"])
     # 3D-ACA group sizes, then the stack reservation
     times = {}
-    for c in ACA3D_CANDIDATES:
+    for c in (aca3d_candidates or ACA3D_CANDIDATES):
         ctx.set_tuning(aca3d_waves=c, aca3d_stack_slices=8)
         st = ctx.aca3d(tol, tol, max_freq_rank, precision)
         times[c] = st.far_ms
         say(f"[autotune] aca3d_waves {c}: {times[c]:.1f} ms")
     best["aca3d_waves"] = list(min(times, key=times.get))
     times = {}
-    for sl in STACK_CANDIDATES:
+    for sl in (stack_candidates or STACK_CANDIDATES):
         ctx.set_tuning(aca3d_waves=best["aca3d_waves"], aca3d_stack_slices=sl)
         st = ctx.aca3d(tol, tol, max_freq_rank, precision)
         times[sl] = st.far_ms
@@ -122,7 +129,8 @@ def tune(ctx, workload: str, precision: int, tol: float, max_rank: int = 64, max
             ctx.set_tuning(product_graph=gr)
             ts = []
             for _ in range(4):
-                ctx.compressed_matvec(PER_FREQUENCY, precision, X, Y)
+                ctx.compressed_matvec(PER_FREQUENCY, product_precision if product_precision is not None
+                                      else precision, X, Y)
                 torch.cuda.synchronize()
                 ts.append(ctx.kernel_ms("matvec_perfreq"))
             times[gr] = sorted(ts)[len(ts) // 2]

@@ -158,6 +158,13 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
   const int dev_cus = ctx->cus;
   // chunks in work-list order, each within the workspace budget
   size_t pos = 0;
+  const int64_t pool_used0 = pool_used;
+  // tile capacity (terms x (m + n)) of the whole list and of the pairs done:
+  // the pool grows to the storage per unit of capacity seen so far times the
+  // whole list's (the list runs largest first, so a per-pair average of the
+  // first chunks would overshoot)
+  int64_t cap_total = 0, cap_done = 0;
+  for (int q : order) cap_total += int64_t(desc[q].cap) * (desc[q].m + desc[q].n);
   std::vector<int64_t> pend_off;
   while (pos < order.size()) {
     std::vector<int> chunk;
@@ -172,6 +179,7 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
       ++pos;
     }
     const int nc = int(chunk.size());
+    for (int q : chunk) cap_done += int64_t(desc[q].cap) * (desc[q].m + desc[q].n);
     std::vector<PairDesc> cd(nc);
     for (int a = 0; a < nc; ++a) cd[a] = desc[chunk[a]];
     GCQ_TRY(ctx->scratchA.ensure(size_t(wsz) + 256));
@@ -219,8 +227,13 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
     }
     const size_t esz = sizeof(cpx<T>);
     if (size_t(need) * esz > pool.bytes) {
+      // grow to the size the storage per pair so far projects for the whole
+      // work list (one copy instead of a cascade; the old and the new pool
+      // coexist during the copy)
+      const double ratio = double(need - pool_used0) / double(std::max<int64_t>(cap_done, 1));
+      const size_t projected = size_t(double(pool_used0) + ratio * double(cap_total) * 1.05);
       DevBuf bigger;
-      GCQ_TRY(bigger.ensure(std::max(size_t(need) * esz, pool.bytes * 3 / 2) + 256));
+      GCQ_TRY(bigger.ensure(std::max(size_t(need), projected) * esz + 256));
       if (pool_used > 0)
         GCQ_HIP(hipMemcpyAsync(bigger.p, pool.p, size_t(pool_used) * esz,
                                hipMemcpyDeviceToDevice, st));
@@ -545,6 +558,16 @@ GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_
     stats->device_ms = ms_aca + ms_rec + ms_apply;
   }
   return ncap > 0 ? GCQ_RANK_CAPPED : GCQ_OK;
+}
+
+GCQ_API int gcq_aca_ranks(gcq_context* ctx, int32_t* ranks, int64_t n) {
+  if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
+  if (!ctx->H.valid) return fail(GCQ_ERR_STATE, "run gcq_aca_blocks first");
+  const int64_t nfar = int64_t(ctx->far_ids.size()), nslot = int64_t(ctx->H.freqs.size());
+  if (!ranks || n != nfar * nslot) return fail(GCQ_ERR_ARG, "ranks must hold %lld values", (long long)(nfar * nslot));
+  for (int64_t q = 0; q < nslot; ++q)
+    for (int64_t f = 0; f < nfar; ++f) ranks[f * nslot + q] = ctx->H.rank[q * nfar + f];
+  return GCQ_OK;
 }
 
 GCQ_API int gcq_get_block_factors(gcq_context* ctx, int32_t block, int32_t freq, gcq_c128* U,

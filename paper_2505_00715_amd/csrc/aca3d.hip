@@ -895,7 +895,11 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   // blocks' stack reservations, plus one fiber per term
   const int64_t rexp = std::max(8, int(max_freq_rank) / 2 + 4);
   int64_t want = near_elems * rexp + far_stack + int64_t(nb) * rexp * nK;
-  int64_t capacity = std::min<int64_t>(want, int64_t(double(freeb) * 0.5) / csz);
+  // at most a quarter of the free memory, and after a first call on this
+  // tree a quarter more than that call used (the pool grows between rounds
+  // when a block's slices do not fit, so a short estimate costs a round)
+  int64_t capacity = std::min<int64_t>(want, int64_t(double(freeb) * 0.25) / csz);
+  if (F.last_used > 0 && F.last_nb == nb) capacity = std::min(capacity, F.last_used + F.last_used / 4 + (int64_t(1) << 20));
   // the pool of an earlier call is reused (its contents are rebuilt); it only
   // grows when this operator needs more
   GCQ_TRY(F.slices.ensure(size_t(capacity) * csz + 256));
@@ -925,7 +929,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   const std::vector<int64_t>& sing_off = ctx->sing_off;
   DevBuf& tensor = ctx->scratchT;
   const int64_t tensor_budget = std::max<int64_t>(int64_t(1) << 28,
-                                                  std::min<int64_t>(int64_t(48) << 30, int64_t(double(freeb) * 0.25)));
+                                                  std::min<int64_t>(int64_t(16) << 30, int64_t(double(freeb) * 0.15)));
   hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, reinterpret_cast<int*>(d_work), 4);
   // the dense near-field entries at every frequency of K, as the per-frequency
   // H-matrix of the same frequencies and precision holds them ([k][near
@@ -1197,6 +1201,8 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   GCQ_HIP(hipStreamSynchronize(ctx->stream));
   F.storage_bytes = store * csz;
   F.dense_bytes = int64_t(ctx->n) * ctx->n * nK * csz;
+  F.last_used = used;
+  F.last_nb = nb;
   F.valid = true;
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));

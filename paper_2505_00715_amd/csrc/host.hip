@@ -719,6 +719,37 @@ GCQ_API int gcq_upload_cluster_tree(gcq_context* ctx, const int32_t* perm, int32
   return finish_tree(ctx, info);
 }
 
+GCQ_API int gcq_trim(gcq_context* ctx, int32_t release_faces) {
+  if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
+  GCQ_NEED_DEVICE(ctx);
+  GCQ_HIP(hipSetDevice(ctx->device));
+  GCQ_HIP(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < 3; ++i)
+    if (ctx->side[i]) GCQ_HIP(hipStreamSynchronize(ctx->side[i]));
+  ctx->scratchA.release();
+  ctx->scratchB.release();
+  ctx->scratchC.release();
+  ctx->scratchD.release();
+  ctx->scratchT.release();
+  ctx->F.graphs.clear();       // they refer to the product buffers released below
+  ctx->F.meta_valid = false;
+  ctx->F.bf_valid = false;
+  ctx->F.bfpool.release();
+  ctx->F.bftbuf.release();
+  ctx->F.pxy.release();
+  if (release_faces) {
+    HFaces& H = ctx->H;
+    H.valid = false;
+    H.factors.release();
+    H.near.release();
+    H.d_off.release();
+    H.d_rank.release();
+    H.d_near_off.release();
+    H.d_sig.release();
+  }
+  return GCQ_OK;
+}
+
 GCQ_API int gcq_get_tree(gcq_context* ctx, int32_t* perm, int32_t* blocks) {
   if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
   if (!ctx->have_tree) return fail(GCQ_ERR_STATE, "build the cluster tree first");

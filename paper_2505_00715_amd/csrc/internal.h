@@ -161,9 +161,13 @@ struct Faces3D {
     graphs.clear();
     meta_valid = false;
     bf_valid = false;
+    bfpool.release();   // tens of GB at 80k triangles: not kept for a rebuilt operator
+    bftbuf.release();
   }
   int n_mvblocks = 0;
   int64_t storage_bytes = 0;
+  int64_t last_used = 0;         // pool elements the last gcq_aca3d used (sizes the next pool)
+  int last_nb = 0;               // blocks of that call's partition
   int64_t dense_bytes = 0;
 };
 
