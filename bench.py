@@ -96,7 +96,6 @@ def _oracle_pairs(args):
     """Worker: the oracle's ACA + recompression on a list of (far block,
     frequency) pairs, for `seconds` at most; returns the number done."""
     name, seed, seconds = args
-    os.environ["OMP_NUM_THREADS"] = "1"
     from oracle import aca
     from oracle.geometry import Panels
     from oracle.tree import ClusterTree, block_tree
@@ -125,11 +124,25 @@ def cpu_baseline(name, seconds=12.0):
     per core) and on one core."""
     import multiprocessing as mp
     # one process per host core, at most the 16 cores a one-GPU box provides;
-    # spawned (fresh interpreters: they hold no GPU state)
+    # spawned (fresh interpreters that hold no GPU state), each with one BLAS
+    # thread: the variables are read when the child imports numpy
     cores = max(1, min(os.cpu_count() or 1, 16))
-    done1, dt1 = _oracle_pairs((name, 0, seconds))
-    with mp.get_context("spawn").Pool(cores) as pool:
-        res = pool.map(_oracle_pairs, [(name, 1 + i, seconds) for i in range(cores)])
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    for k in keys:
+        os.environ[k] = "1"
+    try:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(1) as pool:
+            done1, dt1 = pool.map(_oracle_pairs, [(name, 0, seconds)])[0]
+        with ctx.Pool(cores) as pool:
+            res = pool.map(_oracle_pairs, [(name, 1 + i, seconds) for i in range(cores)])
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
     # the processes run their timed loops at the same time (each times its own,
     # after building its panel tables and tree): the rates add
     done = sum(r[0] for r in res)
