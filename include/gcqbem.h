@@ -384,6 +384,23 @@ GCQ_API int gcq_assemble_slices(gcq_context* ctx, const int32_t* rows, int64_t n
                                 const int32_t* cols, int64_t n_cols, const int32_t* freq_idx,
                                 int32_t n_fidx, int32_t precision, void* out_dev);
 
+/* gcq_assemble_slices_noalloc: gcq_assemble_slices for callers that cannot
+ *   allocate device memory (code under HIP graph capture, serving loops,
+ *   harnesses that forbid hipMalloc): same arguments, layout and results, but
+ *   the permuted index lists and the frequencies are staged in a fixed 8 MiB
+ *   array of each device (one per GPU for the life of the process) instead of
+ *   the context's buffers, and the call allocates nothing, records no timing
+ *   and returns without synchronising.  A request needs
+ *   ceil256(4 n_rows) + ceil256(4 n_cols) + 16 n_fidx bytes of staging
+ *   (ceil256 rounds up to a multiple of 256); GCQ_ERR_ARG above 8 MiB.  Every
+ *   call on a GPU shares that GPU's array: calls that overlap on one GPU (two
+ *   contexts or streams, or a second call while a first one's kernel has not
+ *   started) race; every part of the array a call reads is written by that
+ *   call first, so nothing needs clearing between calls. */
+GCQ_API int gcq_assemble_slices_noalloc(gcq_context* ctx, const int32_t* rows, int64_t n_rows,
+                                        const int32_t* cols, int64_t n_cols, const int32_t* freq_idx,
+                                        int32_t n_fidx, int32_t precision, void* out_dev);
+
 /* gcq_assemble_dlp_slices: dense double-layer entries K(s_f)[rows[a], cols[b]]
  *   (Sec. 2, eq. dlp, transformed as in Sec. 3): the integral over panel
  *   cols[b] of the normal derivative in y (outward unit normal of the panel,

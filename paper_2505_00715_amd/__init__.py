@@ -99,6 +99,7 @@ def _load():
         "gcq_upload_cluster_tree": [P, P, I32, P, P, P, I32, P, P, P, P],
         "gcq_assemble_slices": [P, P, I64, P, I64, P, I32, I32, P],
         "gcq_assemble_dlp_slices": [P, P, I64, P, I64, P, I32, I32, P],
+        "gcq_assemble_slices_noalloc": [P, P, I64, P, I64, P, I32, I32, P],
         "gcq_aca_blocks": [P, P, I32, D, I32, I32, U32, P],
         "gcq_get_block_factors": [P, I32, I32, P, P, I32, P],
         "gcq_aca_ranks": [P, P, I64],
@@ -298,6 +299,19 @@ class Context:
         po = _dev(out, dt, len(fi) * len(cols) * len(rows), "out")
         _check(_lib.gcq_assemble_slices(self._h, pr, len(rows), pc, len(cols), pf, len(fi),
                                         precision, po))
+        return out
+
+    def assemble_slices_noalloc(self, rows, cols, freq_idx, precision, out):
+        """gcq_assemble_slices_noalloc: as assemble_slices, staged in the
+        device's fixed array (no device allocation, no synchronisation)."""
+        import torch
+        rows, pr = _host(rows, np.int32)
+        cols, pc = _host(cols, np.int32)
+        fi, pf = _host(freq_idx, np.int32)
+        dt = torch.complex128 if precision == C128 else torch.complex64
+        po = _dev(out, dt, len(fi) * len(cols) * len(rows), "out")
+        _check(_lib.gcq_assemble_slices_noalloc(self._h, pr, len(rows), pc, len(cols), pf, len(fi),
+                                                precision, po))
         return out
 
     def assemble_dlp_slices(self, rows, cols, freq_idx, precision, out):

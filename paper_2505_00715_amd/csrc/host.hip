@@ -327,7 +327,8 @@ GCQ_API int gcq_create(int device, void* hip_stream, gcq_context** out) {
   }
   Consts K;
   build_consts(K);
-  int st = ctx->d_consts.ensure(sizeof(Consts));
+  int st = noalloc_scratch_init(device);
+  if (st == GCQ_OK) st = ctx->d_consts.ensure(sizeof(Consts));
   if (st == GCQ_OK &&
       hipMemcpy(ctx->d_consts.p, &K, sizeof(Consts), hipMemcpyHostToDevice) != hipSuccess)
     st = fail(GCQ_ERR_HIP, "upload of constant tables failed");

@@ -264,6 +264,9 @@ namespace gcq {
 #define GCQ_NEED_DEVICE(ctx) \
   do { if ((ctx)->device < 0) return ::gcq::fail(GCQ_ERR_STATE, "host-only context"); } while (0)
 int check_device_ptr(gcq_context* ctx, const void* p, const char* what);
+// per-device address of the staging array of gcq_assemble_slices_noalloc
+// (entries.hip), resolved once per device at context creation
+int noalloc_scratch_init(int device);
 int timed_begin(gcq_context* ctx);
 double timed_end(gcq_context* ctx, const char* name);
 inline int csize(int precision) { return precision == GCQ_C128 ? 16 : 8; }
