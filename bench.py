@@ -54,8 +54,8 @@ WORKLOADS = {
                        "{L} BDF2-circle frequencies (N 128, dt 1e-4 s; {nK} distinct)"),
     "housing40k": dict(tol=3e-6, chunk=43, desc="finned housing, {n} triangles, c 343 m/s, leaf 64, eta 1, "
                        "ACA/3D-ACA tol 3e-6, {L} BDF2-circle frequencies ({nK} distinct)"),
-    "sphere20480": dict(tol=1e-5, chunk=33, desc="icosphere subdivision 5 ({n} triangles), c 1, leaf 64, "
-                        "eta 1, ACA/3D-ACA tol 1e-5, {L} BDF2-circle frequencies ({nK} distinct)"),
+    "sphere20480": dict(tol=3e-6, chunk=33, desc="icosphere subdivision 5 ({n} triangles), c 1, leaf 64, "
+                        "eta 1, ACA/3D-ACA tol 3e-6, {L} BDF2-circle frequencies ({nK} distinct)"),
 }
 
 
