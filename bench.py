@@ -47,6 +47,37 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0
 # 3 sub + 3 fma (r^2) + sqrt + 2 mul + exp + sin + cos + rcp + 2 mul + 2 fma (accumulate)
 OPS_PER_QPOINT = 20
 PROFILE_DIR = os.path.join(ROOT, "profiles")
+# HBM traffic of the split-bf16 product (its kernels bf_tfill + bf_rows per
+# product) from rocprofv3 FETCH_SIZE / WRITE_SIZE counters calibrated against a
+# copy kernel, valid for the sources it was measured on
+TRAFFIC_FILE = os.path.join(PROFILE_DIR, "product_split_bf16_housing40k_traffic.txt")
+KERNEL_SOURCES = ["matvec_bf16.hip", "matvec3d.hip", "internal.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2505_00715_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(config):
+    """Bytes per product from the committed counter summary, or None when the
+    kernel sources changed since it was taken or it covers another workload."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_sha1") != kernel_source_hash() or kv.get("workload") != config:
+            return None
+        return float(kv["traffic_bytes_per_product"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 WORKLOADS = {
     "housing80k": dict(tol=3e-6, chunk=11, desc="finned housing, {n} triangles (cylinder R 0.1 m, length "
@@ -67,7 +98,6 @@ def parse():
     ap.add_argument("--config", default="housing40k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch parameters")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner's cache")
@@ -330,15 +360,12 @@ def main():
         ctx.compressed_matvec(g.PER_FREQUENCY, PREC_MV, Xd, Yd)
         torch.cuda.synchronize()
         mv_ms = ctx.kernel_ms("matvec_perfreq")
-        ss = None
-        if not args.no_solve:
-            ss = ctx.solve(B, Xs, rtol=1e-6, max_iter=400, restart=50, precision=PREC_MV)
+        ss = ctx.solve(B, Xs, rtol=1e-6, max_iter=400, restart=50, precision=PREC_MV)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         say(f"[bench] step {wall * 1e3:.0f} ms: aca_blocks {aca_ms:.0f} ms (kernel {aca_k:.0f}, recompress "
             f"{rec_k:.0f}, apply {app_k:.0f}), aca3d {s3.device_ms:.0f} ms (far {s3.far_ms:.0f}), product "
-            f"{mv_ms:.2f} ms" + ("" if ss is None else f", solve {ss.device_ms:.0f} ms ({ss.iters_max} it, "
-                                                       f"{ss.n_converged}/{ss.n_systems})") +
+            f"{mv_ms:.2f} ms, solve {ss.device_ms:.0f} ms ({ss.iters_max} it, {ss.n_converged}/{ss.n_systems})" +
             f"; after aca_blocks {m_aca}, after aca3d {m_3d}, at the end {mem()}")
         if record is not None:
             record.append(dict(wall=wall, pairs=pairs, aca_ms=aca_ms, aca_k=aca_k, rec_k=rec_k, app_k=app_k,
@@ -396,7 +423,7 @@ def main():
     err = float(per_k.max())
 
     # the dominant kernel of the step, by device time
-    iters = 0 if solve is None else solve.iters_max
+    iters = solve.iters_max
     kern = {"aca_kernel<float,true,...> (per-frequency ACA)": med("aca_k"),
             "recompress_kernel<float>": med("rec_k"),
             "aca3d_kernel<float,true,...> (3D-ACA, admissible blocks)": far_ms,
@@ -421,7 +448,9 @@ def main():
     else:
         gbps = mv_bytes / (mv_ms / 1e3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": gbps / HBM_PEAK_GBPS, "traffic": None, "launch_ms": mv_ms,
+                "frac": gbps / HBM_PEAK_GBPS,
+                "traffic": measured_traffic(args.config) if PREC_MV == g.C64_SPLIT_BF16 else None,
+                "launch_ms": mv_ms,
                 "bytes_per_launch": mv_bytes,
                 "mfma_algorithmic_tflops": mv_flops / (mv_ms / 1e3) / 1e12,
                 "note": "HBM time of the algorithmic bytes exceeds the bf16 matrix-core time of the "
@@ -452,8 +481,7 @@ def main():
         "matvec_bytes": mv_bytes,
         "hbm_copy_GBps": copy_gbps,
         "aca3d_ms": float(np.median([r["a3"].device_ms for r in recs])),
-        "solve": None if solve is None else
-        {"iters_max": solve.iters_max, "resid_max": solve.resid_max, "ms": solve.device_ms,
+        "solve": {"iters_max": solve.iters_max, "resid_max": solve.resid_max, "ms": solve.device_ms,
          "converged": f"{solve.n_converged}/{solve.n_systems}"},
         "rel_err_matvec_vs_oracle": err,
         "rel_err_matvec_per_freq": {int(k): float(e) for k, e in zip(kk, per_k)},
