@@ -456,6 +456,14 @@ GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol, int32_t max_
 GCQ_API int gcq_get_aca3d_block(gcq_context* ctx, int32_t block, int32_t cap, int32_t* rank,
                                 int32_t* freqs, gcq_c128* fibers, gcq_c128* slices);
 
+/* gcq_aca3d_ranks: per block of the partition (depth-first order) the number
+ *   of terms of its 3D-ACA (Alg. 1) into terms[b], and for an admissible block
+ *   the sum of its slices' ranks (the stacked columns of Ubar and Vbar that the
+ *   products of eq. product contract over) into columns[b]; 0 for an
+ *   inadmissible block, whose slices are dense.  Host arrays of n = number of
+ *   blocks values (GCQ_ERR_ARG otherwise); GCQ_ERR_STATE before gcq_aca3d. */
+GCQ_API int gcq_aca3d_ranks(gcq_context* ctx, int32_t* terms, int32_t* columns, int64_t n);
+
 /* gcq_sample_rows: rows of the compressed 3D array at frequency `freq`
  *   (0..n_freq-1): out[a][j] = V~(s_freq)[rows[a], j] for every column j,
  *   V~(s) = sum_b sum_d f_{b,d}(s) H_{b,d} the approximant of Alg. 1 that the

@@ -105,6 +105,7 @@ def _load():
         "gcq_aca_ranks": [P, P, I64],
         "gcq_aca3d": [P, D, D, I32, I32, U32, P],
         "gcq_get_aca3d_block": [P, I32, I32, P, P, P, P],
+        "gcq_aca3d_ranks": [P, P, P, I64],
         "gcq_compressed_matvec": [P, I32, I32, P, P, I32],
         "gcq_sample_rows": [P, P, I32, I32, P],
         "gcq_solve": [P, P, P, D, I32, I32, I32, P],
@@ -369,6 +370,16 @@ class Context:
         self.F_precision = precision
         st.status = code
         return st
+
+    def aca3d_ranks(self):
+        """Per block of the partition: the number of 3D-ACA terms and, for an
+        admissible block, the sum of its slices' ranks; two int32 arrays."""
+        nb = int(self.get_tree()[1].shape[0])
+        terms = np.zeros(nb, np.int32)
+        cols = np.zeros(nb, np.int32)
+        _check(_lib.gcq_aca3d_ranks(self._h, terms.ctypes.data_as(C.c_void_p),
+                                    cols.ctypes.data_as(C.c_void_p), nb))
+        return terms, cols
 
     def get_aca3d_block(self, block: int, nK: int, cap: int = 64):
         if not hasattr(self, "_blocks"):

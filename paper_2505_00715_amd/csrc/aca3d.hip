@@ -1231,6 +1231,21 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   return ncap > 0 ? GCQ_RANK_CAPPED : GCQ_OK;
 }
 
+extern "C" GCQ_API int gcq_aca3d_ranks(gcq_context* ctx, int32_t* terms, int32_t* columns, int64_t n) {
+  if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
+  if (!ctx->F.valid) return fail(GCQ_ERR_STATE, "run gcq_aca3d first");
+  const Faces3D& F = ctx->F;
+  const int64_t nb = int64_t(ctx->blocks.size());
+  if (!terms || !columns || n != nb) return fail(GCQ_ERR_ARG, "terms and columns must hold %lld values", (long long)nb);
+  for (int64_t b = 0; b < nb; ++b) {
+    terms[b] = F.brank[b];
+    int c = 0;
+    for (int d = F.bterm[b]; d < F.bterm[b + 1]; ++d) c += F.trank[d] > 0 ? F.trank[d] : 0;
+    columns[b] = c;
+  }
+  return GCQ_OK;
+}
+
 extern "C" GCQ_API int gcq_get_aca3d_block(gcq_context* ctx, int32_t block, int32_t cap,
                                            int32_t* rank, int32_t* freqs, gcq_c128* fibers,
                                            gcq_c128* slices) {

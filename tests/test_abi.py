@@ -82,6 +82,9 @@ def test_argument_and_state_errors():
     # device work on a host-only context is a state error
     rc = g.lib.gcq_aca3d(ctx._h, 1e-5, 1e-5, 10, 0, 0, None)
     assert rc < 0
+    with pytest.raises(g.GcqError) as e:            # no 3D-ACA yet
+        ctx.aca3d_ranks()
+    assert e.value.code == -4
     assert g.lib.gcq_destroy(None) == 0
     ctx.destroy()
 

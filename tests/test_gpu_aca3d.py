@@ -246,6 +246,27 @@ def test_sample_rows_are_rows_of_the_product(setup, prec):
         ctx.sample_rows(rows, L, out)
 
 
+def test_aca3d_ranks_describe_the_storage(setup):
+    """gcq_aca3d_ranks: per block the number of terms (those of
+    gcq_get_aca3d_block) and, for admissible blocks, the stacked slice ranks;
+    together they account for the stored slices and fibers exactly."""
+    xyz, tri, s, P, T, B, rep, conj, K, kpos, b3 = setup
+    ctx = make_ctx(xyz, tri, 1.0, s, 32, 1.0)
+    st = ctx.aca3d(TOLA, TOLF, 40, g.C64)
+    terms, cols = ctx.aca3d_ranks()
+    blocks = ctx.get_tree()[1]
+    m = blocks[:, 1] - blocks[:, 0]
+    n = blocks[:, 3] - blocks[:, 2]
+    adm = blocks[:, 4] != 0
+    assert len(terms) == len(B) and terms.max() == st.rank_max
+    assert cols.sum() == st.slice_rank_sum
+    assert np.all(cols[~adm] == 0) and np.all(cols[adm] >= terms[adm])
+    words = np.where(adm, cols * (m + n), terms * m * n) + terms * len(K)
+    assert int(words.sum()) * 8 == st.storage_bytes
+    for b in np.random.default_rng(0).choice(len(B), 12, replace=False):
+        assert len(ctx.get_aca3d_block(int(b), len(K), cap=max(1, st.rank_max))[0]) == terms[b]
+
+
 def test_split_bf16_product(setup):
     """The split-bf16 per-frequency product (complex64 operator, operands as
     bf16 hi + lo planes, float accumulation) against the oracle's product of
