@@ -427,7 +427,7 @@ def main():
     kern = {"aca_kernel<float,true,...> (per-frequency ACA)": med("aca_k"),
             "recompress_kernel<float>": med("rec_k"),
             "aca3d_kernel<float,true,...> (3D-ACA, admissible blocks)": far_ms,
-            "per-frequency product (" + ("split-bf16 bf_rows + bf_tfill" if PREC_MV == g.C64_SPLIT_BF16 else
+            "per-frequency product (" + ("split-bf16 bf_tfill + bf_rows + bf_near" if PREC_MV == g.C64_SPLIT_BF16 else
                                         "perfreq_mfma") + "), inside GMRES": mv_ms * (iters + 2 * (iters // 50 + 1))}
     dom = max(kern, key=kern.get)
     aca_ops = last["entries"] * 7 * OPS_PER_QPOINT

@@ -117,7 +117,7 @@ enum {
  *   aca3d_stack_slices: initial reservation of an admissible block's stacked
  *     slice factors, in slices of full ACA rank (1..64, default 8); a block
  *     that needs more moves its stack to a reservation twice as large.
- *   aca_waves, product_graph: see the fields.
+ *   aca_waves, product_graph, product_cols_per_wave: see the fields.
  * Results do not depend on the configuration beyond rounding order. */
 typedef struct {
   int32_t aca3d_waves[4];
@@ -127,6 +127,10 @@ typedef struct {
   int32_t product_graph;       /* 1 (default): gcq_compressed_matvec and gcq_solve replay
                                   the per-frequency product as a captured HIP graph;
                                   0: plain launches */
+  int32_t product_cols_per_wave; /* frequency columns a wave64 of the split-bf16
+                                  product owns: 32 (default; 8 waves per workgroup)
+                                  or 64 (4 waves; each operator fragment serves two
+                                  32-column tiles) */
 } gcq_tuning;
 
 typedef struct {

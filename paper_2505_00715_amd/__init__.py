@@ -52,7 +52,8 @@ class SolveStats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("aca3d_waves", C.c_int32 * 4), ("aca3d_stack_slices", C.c_int32),
-                ("aca_waves", C.c_int32), ("product_graph", C.c_int32)]
+                ("aca_waves", C.c_int32), ("product_graph", C.c_int32),
+                ("product_cols_per_wave", C.c_int32)]
 
 
 class TrainCfg(C.Structure):
@@ -216,12 +217,15 @@ class Context:
         return _lib.gcq_kernel_ms(self._h, name.encode())
 
     def set_tuning(self, aca3d_waves=None, aca3d_stack_slices=None, aca_waves=None,
-                   product_graph=None):
+                   product_graph=None, product_cols_per_wave=None):
         """aca3d_waves: 4 group sizes (waves per block) of the 3D-ACA size classes;
         aca3d_stack_slices: initial stack reservation of a far block (slices);
         aca_waves: waves per pair of aca_blocks; product_graph: replay the
-        per-frequency product as a captured graph."""
+        per-frequency product as a captured graph; product_cols_per_wave:
+        frequency columns per wave of the split-bf16 product (32 or 64)."""
         t = self.get_tuning()
+        if product_cols_per_wave is not None:
+            t.product_cols_per_wave = int(product_cols_per_wave)
         if aca_waves is not None:
             t.aca_waves = int(aca_waves)
         if product_graph is not None:

@@ -7,6 +7,7 @@ HIP-event device times the library records (``Context.kernel_ms``):
   aca3d_waves          wave64s per admissible block of ``aca3d``, per size class
   aca3d_stack_slices   initial stack reservation of an admissible block: 4, 8, 16
   product_graph        per-frequency product as a replayed graph or plain launches
+  product_cols_per_wave  frequency columns per wave64 of the split-bf16 product: 32, 64
 
 Results are cached as JSON, keyed by (workload key, device architecture,
 precision).  Every candidate is a valid configuration: results differ only in
@@ -18,7 +19,7 @@ import json
 import os
 import time
 
-from . import C64, FLAG_RECOMPRESS, PER_FREQUENCY
+from . import C64, C64_SPLIT_BF16, FLAG_RECOMPRESS, PER_FREQUENCY
 
 ACA3D_CANDIDATES = [(4, 4, 4, 4), (2, 4, 4, 4), (2, 2, 4, 4), (4, 4, 4, 8), (1, 2, 4, 8)]
 STACK_CANDIDATES = [4, 8, 16]
@@ -69,7 +70,8 @@ def save(workload: str, precision: int, params: dict, path: str | None = None, d
 
 def apply(ctx, params: dict):
     ctx.set_tuning(aca3d_waves=params["aca3d_waves"], aca3d_stack_slices=params["aca3d_stack_slices"],
-                   aca_waves=params["aca_waves"], product_graph=params["product_graph"])
+                   aca_waves=params["aca_waves"], product_graph=params["product_graph"],
+                   product_cols_per_wave=params.get("product_cols_per_wave", 32))
 
 
 def tune(ctx, workload: str, precision: int, tol: float, max_rank: int = 64, max_freq_rank: int = 40,
@@ -120,22 +122,35 @@ def tune(ctx, workload: str, precision: int, tol: float, max_rank: int = 64, max
     ctx.set_tuning(aca3d_stack_slices=best["aca3d_stack_slices"])
     best["aca3d_ms"] = times[best["aca3d_stack_slices"]]
     ctx.aca3d(tol, tol, max_freq_rank, precision)   # the operator of the chosen setting
-    # the product: graph replay or plain launches
+    # the product: graph replay or plain launches, then (split-bf16) the
+    # frequency columns per wave
     best["product_graph"] = 1
+    best["product_cols_per_wave"] = 32
     if X is not None and Y is not None:
         import torch
+        pprec = product_precision if product_precision is not None else precision
+
+        def product_ms():
+            ts = []
+            for _ in range(4):
+                ctx.compressed_matvec(PER_FREQUENCY, pprec, X, Y)
+                torch.cuda.synchronize()
+                ts.append(ctx.kernel_ms("matvec_perfreq"))
+            return sorted(ts)[len(ts) // 2]
         times = {}
         for gr in (0, 1):
             ctx.set_tuning(product_graph=gr)
-            ts = []
-            for _ in range(4):
-                ctx.compressed_matvec(PER_FREQUENCY, product_precision if product_precision is not None
-                                      else precision, X, Y)
-                torch.cuda.synchronize()
-                ts.append(ctx.kernel_ms("matvec_perfreq"))
-            times[gr] = sorted(ts)[len(ts) // 2]
+            times[gr] = product_ms()
             say(f"[autotune] product_graph {gr}: {times[gr]:.3f} ms")
         best["product_graph"] = min(times, key=times.get)
+        ctx.set_tuning(product_graph=best["product_graph"])
+        if pprec == C64_SPLIT_BF16:
+            times = {}
+            for cw in (32, 64):
+                ctx.set_tuning(product_cols_per_wave=cw)
+                times[cw] = product_ms()
+                say(f"[autotune] product_cols_per_wave {cw}: {times[cw]:.3f} ms")
+            best["product_cols_per_wave"] = min(times, key=times.get)
     apply(ctx, best)
     best["tuning_s"] = time.perf_counter() - t0
     save(workload, precision, best, path)

@@ -376,6 +376,9 @@ GCQ_API int gcq_set_tuning(gcq_context* ctx, const gcq_tuning* tuning) {
     return fail(GCQ_ERR_ARG, "aca_waves = %d is not 1, 2 or 4", tuning->aca_waves);
   if (tuning->product_graph != 0 && tuning->product_graph != 1)
     return fail(GCQ_ERR_ARG, "product_graph = %d is not 0 or 1", tuning->product_graph);
+  if (tuning->product_cols_per_wave != 32 && tuning->product_cols_per_wave != 64)
+    return fail(GCQ_ERR_ARG, "product_cols_per_wave = %d is not 32 or 64", tuning->product_cols_per_wave);
+  if (tuning->product_cols_per_wave != ctx->tune.product_cols_per_wave) ctx->F.graphs.clear();
   ctx->tune = *tuning;
   return GCQ_OK;
 }

@@ -150,7 +150,7 @@ struct Faces3D {
   bool meta_valid = false;       // pmeta holds the current frequency set's tables
   // the operator's slices split into bf16 planes for GCQ_C64_SPLIT_BF16
   // products (built on first use, per block table d_bfblk)
-  DevBuf bfpool, bftbuf, d_bfblk, d_bfitems, d_bfrowblk, d_bfbig, d_bfmask;
+  DevBuf bfpool, bftbuf, d_bfblk, d_bfitems, d_bfrange, d_bfrowblk, d_bfbig, d_bfmask;
   bool bf_valid = false;
   int bf_items = 0, bf_big = 0, bf_levels = 0;
   int64_t bf_bytes = 0;
@@ -192,7 +192,7 @@ struct gcq_context {
   hipStream_t side[3] = {nullptr, nullptr, nullptr};
   hipEvent_t evfork = nullptr, evjoin[3] = {nullptr, nullptr, nullptr};
   // launch configuration
-  gcq_tuning tune = {{4, 4, 4, 4}, 8, 1, 1};
+  gcq_tuning tune = {{4, 4, 4, 4}, 8, 1, 1, 32};
 
   // mesh
   bool have_mesh = false;

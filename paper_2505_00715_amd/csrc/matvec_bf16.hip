@@ -15,23 +15,15 @@
 // float products (Gauss) on the float matrix cores, which run at 1/16 of the
 // bf16 rate.
 //
-// Operand storage: "groups" of 8 consecutive values along the contraction
-// index, holding the planes of those 8 values (operator groups: hi(Re), lo(Re),
-// hi(Im), lo(Im), 64 bytes; vector groups: hi, mid, lo of Re then of Im, 96
-// bytes).  Contractions over a block's columns (Vbar^H X_J, D_d X_J) use
-// groups aligned to global cluster positions (group g covers positions
-// 8g .. 8g + 7), so the slice groups and the right-hand side's groups line up
-// and every lane load is an aligned 16-byte load; positions outside the block
-// are zero in the slice groups.
-//   far block (R stacked columns): Vg[c][g] = conj(Vbar[:, c]) over the
-//     block's column groups; Ug[i][gc] = Ubar[i, 8 gc .. 8 gc + 7]
-//   near block, term d: Dg_d[i][g] = D_d[i, :] over the column groups
-//   right-hand side: Xg[k][g] (frequency k, all positions of the mesh)
-// The product: per block and 64-column chunk of frequencies, as in the float
-// kernel -- far: T = Vbar^H X_J (stacked columns x 64), T' = F o T (fibers),
-// split into vector planes in LDS, Y_I += Ubar T'; near:
-// Y_I += sum_d f_d o (D_d X_J); float atomics into Y (frequency fastest),
-// permuted out afterwards.
+// Operand storage: every operand in the order the matrix cores take it
+// (fragments, below), 16-byte aligned loads of 8 bf16 values.  The product per
+// frequency column, as in the float kernel -- far block: T = Vbar^H X_J
+// (stacked columns x columns), T' = F o T (fibers), Y_I += Ubar T'; near block:
+// Y_I += sum_d f_d o (D_d X_J).  Work items are rows of one row cluster with all
+// its far (or all its near) blocks; a workgroup's waves own the frequency
+// columns, accumulate the item's rows in registers and store them once into
+// the level buffer of the cluster's depth (near blocks: the level after the
+// deepest); a last pass sums the levels of each row into Y.  No atomics.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -177,6 +169,10 @@ __device__ __forceinline__ void cstep2(const BfGroup& a, const BfGroup3& x, f16v
 
 constexpr int BF_MC = 64;    // rows of a work item: BF_RT 32-row tiles
 constexpr int BF_RT = BF_MC / 32;
+constexpr int BF_NX = 8;     // work lists of the product, one per XCD (workgroup i runs on XCD i % 8)
+constexpr int BF_WAVES = 8;  // waves of a workgroup: one 32-column frequency tile each (256 columns)
+constexpr int BF_RTB = 3;    // 32-row tiles of a work item on a row cluster above BF_MC rows (T' from the buffer)
+constexpr int BF_COUNTERS = 4 * BF_NX;   // work counters: lists of far items (small, big row clusters), near items, T' blocks
 constexpr int FRAG = 256;    // uint4 per operator fragment: 4 planes x 64 lanes
 constexpr int VFRAG = 384;   // uint4 per T' fragment: 6 planes x 64 lanes
 
@@ -286,7 +282,7 @@ __global__ void __launch_bounds__(256) bf_convert(const int* __restrict__ blk, c
 __global__ void __launch_bounds__(256) bf_x_in(const cpx<float>* __restrict__ X, uint4* __restrict__ Xg,
                                                const int* __restrict__ perm, const int* __restrict__ conjflag,
                                                int n, int L, int ng, int nkt, int* __restrict__ counter) {
-  if (blockIdx.x == 0 && threadIdx.x < 2) counter[threadIdx.x] = 0;   // work counter of the product
+  if (blockIdx.x == 0 && threadIdx.x < BF_COUNTERS) counter[threadIdx.x] = 0;   // work counters of the product
   const int64_t total = int64_t(nkt) * ng * 32;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += int64_t(gridDim.x) * blockDim.x) {
@@ -337,19 +333,45 @@ __device__ __forceinline__ BfGroup3 load_x(const uint4* __restrict__ xk, int g, 
 
 
 
-// T tile (stacked columns 32 t .. + 32 of a far block x the wave's 32
-// frequency columns) = Vbar^H X_J, contracted over the block's column groups
-__device__ __forceinline__ void t_tile(const uint4* __restrict__ Vg, const BfBlock& B, int t,
-                                       const uint4* __restrict__ xk, int lane, int lr, int lh,
-                                       f16v& re, f16v& im) {
-  re = f16_zero();
-  im = f16_zero();
+// the KW 32-column frequency tiles kt0 .. kt0 + KW - 1 that a wave owns
+template <int KW>
+struct Tiles {
+  int kcol[KW];            // the lane's column in each tile
+  bool kin[KW];            // that column exists (kcol < L)
+  bool kv[KW];             // the tile exists (kt < number of tiles)
+  int kp[KW];              // frequency position of the lane's column
+  const uint4* xk[KW];     // the tile's right-hand side fragments
+  __device__ __forceinline__ Tiles(int kt0, int nkt, int L, int lr, int ng, const int* __restrict__ colpos,
+                                   const uint4* __restrict__ Xg) {
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+      const int kt = kt0 + u;
+      kv[u] = kt < nkt;
+      kcol[u] = kt * 32 + lr;
+      kin[u] = kv[u] && kcol[u] < L;
+      kp[u] = kin[u] ? colpos[kcol[u]] : 0;
+      xk[u] = Xg + int64_t(kv[u] ? kt : 0) * ng * 192;
+    }
+  }
+};
+
+// T tile (stacked columns 32 t .. + 32 of a far block x 32 frequency columns)
+// = Vbar^H X_J for each of the wave's tiles, contracted over the block's column
+// groups; each Vbar fragment serves all KW tiles
+template <int KW>
+__device__ __forceinline__ void t_tile(const uint4* __restrict__ Vg, const BfBlock& B, int t, const Tiles<KW>& C,
+                                       int lane, int lr, int lh, f16v* re, f16v* im) {
+#pragma unroll
+  for (int u = 0; u < KW; ++u) re[u] = im[u] = f16_zero();
   const uint4* vf = Vg + int64_t(t) * B.KS * FRAG;
   for (int j = 0; j < B.KS; ++j) {
     const int g = 2 * j + lh;
     const BfGroup a = load_op(vf + int64_t(j) * FRAG, lane);
-    const BfGroup3 x = g < B.G ? load_x(xk, B.g0 + g, lr) : zero_group3();
-    cstep2(a, x, re, im);
+#pragma unroll
+    for (int u = 0; u < KW; ++u) {
+      const BfGroup3 x = (g < B.G && C.kv[u]) ? load_x(C.xk[u], B.g0 + g, lr) : zero_group3();
+      cstep2(a, x, re[u], im[u]);
+    }
   }
 }
 
@@ -381,44 +403,99 @@ __device__ __forceinline__ void t_prime(const f16v& re, const f16v& im, const Bf
   }
 }
 
+// next work item of a workgroup: from its XCD's list (spatially ordered, so
+// that the row clusters in flight on one XCD share their blocks' column vectors
+// in its L2), then from the other lists; -1 when all are done.  range holds
+// BF_NX + 1 list bounds, counter BF_NX counters.
+__device__ __forceinline__ int next_item(const int* __restrict__ range, int* __restrict__ counter, int home,
+                                         int& visited, int* cur) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int got = -1;
+    while (visited < BF_NX) {
+      const int li = (home + visited) % BF_NX;
+      const int q = atomicAdd(counter + li, 1);
+      if (q < range[li + 1] - range[li]) {
+        got = range[li] + q;
+        break;
+      }
+      ++visited;
+    }
+    *cur = got;
+  }
+  __syncthreads();
+  return *cur;
+}
+
+__device__ __forceinline__ void store_t(uint4* __restrict__ f, const BfGroup3& a) {
+  f[0] = a.hr;
+  f[64] = a.mr;
+  f[128] = a.lr;
+  f[192] = a.hi;
+  f[256] = a.mi;
+  f[320] = a.li;
+}
+
 // T' of far blocks whose row cluster has more than BF_MC rows, into the T'
-// buffer ([t][kt][s][plane][lane]); one workgroup per block, waves over
-// (32-column tile, frequency tile) pairs
-__global__ void __launch_bounds__(256) bf_tfill(const int* __restrict__ big, int nbig, const BfBlock* __restrict__ bb,
-                                                const uint4* __restrict__ bfp, const int* __restrict__ bcol,
-                                                const int64_t* __restrict__ cols, const cpx<float>* __restrict__ pool,
-                                                const int* __restrict__ colpos, int L, int ng,
-                                                const uint4* __restrict__ Xg, uint4* __restrict__ Tbuf) {
+// buffer ([t][kt][s][plane][lane]); one workgroup per block, blocks from the
+// workgroup's XCD list (ordered by column cluster, so that blocks in flight on
+// an XCD share their right-hand side in its L2), each wave KW
+// 32-column frequency tiles, the stacked columns in groups of BF_TG tiles, so
+// that each right-hand side fragment serves BF_TG tiles and each Vbar fragment
+// KW tiles
+constexpr int BF_TG = 2;
+template <int KW>
+__global__ void __launch_bounds__(KW == 1 ? 512 : 256) bf_tfill(
+    const int* __restrict__ big, const int* __restrict__ range, int* __restrict__ counter,
+    const BfBlock* __restrict__ bb, const uint4* __restrict__ bfp,
+    const int* __restrict__ bcol, const int64_t* __restrict__ cols, const cpx<float>* __restrict__ pool,
+    const int* __restrict__ colpos, int L, int ng, const uint4* __restrict__ Xg, uint4* __restrict__ Tbuf) {
   const int lane = threadIdx.x & 63, lr = lane & 31, lh = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
   const int nkt = (L + 31) >> 5;
-  for (int q = blockIdx.x; q < nbig; q += gridDim.x) {
+  __shared__ int cur;
+  int visited = 0;
+  for (int q; (q = next_item(range, counter, blockIdx.x % BF_NX, visited, &cur)) >= 0;) {
     const int b = big[q];
     const BfBlock B = bb[b];
     const uint4* Vg = bfp + B.off * FRAG;
-    for (int pr = w; pr < B.T * nkt; pr += nw) {
-      const int t = pr / nkt, kt = pr % nkt;
-      const int kcol = kt * 32 + lr;
-      const bool kin = kcol < L;
-      const int kp = kin ? colpos[kcol] : 0;
-      f16v re, im;
-      t_tile(Vg, B, t, Xg + int64_t(kt) * ng * 192, lane, lr, lh, re, im);
-      BfGroup3 t0, t1;
-      t_prime(re, im, B, t, bcol[b], cols, pool, kin, kp, lh, t0, t1);
-      uint4* f = Tbuf + (B.toff + int64_t(t * nkt + kt) * 2) * VFRAG + lane;
-      f[0] = t0.hr;
-      f[64] = t0.mr;
-      f[128] = t0.lr;
-      f[192] = t0.hi;
-      f[256] = t0.mi;
-      f[320] = t0.li;
-      f += VFRAG;
-      f[0] = t1.hr;
-      f[64] = t1.mr;
-      f[128] = t1.lr;
-      f[192] = t1.hi;
-      f[256] = t1.mi;
-      f[320] = t1.li;
+    for (int kt0 = w * KW; kt0 < nkt; kt0 += nw * KW) {
+      const Tiles<KW> C(kt0, nkt, L, lr, ng, colpos, Xg);
+      for (int t0 = 0; t0 < B.T; t0 += BF_TG) {
+        const int nt = min(BF_TG, B.T - t0);
+        f16v re[BF_TG][KW], im[BF_TG][KW];
+#pragma unroll
+        for (int v = 0; v < BF_TG; ++v)
+#pragma unroll
+          for (int u = 0; u < KW; ++u) re[v][u] = im[v][u] = f16_zero();
+        for (int j = 0; j < B.KS; ++j) {
+          const int g = 2 * j + lh;
+          BfGroup3 x[KW];
+#pragma unroll
+          for (int u = 0; u < KW; ++u) x[u] = (g < B.G && C.kv[u]) ? load_x(C.xk[u], B.g0 + g, lr) : zero_group3();
+#pragma unroll
+          for (int v = 0; v < BF_TG; ++v) {
+            if (v >= nt) break;
+            const BfGroup a = load_op(Vg + (int64_t(t0 + v) * B.KS + j) * FRAG, lane);
+#pragma unroll
+            for (int u = 0; u < KW; ++u) cstep2(a, x[u], re[v][u], im[v][u]);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < BF_TG; ++v) {
+          if (v >= nt) break;
+          const int t = t0 + v;
+#pragma unroll
+          for (int u = 0; u < KW; ++u) {
+            if (!C.kv[u]) continue;
+            BfGroup3 a, c;
+            t_prime(re[v][u], im[v][u], B, t, bcol[b], cols, pool, C.kin[u], C.kp[u], lh, a, c);
+            uint4* f = Tbuf + (B.toff + int64_t(t * nkt + kt0 + u) * 2) * VFRAG + lane;
+            store_t(f, a);
+            store_t(f + VFRAG, c);
+          }
+        }
+      }
     }
   }
 }
@@ -434,102 +511,190 @@ __device__ __forceinline__ BfGroup3 load_t(const uint4* __restrict__ f, int lane
   return x;
 }
 
-// the product: work items (rows of a row cluster, all its blocks) fetched from a
-// counter; each wave owns 32-column frequency tiles and accumulates the item's
-// rows in registers; plain stores into the row cluster's level buffer
-__global__ void __launch_bounds__(256) bf_rows(
-    const BfItem* __restrict__ items, int nitems, const int* __restrict__ rowblk, const int* __restrict__ blk,
-    const int* __restrict__ bterm, const int64_t* __restrict__ tfoff, const int64_t* __restrict__ cols,
-    const int* __restrict__ bcol, const cpx<float>* __restrict__ pool, const BfBlock* __restrict__ bb,
-    const uint4* __restrict__ bfp, const int* __restrict__ colpos, int L, int ng,
+// stores of a wave's accumulated rows (its 32-column tile) into a level buffer
+template <int RT>
+__device__ __forceinline__ void store_rows(const f16v* yre, const f16v* yim, int nrt, const BfItem& I, int lh,
+                                           int kcol, int L, cpx<float>* __restrict__ yl) {
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    if (rt >= nrt) break;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 32 * rt + 8 * (r >> 2) + 4 * lh + (r & 3);
+      if (row < I.rows) yl[int64_t(I.rb + I.r0 + row) * L + kcol] = {yre[rt][r], yim[rt][r]};
+    }
+  }
+}
+
+// far blocks of the product: work items (rows of a row cluster, all its far
+// blocks); each wave owns KW 32-column frequency tiles (all L columns in one
+// pass, so the workgroup fetches each operator fragment once, and each
+// fragment a wave loads serves KW tiles) and accumulates the item's rows in
+// registers; per 32 stacked columns of a block, T' (BIG: read from the T'
+// buffer, items of up to 32 BF_RTB rows; else computed here, items of up to
+// BF_MC rows), then Y += Ubar[rows, tile] T'; plain stores into the row
+// cluster's level buffer
+template <bool BIG, int KW>
+__global__ void __launch_bounds__(KW == 1 ? 512 : 256) bf_rows(
+    const BfItem* __restrict__ items, const int* __restrict__ range, const int* __restrict__ rowblk,
+    const int64_t* __restrict__ cols, const int* __restrict__ bcol, const cpx<float>* __restrict__ pool,
+    const BfBlock* __restrict__ bb, const uint4* __restrict__ bfp, const int* __restrict__ colpos, int L, int ng,
     const uint4* __restrict__ Xg, const uint4* __restrict__ Tbuf, cpx<float>* __restrict__ Ylev,
     int64_t lev_stride, int* __restrict__ counter) {
+  constexpr int RT = BIG ? BF_RTB : BF_RT;
   __shared__ int cur;
   const int lane = threadIdx.x & 63, lr = lane & 31, lh = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
   const int nkt = (L + 31) >> 5;
-  while (true) {
-    __syncthreads();
-    if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = cur;
-    if (it >= nitems) break;
+  int visited = 0;
+  for (int it; (it = next_item(range, counter, blockIdx.x % BF_NX, visited, &cur)) >= 0;) {
     const BfItem I = items[it];
     const int nrt = (I.rows + 31) >> 5;
     const int rt0 = I.r0 >> 5;
-    for (int kt = w; kt < nkt; kt += nw) {
-      const int kcol = kt * 32 + lr;
-      const bool kin = kcol < L;
-      const int kp = kin ? colpos[kcol] : 0;
-      const uint4* xk = Xg + int64_t(kt) * ng * 192;
-      f16v yre[BF_RT], yim[BF_RT];
+    for (int kt0 = w * KW; kt0 < nkt; kt0 += nw * KW) {
+      const Tiles<KW> C(kt0, nkt, L, lr, ng, colpos, Xg);
+      f16v yre[KW][RT], yim[KW][RT];
 #pragma unroll
-      for (int rt = 0; rt < BF_RT; ++rt) yre[rt] = yim[rt] = f16_zero();
+      for (int u = 0; u < KW; ++u)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) yre[u][rt] = yim[u][rt] = f16_zero();
       for (int bi = 0; bi < I.nb; ++bi) {
         const int b = rowblk[I.b0 + bi];
         const BfBlock B = bb[b];
-        if (B.G == 0) continue;
         const uint4* op = bfp + B.off * FRAG;
-        if (!(blk[5 * b + 4] & 1)) {
-          // near block: Y += f_d o (D_d X_J) per term and row tile
-          const int d0 = bterm[b], nd = bterm[b + 1] - d0;
+        const uint4* Ug = op + int64_t(B.T) * B.KS * FRAG;
+        if constexpr (BIG) {
+          // the block's T' halves (t, sd) in order, the next one loaded while
+          // the current one is applied; one row tile's fragments in flight (the
+          // compiler barriers keep the loads of all row tiles from being
+          // hoisted together, which would not fit the registers)
+          auto tload = [&](int h, BfGroup3* tv) {
 #pragma unroll
-          for (int rt = 0; rt < BF_RT; ++rt) {
-            if (rt >= nrt) break;
-            for (int d = 0; d < nd; ++d) {
-              const uint4* df = op + (int64_t(d) * B.mt + rt0 + rt) * B.KS * FRAG;
-              f16v re = f16_zero(), im = f16_zero();
-              for (int j = 0; j < B.KS; ++j) {
-                const int g = 2 * j + lh;
-                const BfGroup a = load_op(df + int64_t(j) * FRAG, lane);
-                const BfGroup3 x = g < B.G ? load_x(xk, B.g0 + g, lr) : zero_group3();
-                cstep2(a, x, re, im);
-              }
-              const cpx<float> f = kin ? pool[tfoff[d0 + d] + kp] : cpx<float>{0.f, 0.f};
+            for (int u = 0; u < KW; ++u)
+              tv[u] = C.kv[u] ? load_t(Tbuf + (B.toff + int64_t((h >> 1) * nkt + kt0 + u) * 2 + (h & 1)) * VFRAG,
+                                       lane)
+                              : zero_group3();
+          };
+          BfGroup3 nxt[KW];
+          tload(0, nxt);
+          for (int h = 0; h < 2 * B.T; ++h) {
+            BfGroup3 tv[KW];
 #pragma unroll
-              for (int r = 0; r < 16; ++r) {
-                yre[rt][r] += f.re * re[r] - f.im * im[r];
-                yim[rt][r] += f.re * im[r] + f.im * re[r];
-              }
+            for (int u = 0; u < KW; ++u) tv[u] = nxt[u];
+            if (h + 1 < 2 * B.T) tload(h + 1, nxt);
+            const int t = h >> 1, sd = h & 1;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+              if (rt >= nrt) break;
+              const BfGroup a = load_op(Ug + ((int64_t(rt0 + rt) * B.T + t) * 2 + sd) * FRAG, lane);
+#pragma unroll
+              for (int u = 0; u < KW; ++u) cstep2(a, tv[u], yre[u][rt], yim[u][rt]);
+              asm volatile("" ::: "memory");
             }
           }
           continue;
         }
-        // far block: per 32 stacked columns, T' (computed here, or read from the
-        // T' buffer), then Y += Ubar[rows, tile] T'
-        const uint4* Ug = op + int64_t(B.T) * B.KS * FRAG;
         for (int t = 0; t < B.T; ++t) {
-          BfGroup3 t0, t1;
-          if (B.toff < 0) {
-            f16v re, im;
-            t_tile(op, B, t, xk, lane, lr, lh, re, im);
-            t_prime(re, im, B, t, bcol[b], cols, pool, kin, kp, lh, t0, t1);
-          } else {
-            const uint4* f = Tbuf + (B.toff + int64_t(t * nkt + kt) * 2) * VFRAG;
-            t0 = load_t(f, lane);
-            t1 = load_t(f + VFRAG, lane);
-          }
+          {
+            f16v re[KW], im[KW];
+            t_tile<KW>(op, B, t, C, lane, lr, lh, re, im);
+            BfGroup3 t0[KW], t1[KW];
 #pragma unroll
-          for (int rt = 0; rt < BF_RT; ++rt) {
-            if (rt >= nrt) break;
-            const uint4* uf = Ug + ((int64_t(rt0 + rt) * B.T + t) * 2) * FRAG;
-            cstep2(load_op(uf, lane), t0, yre[rt], yim[rt]);
-            cstep2(load_op(uf + FRAG, lane), t1, yre[rt], yim[rt]);
-          }
-        }
-      }
-      if (kin) {
-        cpx<float>* yl = Ylev + I.lev * lev_stride;
+            for (int u = 0; u < KW; ++u)
+              t_prime(re[u], im[u], B, t, bcol[b], cols, pool, C.kin[u], C.kp[u], lh, t0[u], t1[u]);
 #pragma unroll
-        for (int rt = 0; rt < BF_RT; ++rt) {
-          if (rt >= nrt) break;
+            for (int rt = 0; rt < RT; ++rt) {
+              if (rt >= nrt) break;
+              const uint4* uf = Ug + ((int64_t(rt0 + rt) * B.T + t) * 2) * FRAG;
+              const BfGroup a0 = load_op(uf, lane);
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int row = 32 * rt + 8 * (r >> 2) + 4 * lh + (r & 3);
-            if (row < I.rows) yl[int64_t(I.rb + I.r0 + row) * L + kcol] = {yre[rt][r], yim[rt][r]};
+              for (int u = 0; u < KW; ++u) cstep2(a0, t0[u], yre[u][rt], yim[u][rt]);
+              const BfGroup a1 = load_op(uf + FRAG, lane);
+#pragma unroll
+              for (int u = 0; u < KW; ++u) cstep2(a1, t1[u], yre[u][rt], yim[u][rt]);
+            }
           }
         }
       }
+#pragma unroll
+      for (int u = 0; u < KW; ++u)
+        if (C.kin[u]) store_rows<RT>(yre[u], yim[u], nrt, I, lh, C.kcol[u], L, Ylev + I.lev * lev_stride);
+    }
+  }
+}
+
+// near blocks of the product: work items (rows of a row cluster, all its
+// inadmissible blocks), waves as in bf_rows; Y += f_d o (D_d X_J) per term,
+// each right-hand side fragment serving every row tile and each operator
+// fragment every tile of the wave; plain stores into the near-field buffer
+// (the level after the tree's deepest)
+template <int KW>
+__global__ void __launch_bounds__(KW == 1 ? 512 : 256) bf_near(
+    const BfItem* __restrict__ items, const int* __restrict__ range, const int* __restrict__ rowblk,
+    const int* __restrict__ bterm, const int64_t* __restrict__ tfoff, const cpx<float>* __restrict__ pool,
+    const BfBlock* __restrict__ bb, const uint4* __restrict__ bfp, const int* __restrict__ colpos, int L, int ng,
+    const uint4* __restrict__ Xg, cpx<float>* __restrict__ Ylev, int64_t lev_stride, int* __restrict__ counter) {
+  __shared__ int cur;
+  const int lane = threadIdx.x & 63, lr = lane & 31, lh = lane >> 5;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+  const int nkt = (L + 31) >> 5;
+  int visited = 0;
+  for (int it; (it = next_item(range, counter, blockIdx.x % BF_NX, visited, &cur)) >= 0;) {
+    const BfItem I = items[it];
+    const int nrt = (I.rows + 31) >> 5;
+    const int rt0 = I.r0 >> 5;
+    for (int kt0 = w * KW; kt0 < nkt; kt0 += nw * KW) {
+      const Tiles<KW> C(kt0, nkt, L, lr, ng, colpos, Xg);
+      f16v yre[KW][BF_RT], yim[KW][BF_RT];
+#pragma unroll
+      for (int u = 0; u < KW; ++u)
+#pragma unroll
+        for (int rt = 0; rt < BF_RT; ++rt) yre[u][rt] = yim[u][rt] = f16_zero();
+      for (int bi = 0; bi < I.nb; ++bi) {
+        const int b = rowblk[I.b0 + bi];
+        const BfBlock B = bb[b];
+        const uint4* op = bfp + B.off * FRAG;
+        const int d0 = bterm[b], nd = bterm[b + 1] - d0;
+        for (int d = 0; d < nd; ++d) {
+          f16v tre[KW][BF_RT], tim[KW][BF_RT];
+#pragma unroll
+          for (int u = 0; u < KW; ++u)
+#pragma unroll
+            for (int rt = 0; rt < BF_RT; ++rt) tre[u][rt] = tim[u][rt] = f16_zero();
+          const uint4* df = op + int64_t(d) * B.mt * B.KS * FRAG;
+#pragma unroll 1
+          for (int j = 0; j < B.KS; ++j) {
+            const int g = 2 * j + lh;
+            BfGroup3 x[KW];
+#pragma unroll
+            for (int u = 0; u < KW; ++u)
+              x[u] = (g < B.G && C.kv[u]) ? load_x(C.xk[u], B.g0 + g, lr) : zero_group3();
+#pragma unroll
+            for (int rt = 0; rt < BF_RT; ++rt) {
+              if (rt >= nrt) break;
+              const BfGroup a = load_op(df + (int64_t(rt0 + rt) * B.KS + j) * FRAG, lane);
+#pragma unroll
+              for (int u = 0; u < KW; ++u) cstep2(a, x[u], tre[u][rt], tim[u][rt]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < KW; ++u) {
+            const cpx<float> f = C.kin[u] ? pool[tfoff[d0 + d] + C.kp[u]] : cpx<float>{0.f, 0.f};
+#pragma unroll
+            for (int rt = 0; rt < BF_RT; ++rt) {
+              if (rt >= nrt) break;
+#pragma unroll
+              for (int r = 0; r < 16; ++r) {
+                yre[u][rt][r] += f.re * tre[u][rt][r] - f.im * tim[u][rt][r];
+                yim[u][rt][r] += f.re * tim[u][rt][r] + f.im * tre[u][rt][r];
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < KW; ++u)
+        if (C.kin[u]) store_rows<BF_RT>(yre[u], yim[u], nrt, I, lh, C.kcol[u], L, Ylev + I.lev * lev_stride);
     }
   }
 }
@@ -602,56 +767,104 @@ int bf16_setup(gcq_context* ctx) {
       off += int64_t(F.brank[b]) * x.mt * x.KS;
     }
   }
-  // work items: per row cluster with blocks, chunks of BF_MC rows, cost-ordered
-  std::vector<std::vector<int>> byrow(ctx->clusters.size());
-  for (int b = 0; b < nb; ++b)
-    if (bb[b].G > 0) byrow[ctx->blocks[b].row].push_back(b);
-  std::vector<int> rowblk;
-  std::vector<BfItem> items;
-  std::vector<double> cost;
-  std::vector<unsigned> mask(n, 0u);
-  for (size_t c = 0; c < byrow.size(); ++c) {
-    if (byrow[c].empty()) continue;
-    const Cluster& A = ctx->clusters[c];
-    if (A.depth > 31) return fail(GCQ_ERR_UNSUPPORTED, "cluster tree deeper than 31 levels");
-    const int m = A.end - A.begin;
-    for (int p = A.begin; p < A.end; ++p) mask[p] |= 1u << A.depth;
-    const int b0 = int(rowblk.size());
-    rowblk.insert(rowblk.end(), byrow[c].begin(), byrow[c].end());
-    for (int r0 = 0; r0 < m; r0 += BF_MC) {
-      BfItem it;
-      it.b0 = b0;
-      it.nb = int(byrow[c].size());
-      it.rb = A.begin;
-      it.m = m;
-      it.r0 = r0;
-      it.rows = std::min(BF_MC, m - r0);
-      it.lev = A.depth;
-      it.pad = 0;
-      const int nrt = (it.rows + 31) / 32;
-      double wk = 0;
-      for (int b : byrow[c]) {
-        const BfBlock& x = bb[b];
-        if (ctx->blocks[b].admissible)
-          wk += double(x.T) * (x.toff < 0 ? x.KS + 2 * nrt : 3 * nrt);
-        else
-          wk += double(F.brank[b]) * nrt * x.KS;
-      }
-      items.push_back(it);
-      cost.push_back(wk);
-    }
-  }
-  std::vector<int> ord(items.size());
-  std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-  std::vector<BfItem> sitems(items.size());
-  for (size_t a = 0; a < ord.size(); ++a) sitems[a] = items[ord[a]];
+  // work items: per row cluster, chunks of BF_MC rows with all its far blocks
+  // (far items, stored into the level of the cluster's depth) and with all its
+  // near blocks (near items, stored into the level after the deepest)
   int nlev = 0;
   for (auto& C : ctx->clusters) nlev = std::max(nlev, C.depth + 1);
+  if (nlev > 31) return fail(GCQ_ERR_UNSUPPORTED, "cluster tree deeper than 31 levels");
+  // kinds: 0 far blocks of row clusters up to BF_MC rows (T' computed in the
+  // item), 1 far blocks of larger row clusters (T' from the buffer), 2 near blocks
+  std::vector<std::vector<int>> byrow[3];
+  for (auto& v : byrow) v.resize(ctx->clusters.size());
+  for (int b = 0; b < nb; ++b) {
+    if (bb[b].G == 0) continue;
+    const int r = ctx->blocks[b].row;
+    const int kind = ctx->blocks[b].admissible ? (bb[b].toff >= 0 ? 1 : 0) : 2;
+    byrow[kind][r].push_back(b);
+  }
+  std::vector<int> rowblk;
+  std::vector<BfItem> sitems;
+  std::vector<int> range;   // BF_NX + 1 bounds of the lists of each kind
+  std::vector<unsigned> mask(n, 0u);
+  for (int kind = 0; kind < 3; ++kind) {
+    std::vector<BfItem> items;
+    std::vector<double> cost;
+    const int chunk = kind == 1 ? 32 * BF_RTB : BF_MC;
+    for (size_t c = 0; c < byrow[kind].size(); ++c) {
+      const std::vector<int>& bl = byrow[kind][c];
+      if (bl.empty()) continue;
+      const Cluster& A = ctx->clusters[c];
+      const int m = A.end - A.begin;
+      const int lev = kind < 2 ? A.depth : nlev;
+      for (int p = A.begin; p < A.end; ++p) mask[p] |= 1u << lev;
+      const int b0 = int(rowblk.size());
+      rowblk.insert(rowblk.end(), bl.begin(), bl.end());
+      for (int r0 = 0; r0 < m; r0 += chunk) {
+        BfItem it;
+        it.b0 = b0;
+        it.nb = int(bl.size());
+        it.rb = A.begin;
+        it.m = m;
+        it.r0 = r0;
+        it.rows = std::min(chunk, m - r0);
+        it.lev = lev;
+        it.pad = 0;
+        const int nrt = (it.rows + 31) / 32;
+        double wk = 0;
+        for (int b : bl) {
+          const BfBlock& x = bb[b];
+          if (kind == 0)
+            wk += double(x.T) * (x.KS + 2 * nrt);
+          else if (kind == 1)
+            wk += double(x.T) * 3 * nrt;
+          else
+            wk += double(F.brank[b]) * nrt * x.KS;
+        }
+        items.push_back(it);
+        cost.push_back(wk);
+      }
+    }
+    // spatial order (first row), cut into BF_NX consecutive lists of equal cost
+    std::vector<int> ord(items.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+      return items[a].rb + items[a].r0 < items[b].rb + items[b].r0;
+    });
+    const int base = int(sitems.size());
+    for (int a : ord) sitems.push_back(items[a]);
+    std::vector<int> r(BF_NX + 1, int(sitems.size()));
+    r[0] = base;
+    double total = 0, acc = 0;
+    for (double c : cost) total += c;
+    int x = 1;
+    for (size_t a = 0; a < ord.size() && x < BF_NX; ++a) {
+      acc += cost[ord[a]];
+      while (x < BF_NX && acc >= total * x / BF_NX) r[x++] = base + int(a + 1);
+    }
+    range.insert(range.end(), r.begin(), r.end());
+  }
+  // T' blocks: ordered by column cluster, cut into BF_NX lists of equal work
+  std::stable_sort(big.begin(), big.end(), [&](int a, int b) {
+    return bb[a].g0 != bb[b].g0 ? bb[a].g0 < bb[b].g0 : a < b;
+  });
+  {
+    double total = 0, acc = 0;
+    for (int b : big) total += double(bb[b].T) * bb[b].KS;
+    std::vector<int> r(BF_NX + 1, int(big.size()));
+    r[0] = 0;
+    int x = 1;
+    for (size_t a = 0; a < big.size() && x < BF_NX; ++a) {
+      acc += double(bb[big[a]].T) * bb[big[a]].KS;
+      while (x < BF_NX && acc >= total * x / BF_NX) r[x++] = int(a + 1);
+    }
+    range.insert(range.end(), r.begin(), r.end());
+  }
   GCQ_TRY(F.bfpool.ensure(size_t(off) * FRAG * sizeof(uint4) + 256));
   GCQ_TRY(F.bftbuf.ensure(size_t(toff) * VFRAG * sizeof(uint4) + 256));
   GCQ_TRY(upload(F.d_bfblk, bb, ctx->stream));
   GCQ_TRY(upload(F.d_bfitems, sitems, ctx->stream));
+  GCQ_TRY(upload(F.d_bfrange, range, ctx->stream));
   GCQ_TRY(upload(F.d_bfrowblk, rowblk, ctx->stream));
   GCQ_TRY(upload(F.d_bfbig, big, ctx->stream));
   GCQ_TRY(upload(F.d_bfmask, mask, ctx->stream));
@@ -662,7 +875,7 @@ int bf16_setup(gcq_context* ctx) {
   GCQ_HIP(hipStreamSynchronize(ctx->stream));
   F.bf_items = int(sitems.size());
   F.bf_big = int(big.size());
-  F.bf_levels = nlev;
+  F.bf_levels = nlev + 1;
   F.bf_bytes = off * FRAG * int64_t(sizeof(uint4));
   F.bf_valid = true;
   return GCQ_OK;
@@ -676,6 +889,39 @@ static size_t bf_xg_bytes(gcq_context* ctx) {
 }
 size_t bf16_buffer_bytes(gcq_context* ctx) {
   return bf_xg_bytes(ctx) + 256 + size_t(ctx->F.bf_levels) * ctx->n * ctx->L * sizeof(cpx<float>) + 256;
+}
+
+// the T' fill and the row kernels with KW 32-column tiles per wave
+template <int KW>
+static void enqueue_bf_kernels(gcq_context* ctx, hipStream_t st, const uint4* Xg, int* counter, cpx<float>* Ylev,
+                               int64_t lev_stride, const int* d_colpos) {
+  Faces3D& F = ctx->F;
+  const int n = ctx->n, L = ctx->L, ng = (n + 7) / 8, nkt = (L + 31) / 32;
+  const int waves = std::max(1, std::min(BF_WAVES / KW, (nkt + KW - 1) / KW));
+  const int* range = F.d_bfrange.as<int>();
+  if (F.bf_big > 0)
+    hipLaunchKernelGGL(bf_tfill<KW>, dim3(ctx->cus * 2), dim3(64 * waves), 0, st, F.d_bfbig.as<int>(),
+                       range + 3 * (BF_NX + 1), counter + 3 * BF_NX, F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(),
+                       F.d_bcol.as<int>(), F.d_cols.as<int64_t>(), F.slices.as<cpx<float>>(), d_colpos, L, ng, Xg,
+                       F.bftbuf.as<uint4>());
+  hipLaunchKernelGGL((bf_rows<false, KW>), dim3(ctx->cus * 2), dim3(64 * waves), 0, st, F.d_bfitems.as<BfItem>(),
+                     range, F.d_bfrowblk.as<int>(), F.d_cols.as<int64_t>(), F.d_bcol.as<int>(),
+                     F.slices.as<cpx<float>>(), F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), d_colpos, L, ng, Xg,
+                     F.bftbuf.as<uint4>(), Ylev, lev_stride, counter);
+  // row clusters above BF_MC rows: two tiles per wave in either case (measured
+  // faster, and one tile per wave with the T' prefetch does not fit 256 registers)
+  const int bwaves = std::max(1, std::min(BF_WAVES / 2, (nkt + 1) / 2));
+  hipLaunchKernelGGL((bf_rows<true, 2>), dim3(ctx->cus * 2), dim3(64 * bwaves), 0, st, F.d_bfitems.as<BfItem>(),
+                     range + BF_NX + 1, F.d_bfrowblk.as<int>(), F.d_cols.as<int64_t>(), F.d_bcol.as<int>(),
+                     F.slices.as<cpx<float>>(), F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), d_colpos, L, ng, Xg,
+                     F.bftbuf.as<uint4>(), Ylev, lev_stride, counter + BF_NX);
+  // near blocks: one tile per wave (two would not fit the registers: per-term
+  // and item accumulators of both tiles)
+  const int nwaves = std::min(BF_WAVES, nkt);
+  hipLaunchKernelGGL(bf_near<1>, dim3(ctx->cus * 2), dim3(64 * nwaves), 0, st, F.d_bfitems.as<BfItem>(),
+                     range + 2 * (BF_NX + 1), F.d_bfrowblk.as<int>(), F.d_bterm.as<int>(), F.d_tfoff.as<int64_t>(),
+                     F.slices.as<cpx<float>>(), F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), d_colpos, L, ng, Xg,
+                     Ylev, lev_stride, counter + 2 * BF_NX);
 }
 
 // kernels of one product on stream st (no allocation, no host transfer)
@@ -692,17 +938,10 @@ void enqueue_perfreq_bf16(gcq_context* ctx, hipStream_t st, const void* X, void*
   const int* perm = ctx->d_perm.as<int>();
   hipLaunchKernelGGL(bf_x_in, dim3(4096), dim3(256), 0, st, (const cpx<float>*)X, Xg, perm, d_conj, n, L, ng, nkt,
                      counter);
-  if (F.bf_big > 0)
-    hipLaunchKernelGGL(bf_tfill, dim3(std::min(F.bf_big, ctx->cus * 8)), dim3(256), 0, st, F.d_bfbig.as<int>(),
-                       F.bf_big, F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), F.d_bcol.as<int>(),
-                       F.d_cols.as<int64_t>(), F.slices.as<cpx<float>>(), d_colpos, L, ng, (const uint4*)Xg,
-                       F.bftbuf.as<uint4>());
-  const int waves = std::min(4, nkt);
-  hipLaunchKernelGGL(bf_rows, dim3(std::max(1, std::min(F.bf_items, ctx->cus * 8 / waves))), dim3(64 * waves), 0,
-                     st, F.d_bfitems.as<BfItem>(), F.bf_items, F.d_bfrowblk.as<int>(), ctx->d_blk.as<int>(),
-                     F.d_bterm.as<int>(), F.d_tfoff.as<int64_t>(), F.d_cols.as<int64_t>(), F.d_bcol.as<int>(),
-                     F.slices.as<cpx<float>>(), F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), d_colpos, L, ng,
-                     (const uint4*)Xg, F.bftbuf.as<uint4>(), Ylev, lev_stride, counter);
+  if (ctx->tune.product_cols_per_wave == 64)
+    enqueue_bf_kernels<2>(ctx, st, Xg, counter, Ylev, lev_stride, d_colpos);
+  else
+    enqueue_bf_kernels<1>(ctx, st, Xg, counter, Ylev, lev_stride, d_colpos);
   hipLaunchKernelGGL(bf_reduce_out, dim3(4096), dim3(256), 0, st, Ylev, lev_stride, F.d_bfmask.as<unsigned>(),
                      (cpx<float>*)Y, perm, d_conj, n, L);
 }

@@ -101,6 +101,12 @@ def test_tuning_roundtrip_and_rejection():
         ctx.set_tuning(aca3d_stack_slices=0)
     assert list(ctx.get_tuning().aca3d_waves) == [1, 1, 2, 4]
     assert ctx.get_tuning().aca3d_stack_slices == 2
+    assert ctx.get_tuning().product_cols_per_wave == 32
+    ctx.set_tuning(product_cols_per_wave=64)
+    assert ctx.get_tuning().product_cols_per_wave == 64
+    with pytest.raises(g.GcqError):
+        ctx.set_tuning(product_cols_per_wave=48)
+    assert ctx.get_tuning().product_cols_per_wave == 64
 
 
 def test_rank_features_match_oracle_definition():

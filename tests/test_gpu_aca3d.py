@@ -267,12 +267,15 @@ def test_aca3d_ranks_describe_the_storage(setup):
         assert len(ctx.get_aca3d_block(int(b), len(K), cap=max(1, st.rank_max))[0]) == terms[b]
 
 
-def test_split_bf16_product(setup):
+@pytest.mark.parametrize("cpw", [32, 64])
+def test_split_bf16_product(setup, cpw):
     """The split-bf16 per-frequency product (complex64 operator, operands as
     bf16 hi + lo planes, float accumulation) against the oracle's product of
-    its own 3D-ACA, per frequency; captured and replayed like the others."""
+    its own 3D-ACA, per frequency; captured and replayed like the others; 32
+    or 64 frequency columns per wave (16 columns here: one partial tile)."""
     xyz, tri, s, P, T, B, rep, conj, K, kpos, b3 = setup
     ctx = make_ctx(xyz, tri, 1.0, s, 32, 1.0)
+    ctx.set_tuning(product_cols_per_wave=cpw)
     ctx.aca3d(TOLA, TOLF, 40, g.C64)
     X = rhs.random_complex(len(s), P.n, 0)
     Xd = to_dev(X, g.C64).reshape(-1)
@@ -293,13 +296,19 @@ def test_split_bf16_product(setup):
         ctx.compressed_matvec(g.WEIGHTED_SUM, g.C64_SPLIT_BF16, Xd, Ybf[: P.n])
 
 
-def test_split_bf16_product_many_columns():
-    """256 frequencies (four 64-column chunks, conjugate symmetry) on a
-    3000-triangle finned housing: sampled rows of the split-bf16 product
-    against the float product and against dense oracle rows."""
+@pytest.mark.parametrize("cpw,L", [(32, 256), (64, 256), (64, 80)])
+def test_split_bf16_product_many_columns(cpw, L):
+    """256 frequencies (eight 32-column tiles, conjugate symmetry), and the
+    first 80 of them (a partial tile, and with 64 columns per wave a wave
+    whose second tile does not exist), on a 3000-triangle finned housing
+    (row clusters above 64 rows: far blocks through the T' buffer): sampled
+    rows of the split-bf16 product against the float product and against
+    dense oracle rows."""
     from synth import configs
-    cfg = configs.get("housing3k")
+    cfg = dict(configs.get("housing3k"))
+    cfg["s"] = cfg["s"][:L]
     ctx = make_ctx(cfg["xyz"], cfg["tri"], cfg["c"], cfg["s"], cfg["leaf"], cfg["eta"])
+    ctx.set_tuning(product_cols_per_wave=cpw)
     ctx.aca3d(1e-6, 1e-6, 40, g.C64)
     L, n = len(cfg["s"]), len(cfg["tri"])
     X = rhs.random_complex(L, n, 0)
@@ -312,7 +321,7 @@ def test_split_bf16_product_many_columns():
     per = np.linalg.norm(yb - y6, axis=1) / np.linalg.norm(y6, axis=1)
     assert per.max() <= 2e-5, per.max()
     rows = rhs.sample_rows(n, 24, 0)
-    kk = np.array([0, 1, 63, 64, 127, 128, 129, 191, 192, 255])
+    kk = np.array([k for k in (0, 1, 63, 64, 79, 127, 128, 129, 191, 192, 255) if k < L])
     A = entries.block(Panels(cfg["xyz"], cfg["tri"]), rows, np.arange(n), cfg["s"][kk], cfg["c"])
     ref = np.einsum("kij,kj->ki", A, X[kk])
     per = np.linalg.norm(yb[kk][:, rows] - ref, axis=1) / np.linalg.norm(ref, axis=1)
