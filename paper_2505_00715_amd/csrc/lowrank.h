@@ -662,33 +662,59 @@ __device__ __attribute__((always_inline)) inline int recompress_wave(int k, int 
 }
 
 // ---- Ubar = U CU (m x t), Vbar = conj(W) CV (n x t), column-major outputs ----------
+// A thread owns one row of U (or W) and APPLY_COLS output columns: it reads the
+// row once per APPLY_COLS columns (the coefficients are the same for all lanes
+// of a wave, so they come as broadcasts); each output sums over x in the same
+// order as a per-element loop would.
+constexpr int APPLY_COLS = 8;
 template <typename T>
 __device__ inline void apply_factors(int k, int t, int m, int n, const cpx<T>* U, const cpx<T>* W,
                                      const cpx<double>* CU, const cpx<double>* CV, cpx<T>* OU,
                                      cpx<T>* OV, int tid, int nthreads) {
-  const int64_t total = int64_t(m + n) * t;
+  const int rows = m + n;
+  const int nch = (t + APPLY_COLS - 1) / APPLY_COLS;
+  const int64_t total = int64_t(rows) * nch;
   for (int64_t e = tid; e < total; e += nthreads) {
-    if (e < int64_t(m) * t) {
-      const int c = int(e / m), r = int(e % m);
-      cpx<double> acc = {0, 0};
+    const int r = int(e % rows), c0 = int(e / rows) * APPLY_COLS;
+    const int nc = min(APPLY_COLS, t - c0);
+    double are[APPLY_COLS], aim[APPLY_COLS];
+#pragma unroll
+    for (int q = 0; q < APPLY_COLS; ++q) are[q] = aim[q] = 0.0;
+    if (r < m) {
       for (int x = 0; x < k; ++x) {
-        cpx<T> u = U[int64_t(x) * m + r];
-        cpx<double> cu = CU[x * t + c];
-        acc.re += double(u.re) * cu.re - double(u.im) * cu.im;
-        acc.im += double(u.re) * cu.im + double(u.im) * cu.re;
+        const cpx<T> u = U[int64_t(x) * m + r];
+        const double ur = double(u.re), ui = double(u.im);
+#pragma unroll
+        for (int q = 0; q < APPLY_COLS; ++q) {
+          if (q >= nc) break;
+          const cpx<double> cu = CU[x * t + c0 + q];
+          are[q] += ur * cu.re - ui * cu.im;
+          aim[q] += ur * cu.im + ui * cu.re;
+        }
       }
-      OU[int64_t(c) * m + r] = {T(acc.re), T(acc.im)};
+#pragma unroll
+      for (int q = 0; q < APPLY_COLS; ++q) {
+        if (q >= nc) break;
+        OU[int64_t(c0 + q) * m + r] = {T(are[q]), T(aim[q])};
+      }
     } else {
-      const int64_t e2 = e - int64_t(m) * t;
-      const int c = int(e2 / n), j = int(e2 % n);
-      cpx<double> acc = {0, 0};
+      const int j = r - m;
       for (int x = 0; x < k; ++x) {
-        cpx<T> w = W[int64_t(x) * n + j];  // V[j][x] = conj(w)
-        cpx<double> cv = CV[x * t + c];
-        acc.re += double(w.re) * cv.re + double(w.im) * cv.im;
-        acc.im += double(w.re) * cv.im - double(w.im) * cv.re;
+        const cpx<T> w = W[int64_t(x) * n + j];   // V[j][x] = conj(w)
+        const double wr = double(w.re), wi = double(w.im);
+#pragma unroll
+        for (int q = 0; q < APPLY_COLS; ++q) {
+          if (q >= nc) break;
+          const cpx<double> cv = CV[x * t + c0 + q];
+          are[q] += wr * cv.re + wi * cv.im;
+          aim[q] += wr * cv.im - wi * cv.re;
+        }
       }
-      OV[int64_t(c) * n + j] = {T(acc.re), T(acc.im)};
+#pragma unroll
+      for (int q = 0; q < APPLY_COLS; ++q) {
+        if (q >= nc) break;
+        OV[int64_t(c0 + q) * n + j] = {T(are[q]), T(aim[q])};
+      }
     }
   }
 }
