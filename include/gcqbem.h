@@ -468,6 +468,56 @@ GCQ_API int gcq_get_aca3d_block(gcq_context* ctx, int32_t block, int32_t cap, in
  *   blocks values (GCQ_ERR_ARG otherwise); GCQ_ERR_STATE before gcq_aca3d. */
 GCQ_API int gcq_aca3d_ranks(gcq_context* ctx, int32_t* terms, int32_t* columns, int64_t n);
 
+/* ---- FMM-based 3D-ACA (Sec. 4: the face by a black-box FMM, eq. cheb) --------
+ * gcq_fmm3d: the FMM-based variant of the 3D-ACA on the context's partition.
+ *   The far field of an admissible block (X, Y) is the Chebyshev
+ *   interpolation of the kernel in both clusters' boxes (eq. cheb):
+ *     A_XY(s) ~ L_X K_XY(s) R_Y^T,  L_X[i, n] = S_X(x_i, x_n),
+ *     R_Y[j, m] = sum_q w_jq S_Y(y_jq, y_m) (the far 7-point rule),
+ *     K_XY(s)[n, m] = exp(-s r / c) / (4 pi r), r = |x_n - y_m|,
+ *   with `order` Chebyshev nodes (the zeros of T_order) per dimension in each
+ *   cluster's vertex box (a half-width below 1e-3 of the box's largest is
+ *   raised to that), nodes numbered n = a_x + p a_y + p^2 a_z.  Only the M2L
+ *   operators K_XY(s) depend on the frequency: Alg. 1 (eq. norm, tolerance
+ *   tol, at most max_freq_rank terms) compresses each admissible block's
+ *   tensor [K_XY(s_k)]_k over the frequencies of K with dense p^3 x p^3
+ *   slices; inadmissible blocks as in gcq_aca3d.  order 1..6; precision
+ *   GCQ_C128 or GCQ_C64.  The context's 3D-ACA operator is replaced: until
+ *   gcq_aca3d runs again, gcq_compressed_matvec, gcq_solve, gcq_sample_rows and
+ *   the gCQ calls return GCQ_ERR_STATE.  stats may be NULL. */
+typedef struct {
+  int32_t n_far;          /* admissible blocks, i.e. M2L tensors */
+  int32_t rank_max;       /* most terms of an M2L tensor */
+  double rank_mean;       /* mean terms of the M2L tensors */
+  int32_t n_capped;       /* M2L tensors that reached max_freq_rank */
+  int64_t storage_bytes;  /* M2L slices and fibers, interpolation and transfer
+                             tables, near-field slices and fibers */
+  double device_ms;       /* device time of the build */
+  double m2l_ms;          /* of which the M2L entries and their 3D-ACA */
+} gcq_fmm3d_stats;
+GCQ_API int gcq_fmm3d(gcq_context* ctx, int32_t order, double tol, int32_t max_freq_rank,
+                      int32_t precision, gcq_fmm3d_stats* stats);
+
+/* gcq_fmm3d_matvec: Y[k] = V~(s_k) X[k] for every frequency with the operator
+ *   of gcq_fmm3d: the near blocks as gcq_compressed_matvec (GCQ_PER_FREQUENCY)
+ *   applies them, then the far field added by the multi-level evaluation
+ *   P2M (R^T at the leaves), M2M, M2L (sum_d f_d[k] H_d), L2L, L2P (L at the
+ *   leaves), which equals the single-level form above up to rounding (a
+ *   parent's Lagrange polynomials are interpolated exactly by a son's nodes).
+ *   X_dev, Y_dev: device arrays of L x n complex values in gcq_fmm3d's
+ *   precision, frequency-major, caller's triangle order (GCQ_ERR_ARG for
+ *   host memory); GCQ_ERR_STATE before gcq_fmm3d or after a gcq_aca3d. */
+GCQ_API int gcq_fmm3d_matvec(gcq_context* ctx, const void* X_dev, void* Y_dev);
+
+/* gcq_get_fmm3d_block: host copy of admissible block `block`'s M2L 3D-ACA:
+ *   *rank terms, freqs (positions in K), fibers (rank x |K| complex128) and
+ *   slices (rank x p^3 x p^3 complex128, column-major: entry (n, m) at
+ *   m p^3 + n, n a node of the row cluster's box, m of the column
+ *   cluster's).  Buffers hold cap terms (GCQ_ERR_ARG otherwise); freqs,
+ *   fibers, slices may be NULL. */
+GCQ_API int gcq_get_fmm3d_block(gcq_context* ctx, int32_t block, int32_t cap, int32_t* rank,
+                                int32_t* freqs, gcq_c128* fibers, gcq_c128* slices);
+
 /* gcq_sample_rows: rows of the compressed 3D array at frequency `freq`
  *   (0..n_freq-1): out[a][j] = V~(s_freq)[rows[a], j] for every column j,
  *   V~(s) = sum_b sum_d f_{b,d}(s) H_{b,d} the approximant of Alg. 1 that the

@@ -45,6 +45,12 @@ class Aca3dStats(C.Structure):
                 ("far_entries", C.c_int64), ("far_flops", C.c_double), ("far_ms", C.c_double)]
 
 
+class Fmm3dStats(C.Structure):
+    _fields_ = [("n_far", C.c_int32), ("rank_max", C.c_int32), ("rank_mean", C.c_double),
+                ("n_capped", C.c_int32), ("storage_bytes", C.c_int64), ("device_ms", C.c_double),
+                ("m2l_ms", C.c_double)]
+
+
 class SolveStats(C.Structure):
     _fields_ = [("n_systems", C.c_int32), ("n_converged", C.c_int32), ("iters_max", C.c_int32),
                 ("resid_max", C.c_double), ("device_ms", C.c_double)]
@@ -107,6 +113,9 @@ def _load():
         "gcq_aca3d": [P, D, D, I32, I32, U32, P],
         "gcq_get_aca3d_block": [P, I32, I32, P, P, P, P],
         "gcq_aca3d_ranks": [P, P, P, I64],
+        "gcq_fmm3d": [P, I32, D, I32, I32, P],
+        "gcq_fmm3d_matvec": [P, P, P],
+        "gcq_get_fmm3d_block": [P, I32, I32, P, P, P, P],
         "gcq_compressed_matvec": [P, I32, I32, P, P, I32],
         "gcq_sample_rows": [P, P, I32, I32, P],
         "gcq_solve": [P, P, P, D, I32, I32, I32, P],
@@ -400,6 +409,42 @@ class Context:
                                         sl.ctypes.data_as(C.c_void_p)))
         r = rank.value
         # slices: (r, m, n) row-major view of the column-major storage
+        return freqs[:r].copy(), fib[:r].copy(), np.transpose(sl[:r], (0, 2, 1)).copy()
+
+    # ---- FMM-based 3D-ACA
+    def fmm3d(self, order: int, tol: float, max_freq_rank: int, precision: int) -> Fmm3dStats:
+        """Chebyshev interpolation of `order` nodes per dimension on the far
+        blocks, their M2L operators compressed over the frequencies (Alg. 1)."""
+        st = Fmm3dStats()
+        _check(_lib.gcq_fmm3d(self._h, int(order), float(tol), int(max_freq_rank), precision, C.byref(st)))
+        self.fmm_order = int(order)
+        self.fmm_precision = precision
+        return st
+
+    def fmm3d_matvec(self, X, Y):
+        """Y[k] = V~(s_k) X[k] with the FMM-based operator (device tensors of
+        L x n complex values in the precision of fmm3d)."""
+        import torch
+        dt = torch.complex128 if getattr(self, "fmm_precision", C64) == C128 else torch.complex64
+        px = _dev(X, dt, self.L * self.n, "X")
+        py = _dev(Y, dt, self.L * self.n, "Y")
+        _check(_lib.gcq_fmm3d_matvec(self._h, px, py))
+        return Y
+
+    def get_fmm3d_block(self, block: int, nK: int, cap: int = 64):
+        """(freqs, fibers (r, |K|), slices (r, p^3, p^3) row-major) of a far
+        block's M2L 3D-ACA."""
+        np3 = self.fmm_order ** 3
+        rank = C.c_int32()
+        freqs = np.zeros(cap, np.int32)
+        fib = np.zeros((cap, nK), np.complex128)
+        sl = np.zeros((cap, np3, np3), np.complex128)
+        _check(_lib.gcq_get_fmm3d_block(self._h, int(block), cap, C.byref(rank),
+                                        freqs.ctypes.data_as(C.c_void_p),
+                                        fib.ctypes.data_as(C.c_void_p),
+                                        sl.ctypes.data_as(C.c_void_p)))
+        r = rank.value
+        # column-major p^3 x p^3 slices: the stored array is the transpose
         return freqs[:r].copy(), fib[:r].copy(), np.transpose(sl[:r], (0, 2, 1)).copy()
 
     # ---- products and solve

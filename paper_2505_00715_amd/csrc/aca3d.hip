@@ -12,27 +12,6 @@
 
 namespace gcq {
 
-constexpr int R3_MAX = 64;      // terms per block the kernel can hold
-constexpr int NK_MAX = 2048;    // frequencies in K
-
-struct BlockDesc3 {
-  int rb, m, cb, n;
-  int admissible, all_far;
-  int sres;        // admissible: columns reserved for the block's stacked slice factors
-  int pad;
-};
-
-// A term of a block.  Far blocks keep their slices' factors stacked: the
-// block reserves U columns (m x sres) and V columns (n x sres) in the pool,
-// and slice d owns columns [c_d, c_d + rank_d) of both.
-struct Term3 {
-  int64_t slice;   // pool offset (elements) of the slice: dense m x n, or its first Ubar column
-  int64_t vslice;  // far: pool offset of its first Vbar column
-  int64_t fiber;   // pool offset of the fiber (nK elements)
-  int rank;        // slice rank (far) or -1 (dense)
-  int freq;        // position in K of the frequency the slice was taken at
-};
-
 // LDS of the far kernel per group size NW (waves per block).  One area serves
 // three uses that never overlap in time: the residual coefficients of the
 // slice ACA (RES of them: the sum of the accepted slices' ranks; a block whose
@@ -808,6 +787,23 @@ static int ensure_side_streams(gcq_context* ctx) {
   return GCQ_OK;
 }
 
+// Alg. 1 with dense slices on a batch of precomputed tensors: block b =
+// ids[qlist[i]] with descriptor desc[b] (m x n), its tensor at
+// Cn[k * stride + off[qlist[i]] - base0 + e], terms into terms[b * R3_MAX + d]
+void launch_dense_aca3d(int precision, int grid, hipStream_t st, const BlockDesc3* desc, const int* qlist,
+                        int nq, const int* ids, const int64_t* off, int64_t base0, const void* Cn,
+                        int64_t stride, int nK, double tol, int rmax, void* pool, unsigned long long* cursor,
+                        int64_t capacity, Term3* terms, int* brank, int* bstatus, int* counter) {
+  if (precision == GCQ_C128)
+    hipLaunchKernelGGL(aca3d_near_kernel<double>, dim3(grid), dim3(64), 0, st, desc, qlist, nq, ids, off, base0,
+                       static_cast<const cpx<double>*>(Cn), stride, nK, tol, rmax, static_cast<cpx<double>*>(pool),
+                       cursor, capacity, terms, brank, bstatus, counter);
+  else
+    hipLaunchKernelGGL(aca3d_near_kernel<float>, dim3(grid), dim3(64), 0, st, desc, qlist, nq, ids, off, base0,
+                       static_cast<const cpx<float>*>(Cn), stride, nK, tol, rmax, static_cast<cpx<float>*>(pool),
+                       cursor, capacity, terms, brank, bstatus, counter);
+}
+
 }  // namespace gcq
 
 using namespace gcq;
@@ -815,6 +811,15 @@ using namespace gcq;
 extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
                                  int32_t max_freq_rank, int32_t precision, uint32_t flags,
                                  gcq_aca3d_stats* stats) {
+  return gcq::aca3d_run(ctx, tol_aca, tol, max_freq_rank, precision, flags & GCQ_FLAG_DOUBLE_LAYER, false, stats);
+}
+
+namespace gcq {
+
+// the 3D-ACA of the partition; near_only: admissible blocks get no terms
+// (the FMM-based variant compresses their M2L operators instead)
+int aca3d_run(gcq_context* ctx, double tol_aca, double tol, int32_t max_freq_rank, int32_t precision,
+              uint32_t flags, bool near_only, gcq_aca3d_stats* stats) {
   const bool dlp = (flags & GCQ_FLAG_DOUBLE_LAYER) != 0;
   if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
   GCQ_NEED_DEVICE(ctx);
@@ -834,6 +839,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   F.precision = precision;
   F.dlp = dlp;
   F.nK = nK;
+  F.near_only = near_only;
   const int nb = int(ctx->blocks.size());
   std::vector<BlockDesc3> bd(nb);
   int maxm = 0, maxmn = 0;
@@ -889,7 +895,7 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   GCQ_HIP(hipMemGetInfo(&freeb, &totalb));
   int64_t near_elems = 0, far_stack = 0;
   for (int b = 0; b < nb; ++b)
-    if (bd[b].admissible) far_stack += int64_t(bd[b].m + bd[b].n) * bd[b].sres;
+    if (bd[b].admissible) far_stack += near_only ? 0 : int64_t(bd[b].m + bd[b].n) * bd[b].sres;
     else near_elems += int64_t(bd[b].m) * bd[b].n;
   // expected need: dense slices (near) of ~max_freq_rank/2 terms each, the far
   // blocks' stack reservations, plus one fiber per term
@@ -938,7 +944,11 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
                           ctx->H.near_slot_elems == ctx->near_total && ctx->H.near.p != nullptr;
   std::vector<int> opos(nb);
   for (int i = 0; i < nb; ++i) opos[order[i]] = i;
-  std::vector<int> todo = order;
+  std::vector<int> todo;
+  for (int b : order)
+    if (!(near_only && bd[b].admissible)) todo.push_back(b);
+  // blocks left out keep rank 0
+  hipLaunchKernelGGL(zero_int_3d, dim3((2 * nb + 63) / 64), dim3(64), 0, ctx->stream, d_rank, 2 * nb);
   for (int round = 0; round < 8 && !todo.empty(); ++round) {
     hipLaunchKernelGGL(zero_int_3d, dim3(1), dim3(64), 0, ctx->stream, d_counter, 16);
     unsigned long long cur0 = (unsigned long long)used;
@@ -1230,6 +1240,8 @@ extern "C" GCQ_API int gcq_aca3d(gcq_context* ctx, double tol_aca, double tol,
   }
   return ncap > 0 ? GCQ_RANK_CAPPED : GCQ_OK;
 }
+
+}  // namespace gcq
 
 extern "C" GCQ_API int gcq_aca3d_ranks(gcq_context* ctx, int32_t* terms, int32_t* columns, int64_t n) {
   if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");

@@ -278,6 +278,8 @@ static int gcq_prepare(gcq_context* ctx, const double* A, int m, const double* d
     return fail(GCQ_ERR_ARG, "unknown precision %d", precision);
   if (!ctx->F.valid || ctx->F.precision != precision)
     return fail(GCQ_ERR_STATE, "run gcq_aca3d at this precision first");
+  if (ctx->F.near_only)
+    return fail(GCQ_ERR_STATE, "the 3D operator holds only the near field of the FMM-based variant");
   R.L = ctx->L;
   R.n = ctx->n;
   R.m = m;

@@ -165,6 +165,7 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
   if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
   GCQ_NEED_DEVICE(ctx);
   if (!ctx->F.valid) return fail(GCQ_ERR_STATE, "run gcq_aca3d first");
+  if (ctx->F.near_only) return fail(GCQ_ERR_STATE, "the 3D operator holds only the near field of the FMM-based variant: use gcq_fmm3d_matvec");
   if (storage_precision(precision) != ctx->F.precision)
     return fail(GCQ_ERR_ARG, "precision differs from the one the 3D-ACA was built in");
   if (!(rtol > 0.0) || restart < 1 || restart > 200 || max_iter < 0)

@@ -64,7 +64,7 @@ double timed_end(gcq_context* ctx, const char* name) {
 
 // ---- constant tables ------------------------------------------------------------
 // 7-point degree-5 rule on the triangle (Radon): centroid and two orbits of 3.
-static void radon7(double b[7][3], double w[7]) {
+void radon7(double b[7][3], double w[7]) {
   const double sq = std::sqrt(15.0);
   const double a = (6.0 - sq) / 21.0, bb = (6.0 + sq) / 21.0;
   const double wa = (155.0 - sq) / 1200.0, wb = (155.0 + sq) / 1200.0;
@@ -741,6 +741,7 @@ GCQ_API int gcq_trim(gcq_context* ctx, int32_t release_faces) {
   ctx->F.bfpool.release();
   ctx->F.bftbuf.release();
   ctx->F.pxy.release();
+  ctx->Mf.release_work();
   if (release_faces) {
     HFaces& H = ctx->H;
     H.valid = false;

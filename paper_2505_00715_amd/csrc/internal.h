@@ -84,6 +84,28 @@ struct Block {
   bool all_far;      // no self or near-tier pair inside (guaranteed by box distance)
 };
 
+// ---- 3D-ACA work descriptors (shared by the ACA-based and the FMM-based variants) ----
+constexpr int R3_MAX = 64;      // terms per block the kernel can hold
+constexpr int NK_MAX = 2048;    // frequencies in K
+
+struct BlockDesc3 {
+  int rb, m, cb, n;
+  int admissible, all_far;
+  int sres;        // admissible: columns reserved for the block's stacked slice factors
+  int pad;
+};
+
+// A term of a block.  Far blocks keep their slices' factors stacked: the
+// block reserves U columns (m x sres) and V columns (n x sres) in the pool,
+// and slice d owns columns [c_d, c_d + rank_d) of both.
+struct Term3 {
+  int64_t slice;   // pool offset (elements) of the slice: dense m x n, or its first Ubar column
+  int64_t vslice;  // far: pool offset of its first Vbar column
+  int64_t fiber;   // pool offset of the fiber (nK elements)
+  int rank;        // slice rank (far) or -1 (dense)
+  int freq;        // position in K of the frequency the slice was taken at
+};
+
 // ---- per-frequency H-matrices (aca_blocks) ---------------------------------------------
 struct HFaces {
   bool valid = false;
@@ -148,6 +170,7 @@ struct Faces3D {
   // tables (position in K, conjugation flag); fixed while the operator lives
   DevBuf pxy, pmeta;
   bool meta_valid = false;       // pmeta holds the current frequency set's tables
+  bool near_only = false;        // only inadmissible blocks hold terms (near field of the FMM-based variant)
   // the operator's slices split into bf16 planes for GCQ_C64_SPLIT_BF16
   // products (built on first use, per block table d_bfblk)
   DevBuf bfpool, bftbuf, d_bfblk, d_bfitems, d_bfrange, d_bfrowblk, d_bfbig, d_bfmask;
@@ -177,6 +200,45 @@ struct RankModel {
   std::vector<float> params;     // 4609
   float mean[5] = {0, 0, 0, 0, 0}, stdv[5] = {1, 1, 1, 1, 1};
   DevBuf d_params;
+};
+
+// the 3D-ACA of the partition (gcq_aca3d); near_only: admissible blocks get
+// no terms (the FMM-based variant compresses their M2L operators instead)
+int aca3d_run(gcq_context* ctx, double tol_aca, double tol, int32_t max_freq_rank, int32_t precision,
+              uint32_t flags, bool near_only, gcq_aca3d_stats* stats);
+// Alg. 1 with dense slices on a batch of precomputed tensors (aca3d.hip)
+void launch_dense_aca3d(int precision, int grid, hipStream_t st, const BlockDesc3* desc, const int* qlist,
+                        int nq, const int* ids, const int64_t* off, int64_t base0, const void* Cn,
+                        int64_t stride, int nK, double tol, int rmax, void* pool, unsigned long long* cursor,
+                        int64_t capacity, Term3* terms, int* brank, int* bstatus, int* counter);
+// the 7-point rule of the far field on the reference triangle: barycentric
+// points and weights (summing to 1)
+void radon7(double b[7][3], double w[7]);
+
+// ---- FMM-based 3D-ACA (gcq_fmm3d) -----------------------------------------------------
+struct Fmm3D {
+  bool valid = false;
+  int p = 0, np3 = 0, precision = GCQ_C64, nK = 0, nfar = 0;
+  int nitems = 0, nzero = 0, nleaves = 0;
+  // M2L 3D-ACA of the far blocks (ctx->far_ids order): terms fstart[f] ..
+  // fstart[f + 1], each a dense np3 x np3 slice and a fiber in pool
+  std::vector<int> fstart, ffreq;
+  std::vector<int64_t> fslice, ffiber;
+  DevBuf pool;
+  DevBuf d_fstart, d_fslice, d_ffiber, d_fcol, d_rowlist, d_items, d_zlist;
+  // tree tables: leaves, cluster ranges, sons, parents, clusters by depth
+  DevBuf d_leaves, d_clbeg, d_clend, d_son0, d_son1, d_parent, d_uplist, d_downlist, d_conj, d_kpos;
+  std::vector<int> lev_start, down_start;
+  // interpolation: R and L per position (leaf box), transfer into the parent per cluster
+  DevBuf d_R, d_L, d_T;
+  // product work buffers: permuted input, multipole and local expansions
+  DevBuf Xp, W, Z;
+  int64_t table_bytes = 0, m2l_bytes = 0;
+  void release_work() {
+    Xp.release();
+    W.release();
+    Z.release();
+  }
 };
 
 }  // namespace gcq
@@ -236,6 +298,7 @@ struct gcq_context {
   gcq::HFaces H;
   gcq::Faces3D F;
   gcq::RankModel M;
+  gcq::Fmm3D Mf;
 
   // scratch
   gcq::DevBuf scratchA, scratchB, scratchC, scratchD;

@@ -192,6 +192,7 @@ extern "C" GCQ_API int gcq_compressed_matvec(gcq_context* ctx, int32_t mode, int
   }
   if (mode == GCQ_PER_FREQUENCY || mode == GCQ_WEIGHTED_SUM) {
     if (!ctx->F.valid) return fail(GCQ_ERR_STATE, "run gcq_aca3d first");
+    if (ctx->F.near_only) return fail(GCQ_ERR_STATE, "the 3D operator holds only the near field of the FMM-based variant: use gcq_fmm3d_matvec");
     return run_compressed(ctx, mode, precision, X_dev, Y_dev);
   }
   return fail(GCQ_ERR_ARG, "unknown mode %d", mode);

@@ -75,6 +75,7 @@ extern "C" GCQ_API int gcq_sample_rows(gcq_context* ctx, const int32_t* rows, in
   if (!ctx) return fail(GCQ_ERR_ARG, "ctx is NULL");
   GCQ_NEED_DEVICE(ctx);
   if (!ctx->F.valid) return fail(GCQ_ERR_STATE, "run gcq_aca3d first");
+  if (ctx->F.near_only) return fail(GCQ_ERR_STATE, "the 3D operator holds only the near field of the FMM-based variant: use gcq_fmm3d_matvec");
   if (n_rows < 0) return fail(GCQ_ERR_ARG, "n_rows must be >= 0");
   if (n_rows == 0) return GCQ_OK;
   if (!rows) return fail(GCQ_ERR_ARG, "rows is NULL");
