@@ -101,6 +101,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch parameters")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner's cache")
+    ap.add_argument("--fmm", type=int, default=0, metavar="ORDER",
+                    help="after the timed steps, build the FMM-based 3D-ACA of this order on the same "
+                         "partition and report its build, storage, product time and accuracy (0: off)")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device to device (a reference kernel of "
                          "known traffic for hardware counter runs)")
@@ -508,6 +511,32 @@ def main():
                                 "unit": "TFLOP/s",
                                 "frac": aca_ops / (med("aca_k") / 1e3) / 1e12 / FP32_PEAK_TFLOPS},
     }
+    if args.fmm:
+        # the FMM-based variant (Chebyshev interpolation of the far field, M2L
+        # operators compressed over the frequencies) on the same partition,
+        # tolerance and frequencies; it replaces the ACA-based operator
+        ctx.trim(release_faces=False)
+        fs = ctx.fmm3d(args.fmm, tol, 40, g.C64)
+        Yf = torch.zeros_like(Xd)
+        tn, tf, tw = [], [], []
+        for _ in range(4):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ctx.fmm3d_matvec(Xd, Yf)
+            torch.cuda.synchronize()
+            tw.append((time.perf_counter() - t1) * 1e3)
+            tn.append(ctx.kernel_ms("matvec_perfreq"))
+            tf.append(ctx.kernel_ms("fmm3d_far"))
+        Yfm = Yf.cpu().numpy().reshape(L, n).astype(np.complex128)
+        per_f = np.linalg.norm(Yfm[kk][:, rows] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+        out["fmm3d"] = {"order": args.fmm, "tol": tol, "build_ms": fs.device_ms, "m2l_build_ms": fs.m2l_ms,
+                        "m2l_rank_mean": fs.rank_mean, "m2l_rank_max": fs.rank_max, "m2l_capped": fs.n_capped,
+                        "storage_GB": fs.storage_bytes / 1e9,
+                        "product_ms": float(np.median(tw)), "near_ms": float(np.median(tn)),
+                        "far_ms": float(np.median(tf)),
+                        "rel_err_per_freq_max": float(per_f.max()),
+                        "note": "same rows and frequencies as rel_err_matvec_per_freq"}
+        say(f"[bench] fmm3d order {args.fmm}: {json.dumps(out['fmm3d'])}")
     if not args.no_cpu_baseline:
         allc, one = cpu_baseline(args.config)
         out["cpu_baseline"] = allc
