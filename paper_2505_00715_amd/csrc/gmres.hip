@@ -1,7 +1,13 @@
 // Batched restarted GMRES over all frequencies at once: V(s_k) x_k = b_k, the
 // operator being the 3D-ACA compressed product.  Krylov bases, inner products
-// and classical Gram-Schmidt (applied twice) in float64; the small Hessenberg
-// least-squares problems (Givens rotations, back substitution) on the host.
+// and classical Gram-Schmidt (applied twice) in float64.  With graphs enabled
+// (the default) one Arnoldi step -- the product, both Gram-Schmidt passes, the
+// new basis vector, the Hessenberg column with its Givens rotations and the
+// residual estimate of every column -- runs on the device with the step
+// index j read from device memory, captured once per solve and replayed; the
+// host only reads the number of unconverged columns after each step.  Without
+// graphs the small least-squares problems are solved on the host (the
+// reference path).
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -155,6 +161,233 @@ struct Solver {
   }
 };
 
+// ---- device-side Arnoldi step (step index j = *dj) ---------------------------------
+
+__global__ void gm_to32_j(const zc* __restrict__ V, const int* __restrict__ dj, cpx<float>* __restrict__ o,
+                          int64_t total) {
+  const zc* a = V + int64_t(*dj) * total;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x)
+    o[e] = {float(a[e].re), float(a[e].im)};
+}
+
+__global__ void gm_copy_j(const zc* __restrict__ V, const int* __restrict__ dj, zc* __restrict__ o, int64_t total) {
+  const zc* a = V + int64_t(*dj) * total;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x)
+    o[e] = a[e];
+}
+
+// gm_dots over the first *dj + 1 basis vectors (the grid covers the most)
+__global__ void __launch_bounds__(256) gm_dots_j(const zc* __restrict__ V, const zc* __restrict__ w,
+                                                 const int* __restrict__ dj, int L, int n, zc* __restrict__ h) {
+  __shared__ double sr[8], si[8];
+  const int nc = *dj + 1;
+  const int c = blockIdx.x / L, k = blockIdx.x % L;
+  if (c >= nc) return;
+  const zc* v = V + (int64_t(c) * L + k) * n;
+  const zc* x = w + int64_t(k) * n;
+  double ar = 0, ai = 0;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    zc a = v[p], b = x[p];
+    ar += a.re * b.re + a.im * b.im;
+    ai += a.re * b.im - a.im * b.re;
+  }
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  const int wv = threadIdx.x / WAVE;
+  if ((threadIdx.x & (WAVE - 1)) == 0) { sr[wv] = ar; si[wv] = ai; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tr = 0, ti = 0;
+    for (int q = 0; q < int(blockDim.x / WAVE); ++q) { tr += sr[q]; ti += si[q]; }
+    h[int64_t(c) * L + k] = {tr, ti};
+  }
+}
+
+__global__ void gm_sub_j(const zc* __restrict__ V, zc* __restrict__ w, const zc* __restrict__ h,
+                         const int* __restrict__ dj, int L, int n) {
+  const int nc = *dj + 1;
+  const int64_t total = int64_t(L) * n;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int k = int(e / n);
+    zc acc = w[e];
+    for (int c = 0; c < nc; ++c) {
+      zc p = cmul(V[int64_t(c) * total + e], h[int64_t(c) * L + k]);
+      acc.re -= p.re;
+      acc.im -= p.im;
+    }
+    w[e] = acc;
+  }
+}
+
+// per column k: the Hessenberg column j (the two Gram-Schmidt passes' sums and
+// the new vector's norm), the earlier Givens rotations applied to it, a new
+// rotation that zeroes its subdiagonal, the rotated right-hand side g and the
+// residual estimate |g[j + 1]|; the scale of the next basis vector; the number
+// of unconverged columns into *active.  H: [k][row][col] (m + 1) x m
+__global__ void gm_givens(const int* __restrict__ dj, const zc* __restrict__ h1, const zc* __restrict__ h2,
+                          const double* __restrict__ nrm, zc* __restrict__ H, double* __restrict__ cs,
+                          zc* __restrict__ sn, zc* __restrict__ g, int* __restrict__ done,
+                          int* __restrict__ iters, const double* __restrict__ bn, double rtol,
+                          double* __restrict__ scale, int* __restrict__ active, int m, int L) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= L) return;
+  const int j = *dj;
+  zc* Hk = H + int64_t(k) * (m + 1) * m;
+  double* csk = cs + int64_t(k) * m;
+  zc* snk = sn + int64_t(k) * m;
+  zc* gk = g + int64_t(k) * (m + 1);
+  for (int c = 0; c <= j; ++c) {
+    const zc a = h1[int64_t(c) * L + k], b = h2[int64_t(c) * L + k];
+    Hk[c * m + j] = {a.re + b.re, a.im + b.im};
+  }
+  const double hn = sqrt(nrm[k]);
+  Hk[(j + 1) * m + j] = {hn, 0.0};
+  for (int i = 0; i < j; ++i) {
+    const zc hi = Hk[i * m + j], hi1 = Hk[(i + 1) * m + j];
+    const zc s = snk[i];
+    // t = c h_i + s h_{i+1};  h_{i+1} = -conj(s) h_i + c h_{i+1}
+    const zc t = {csk[i] * hi.re + (s.re * hi1.re - s.im * hi1.im), csk[i] * hi.im + (s.re * hi1.im + s.im * hi1.re)};
+    const zc u = {-(s.re * hi.re + s.im * hi.im) + csk[i] * hi1.re, -(s.re * hi.im - s.im * hi.re) + csk[i] * hi1.im};
+    Hk[(i + 1) * m + j] = u;
+    Hk[i * m + j] = t;
+  }
+  const zc a = Hk[j * m + j], bb = Hk[(j + 1) * m + j];
+  const double na = sqrt(a.re * a.re + a.im * a.im), nb = sqrt(bb.re * bb.re + bb.im * bb.im);
+  const double den = sqrt(na * na + nb * nb);
+  double c;
+  zc sv;
+  if (den == 0.0) {
+    c = 1.0;
+    sv = {0.0, 0.0};
+  } else if (na == 0.0) {
+    c = 0.0;
+    sv = {bb.re / nb, -bb.im / nb};
+  } else {
+    c = na / den;
+    // (a / |a|) conj(b) / den
+    const zc ph = {a.re / na, a.im / na};
+    sv = {(ph.re * bb.re + ph.im * bb.im) / den, (ph.im * bb.re - ph.re * bb.im) / den};
+  }
+  csk[j] = c;
+  snk[j] = sv;
+  Hk[j * m + j] = {c * a.re + (sv.re * bb.re - sv.im * bb.im), c * a.im + (sv.re * bb.im + sv.im * bb.re)};
+  Hk[(j + 1) * m + j] = {0.0, 0.0};
+  const zc gj = gk[j];
+  gk[j + 1] = {-(sv.re * gj.re + sv.im * gj.im), -(sv.re * gj.im - sv.im * gj.re)};
+  gk[j] = {c * gj.re, c * gj.im};
+  int dk = done[k];
+  if (!dk) {
+    iters[k] += 1;
+    const double r = sqrt(gk[j + 1].re * gk[j + 1].re + gk[j + 1].im * gk[j + 1].im);
+    if (r <= rtol * bn[k] || hn == 0.0) dk = 2;
+    done[k] = dk;
+  }
+  scale[k] = hn > 0 ? 1.0 / hn : 0.0;
+  if (!dk) atomicAdd(active, 1);
+}
+
+__global__ void gm_scale_j(const zc* __restrict__ a, zc* __restrict__ V, const int* __restrict__ dj,
+                           const double* __restrict__ s, int L, int n) {
+  const int64_t total = int64_t(L) * n;
+  zc* out = V + int64_t(*dj + 1) * total;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const double f = s[e / n];
+    out[e] = {a[e].re * f, a[e].im * f};
+  }
+}
+
+// start of a step: the unconverged count starts at 0
+__global__ void gm_begin_step(int* __restrict__ active) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *active = 0;
+}
+
+// end of a step: j + 1
+__global__ void gm_next_j(int* __restrict__ dj) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dj += 1;
+}
+
+// back substitution per column over the first jdone rows: y[c * L + k]
+__global__ void gm_backsub(const zc* __restrict__ H, const zc* __restrict__ g, const double* __restrict__ beta,
+                           const double* __restrict__ bn, int jdone, int m, int L, zc* __restrict__ y) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= L) return;
+  const zc* Hk = H + int64_t(k) * (m + 1) * m;
+  const zc* gk = g + int64_t(k) * (m + 1);
+  const bool act = beta[k] > 0 && !(bn[k] == 0.0);
+  for (int i = jdone - 1; i >= 0; --i) {
+    zc acc = act ? gk[i] : zc{0.0, 0.0};
+    if (act)
+      for (int c = i + 1; c < jdone; ++c) {
+        const zc p = cmul(Hk[i * m + c], y[int64_t(c) * L + k]);
+        acc.re -= p.re;
+        acc.im -= p.im;
+      }
+    const zc d = Hk[i * m + i];
+    const double dd = d.re * d.re + d.im * d.im;
+    y[int64_t(i) * L + k] = (act && dd > 0) ? zc{(acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd}
+                                            : zc{0.0, 0.0};
+  }
+}
+
+__global__ void gm_zero_d(double* p, int64_t cnt) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < cnt; e += int64_t(gridDim.x) * blockDim.x)
+    p[e] = 0.0;
+}
+
+// device state of the graph path
+struct DevState {
+  zc *H = nullptr, *sn = nullptr, *g = nullptr, *h2 = nullptr;
+  double *cs = nullptr, *bn = nullptr, *beta = nullptr, *scale = nullptr;
+  int *done = nullptr, *iters = nullptr, *dj = nullptr, *active = nullptr;
+  int* host_active = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+// one Arnoldi step (reads j = *D.dj) captured into D.exec
+static int capture_step(gcq_context* ctx, Solver& S, DevState& D, zc* V, int m, double rtol) {
+  Faces3D& F = ctx->F;
+  if (!F.graphs.cap) GCQ_HIP(hipStreamCreateWithFlags(&F.graphs.cap, hipStreamNonBlocking));
+  hipStream_t cs = F.graphs.cap;
+  const int L = S.L, n = S.n;
+  const int64_t total = S.total;
+  const dim3 G(2048), Bk(256);
+  hipGraph_t graph = nullptr;
+  GCQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(gm_begin_step, dim3(1), dim3(64), 0, cs, D.active);
+  if (S.precision == GCQ_C128) {
+    zc* tmp = reinterpret_cast<zc*>(S.t32);
+    hipLaunchKernelGGL(gm_copy_j, G, Bk, 0, cs, V, D.dj, tmp, total);
+    enqueue_perfreq_any(ctx, cs, S.precision, tmp, S.w);
+  } else {
+    hipLaunchKernelGGL(gm_to32_j, G, Bk, 0, cs, V, D.dj, S.t32, total);
+    enqueue_perfreq_any(ctx, cs, S.precision, S.t32, S.t32 + total);
+    hipLaunchKernelGGL(gm_from32, G, Bk, 0, cs, S.t32 + total, S.w, total);
+  }
+  hipLaunchKernelGGL(gm_dots_j, dim3((m + 1) * L), Bk, 0, cs, V, S.w, D.dj, L, n, S.h);
+  hipLaunchKernelGGL(gm_sub_j, G, Bk, 0, cs, V, S.w, S.h, D.dj, L, n);
+  hipLaunchKernelGGL(gm_dots_j, dim3((m + 1) * L), Bk, 0, cs, V, S.w, D.dj, L, n, D.h2);
+  hipLaunchKernelGGL(gm_sub_j, G, Bk, 0, cs, V, S.w, D.h2, D.dj, L, n);
+  hipLaunchKernelGGL(gm_norm2, dim3(L), Bk, 0, cs, S.w, n, S.nrm);
+  hipLaunchKernelGGL(gm_givens, dim3((L + 255) / 256), Bk, 0, cs, D.dj, S.h, D.h2, S.nrm, D.H, D.cs, D.sn, D.g,
+                     D.done, D.iters, D.bn, rtol, D.scale, D.active, m, L);
+  hipLaunchKernelGGL(gm_scale_j, G, Bk, 0, cs, S.w, V, D.dj, D.scale, L, n);
+  hipLaunchKernelGGL(gm_next_j, dim3(1), dim3(64), 0, cs, D.dj);
+  const hipError_t ce = hipGetLastError();
+  GCQ_HIP(hipStreamEndCapture(cs, &graph));
+  if (ce != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(GCQ_ERR_HIP, "capture of the Arnoldi step failed: %s", hipGetErrorString(ce));
+  }
+  const hipError_t ie = hipGraphInstantiate(&D.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(GCQ_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+  return GCQ_OK;
+}
+
 }  // namespace gcq
 
 using namespace gcq;
@@ -213,6 +446,44 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
   double* d_scale = dscale.as<double>();
   zc* d_y = reinterpret_cast<zc*>(d_scale + L);
   int total_iters = 0;
+  // device-side Arnoldi step, replayed as a graph (tuning product_graph)
+  const bool use_graph = ctx->tune.product_graph != 0;
+  DevState D;
+  DevBuf dstate;
+  int* pinned_active = nullptr;
+  if (use_graph) {
+    GCQ_TRY(prepare_perfreq(ctx, precision));
+    const size_t zc_n = size_t(L) * (m + 1) * m + size_t(L) * m + size_t(L) * (m + 1) + size_t(m + 1) * L;
+    // eleven arrays, each rounded up to 256 bytes
+    const size_t bytes = zc_n * sizeof(zc) + sizeof(double) * (size_t(L) * m + 2 * L) + sizeof(int) * (2 * L + 2) + 11 * 256;
+    GCQ_TRY(dstate.ensure(bytes));
+    unsigned char* q = dstate.as<unsigned char>();
+    auto take = [&](size_t b) { unsigned char* r = q; q += (b + 255) & ~size_t(255); return r; };
+    D.H = reinterpret_cast<zc*>(take(sizeof(zc) * size_t(L) * (m + 1) * m));
+    D.sn = reinterpret_cast<zc*>(take(sizeof(zc) * size_t(L) * m));
+    D.g = reinterpret_cast<zc*>(take(sizeof(zc) * size_t(L) * (m + 1)));
+    D.h2 = reinterpret_cast<zc*>(take(sizeof(zc) * size_t(m + 1) * L));
+    D.cs = reinterpret_cast<double*>(take(sizeof(double) * size_t(L) * m));
+    D.bn = reinterpret_cast<double*>(take(sizeof(double) * L));
+    D.beta = reinterpret_cast<double*>(take(sizeof(double) * L));
+    D.done = reinterpret_cast<int*>(take(sizeof(int) * L));
+    D.iters = reinterpret_cast<int*>(take(sizeof(int) * L));
+    D.dj = reinterpret_cast<int*>(take(sizeof(int)));
+    D.active = reinterpret_cast<int*>(take(sizeof(int)));
+    D.scale = d_scale;
+    GCQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned_active), sizeof(int), hipHostMallocDefault));
+    D.host_active = pinned_active;
+    GCQ_HIP(hipMemcpyAsync(D.bn, bn.data(), sizeof(double) * L, hipMemcpyHostToDevice, st));
+    GCQ_HIP(hipMemsetAsync(D.iters, 0, sizeof(int) * L, st));
+  }
+  struct Cleanup {
+    DevState* d;
+    int* pinned;
+    ~Cleanup() {
+      if (d->exec) (void)hipGraphExecDestroy(d->exec);
+      if (pinned) (void)hipHostFree(pinned);
+    }
+  } cleanup{&D, pinned_active};
   while (true) {
     // r = b - A x into V_0
     GCQ_TRY(S.apply(x, S.w));
@@ -229,6 +500,33 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
     for (int k = 0; k < L; ++k) scale[k] = beta[k] > 0 ? 1.0 / beta[k] : 0.0;
     GCQ_HIP(hipMemcpyAsync(d_scale, scale.data(), sizeof(double) * L, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(gm_scale, G, Bk, 0, st, V, V, d_scale, L, n);
+    if (use_graph) {
+      // per restart: right-hand sides g = beta e_1, Hessenberg zero, flags, j = 0
+      std::vector<zc> g0(size_t(L) * (m + 1), zc{0.0, 0.0});
+      for (int k = 0; k < L; ++k) g0[size_t(k) * (m + 1)] = {beta[k], 0.0};
+      std::vector<int> dn(done.begin(), done.end());
+      GCQ_HIP(hipMemcpyAsync(D.g, g0.data(), sizeof(zc) * g0.size(), hipMemcpyHostToDevice, st));
+      GCQ_HIP(hipMemcpyAsync(D.done, dn.data(), sizeof(int) * L, hipMemcpyHostToDevice, st));
+      GCQ_HIP(hipMemcpyAsync(D.beta, beta.data(), sizeof(double) * L, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(gm_zero_d, G, Bk, 0, st, reinterpret_cast<double*>(D.H), int64_t(L) * (m + 1) * m * 2);
+      GCQ_HIP(hipMemsetAsync(D.dj, 0, sizeof(int), st));
+      if (!D.exec) GCQ_TRY(capture_step(ctx, S, D, V, m, rtol));
+      int jdone = 0;
+      for (int j = 0; j < m; ++j) {
+        GCQ_HIP(hipGraphLaunch(D.exec, st));
+        int act = 0;
+        GCQ_HIP(hipMemcpyAsync(D.host_active, D.active, sizeof(int), hipMemcpyDeviceToHost, st));
+        GCQ_HIP(hipStreamSynchronize(st));
+        act = *D.host_active;
+        ++total_iters;
+        jdone = j + 1;
+        if (act == 0 || total_iters >= max_iter) break;
+      }
+      hipLaunchKernelGGL(gm_backsub, dim3((L + 255) / 256), Bk, 0, st, D.H, D.g, D.beta, D.bn, jdone, m, L, d_y);
+      hipLaunchKernelGGL(gm_update, G, Bk, 0, st, V, x, d_y, jdone, L, n);
+      GCQ_HIP(hipGetLastError());
+      continue;
+    }
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     for (int k = 0; k < L; ++k) g[size_t(k) * (m + 1)] = beta[k];
@@ -318,6 +616,7 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
   (void)hipEventDestroy(e1);
   const double ms = msf;
   ctx->kernel_ms["solve"] = ms;
+  if (use_graph) GCQ_HIP(hipMemcpy(iters.data(), D.iters, sizeof(int) * L, hipMemcpyDeviceToHost));
   int nconv = 0, imax = 0;
   double rmax = 0;
   for (int k = 0; k < L; ++k) {

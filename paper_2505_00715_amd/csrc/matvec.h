@@ -6,6 +6,10 @@
 namespace gcq {
 // mode GCQ_PER_FREQUENCY or GCQ_WEIGHTED_SUM; X, Y in the caller's layout
 int run_compressed(gcq_context* ctx, int mode, int precision, const void* X, void* Y);
+// the per-frequency product split for capture: buffers and tables first, then
+// its kernels on a stream (no allocation, no host transfer)
+int prepare_perfreq(gcq_context* ctx, int precision);
+void enqueue_perfreq_any(gcq_context* ctx, hipStream_t s, int precision, const void* X, void* Y);
 // split-bf16 per-frequency product (matvec_bf16.hip): the operator's bf16
 // copy (once per operator), the size of the product's buffers (ctx->F.pxy),
 // and the product's kernels on a stream (capturable: no allocation)

@@ -668,6 +668,29 @@ static int compressed_impl(gcq_context* ctx, int mode, int precision, const void
   return GCQ_OK;
 }
 
+// the per-frequency product's buffers and tables, ahead of a capture
+int prepare_perfreq(gcq_context* ctx, int precision) {
+  if (ctx->F.precision != storage_precision(precision))
+    return fail(GCQ_ERR_ARG, "precision differs from the one the 3D-ACA was built in");
+  const int n = ctx->n, L = ctx->L;
+  if (precision == GCQ_C64_SPLIT_BF16) {
+    GCQ_TRY(bf16_setup(ctx));
+    return product_setup(ctx, bf16_buffer_bytes(ctx));
+  }
+  return product_setup(ctx, size_t(2) * n * L * (precision == GCQ_C128 ? 16 : 8));
+}
+
+// the per-frequency product's kernels on stream s (no allocation, no host
+// transfer: capturable after prepare_perfreq)
+void enqueue_perfreq_any(gcq_context* ctx, hipStream_t s, int precision, const void* X, void* Y) {
+  if (precision == GCQ_C64_SPLIT_BF16)
+    enqueue_perfreq_bf16(ctx, s, X, Y);
+  else if (precision == GCQ_C128)
+    enqueue_perfreq<double>(ctx, s, precision, X, Y);
+  else
+    enqueue_perfreq<float>(ctx, s, precision, X, Y);
+}
+
 int run_compressed(gcq_context* ctx, int mode, int precision, const void* X, void* Y) {
   if (ctx->F.precision != storage_precision(precision))
     return fail(GCQ_ERR_ARG, "precision differs from the one the 3D-ACA was built in");

@@ -43,6 +43,35 @@ def test_gmres_all_frequencies(prec, rtol):
         assert res <= 2 * rtol + 1e-8 + pert, (res, pert)
 
 
+@pytest.mark.parametrize("prec", [g.C128, g.C64, g.C64_SPLIT_BF16])
+def test_gmres_graph_step_matches_host_path(prec):
+    """The device-side Arnoldi step replayed as a graph (default) against the
+    host's least-squares path (graphs off): both converge in the same number
+    of iterations (restart 6: several restart cycles and graph replays per
+    cycle) to the same solutions, and the graph solve repeated gives the
+    same result again (to rounding where the product's sums are ordered by
+    atomics)."""
+    xyz, tri = mesh.icosphere(2)
+    s = freq.bdf2_circle(8, 0.05, 1e-8 ** (1 / 8))
+    ctx = make_ctx(xyz, tri, 1.0, s, 16, 1.0)
+    ctx.aca3d(1e-10, 1e-10, 40, g.C64 if prec == g.C64_SPLIT_BF16 else prec)
+    rtol = 1e-9 if prec == g.C128 else 1e-6      # complex64 products: float rounding
+    B = to_dev(rhs.random_complex(len(s), 320, 2), g.C128).reshape(-1)
+    out = {}
+    for graph in (1, 0, 1):
+        ctx.set_tuning(product_graph=graph)
+        X = torch.zeros_like(B)
+        st = ctx.solve(B, X, rtol=rtol, max_iter=200, restart=6, precision=prec)
+        assert st.status == g.OK and st.n_converged == len(s)
+        out.setdefault(graph, []).append((st.iters_max, from_dev(X).reshape(len(s), 320)))
+    (ig, xg), (ig2, xg2) = out[1]
+    ih, xh = out[0][0]
+    assert abs(ig - ih) <= 1, (ig, ih)
+    assert rel(xg, xh) <= 100 * rtol
+    # the float product adds its blocks with atomics (order-dependent rounding)
+    assert ig2 == ig and rel(xg2, xg) <= (1e-12 if prec == g.C128 else 10 * rtol)
+
+
 def test_gmres_not_converged_flag():
     xyz, tri = mesh.icosphere(2)
     s = freq.bdf2_circle(8, 0.05, 1e-8 ** (1 / 8))
