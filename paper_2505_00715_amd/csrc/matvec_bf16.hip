@@ -624,77 +624,59 @@ __global__ void __launch_bounds__(KW == 1 ? 512 : 256) bf_rows(
 }
 
 // near blocks of the product: work items (rows of a row cluster, all its
-// inadmissible blocks), waves as in bf_rows; Y += f_d o (D_d X_J) per term,
-// each right-hand side fragment serving every row tile and each operator
-// fragment every tile of the wave; plain stores into the near-field buffer
-// (the level after the tree's deepest)
-template <int KW>
-__global__ void __launch_bounds__(KW == 1 ? 512 : 256) bf_near(
+// inadmissible blocks); each wave owns one 32-row tile and one 32-column
+// frequency tile (BF_WAVES x BF_RT waves: registers for one row tile only, so
+// four waves fit a SIMD); Y += f_d o (D_d X_J) per term; plain stores into the
+// near-field buffer (the level after the tree's deepest)
+__global__ void __launch_bounds__(BF_WAVES * BF_RT * 64) bf_near(
     const BfItem* __restrict__ items, const int* __restrict__ range, const int* __restrict__ rowblk,
     const int* __restrict__ bterm, const int64_t* __restrict__ tfoff, const cpx<float>* __restrict__ pool,
     const BfBlock* __restrict__ bb, const uint4* __restrict__ bfp, const int* __restrict__ colpos, int L, int ng,
-    const uint4* __restrict__ Xg, cpx<float>* __restrict__ Ylev, int64_t lev_stride, int* __restrict__ counter) {
+    const uint4* __restrict__ Xg, cpx<float>* __restrict__ Ylev, int64_t lev_stride, int* __restrict__ counter,
+    int wk) {
   __shared__ int cur;
   const int lane = threadIdx.x & 63, lr = lane & 31, lh = lane >> 5;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wrt = w / wk, wkt = w % wk;   // the wave's row tile and first frequency tile
   const int nkt = (L + 31) >> 5;
   int visited = 0;
   for (int it; (it = next_item(range, counter, blockIdx.x % BF_NX, visited, &cur)) >= 0;) {
     const BfItem I = items[it];
     const int nrt = (I.rows + 31) >> 5;
-    const int rt0 = I.r0 >> 5;
-    for (int kt0 = w * KW; kt0 < nkt; kt0 += nw * KW) {
-      const Tiles<KW> C(kt0, nkt, L, lr, ng, colpos, Xg);
-      f16v yre[KW][BF_RT], yim[KW][BF_RT];
-#pragma unroll
-      for (int u = 0; u < KW; ++u)
-#pragma unroll
-        for (int rt = 0; rt < BF_RT; ++rt) yre[u][rt] = yim[u][rt] = f16_zero();
+    if (wrt >= nrt) continue;   // (next_item's barriers are reached by every wave)
+    const int rt = (I.r0 >> 5) + wrt;
+    for (int kt = wkt; kt < nkt; kt += wk) {
+      const Tiles<1> C(kt, nkt, L, lr, ng, colpos, Xg);
+      f16v yre = f16_zero(), yim = f16_zero();
       for (int bi = 0; bi < I.nb; ++bi) {
         const int b = rowblk[I.b0 + bi];
         const BfBlock B = bb[b];
         const uint4* op = bfp + B.off * FRAG;
         const int d0 = bterm[b], nd = bterm[b + 1] - d0;
         for (int d = 0; d < nd; ++d) {
-          f16v tre[KW][BF_RT], tim[KW][BF_RT];
-#pragma unroll
-          for (int u = 0; u < KW; ++u)
-#pragma unroll
-            for (int rt = 0; rt < BF_RT; ++rt) tre[u][rt] = tim[u][rt] = f16_zero();
-          const uint4* df = op + int64_t(d) * B.mt * B.KS * FRAG;
-#pragma unroll 1
+          f16v tre = f16_zero(), tim = f16_zero();
+          const uint4* df = op + (int64_t(d) * B.mt + rt) * B.KS * FRAG;
           for (int j = 0; j < B.KS; ++j) {
             const int g = 2 * j + lh;
-            BfGroup3 x[KW];
-#pragma unroll
-            for (int u = 0; u < KW; ++u)
-              x[u] = (g < B.G && C.kv[u]) ? load_x(C.xk[u], B.g0 + g, lr) : zero_group3();
-#pragma unroll
-            for (int rt = 0; rt < BF_RT; ++rt) {
-              if (rt >= nrt) break;
-              const BfGroup a = load_op(df + (int64_t(rt0 + rt) * B.KS + j) * FRAG, lane);
-#pragma unroll
-              for (int u = 0; u < KW; ++u) cstep2(a, x[u], tre[u][rt], tim[u][rt]);
-            }
+            const BfGroup3 x = (g < B.G && C.kv[0]) ? load_x(C.xk[0], B.g0 + g, lr) : zero_group3();
+            cstep2(load_op(df + int64_t(j) * FRAG, lane), x, tre, tim);
           }
+          const cpx<float> f = C.kin[0] ? pool[tfoff[d0 + d] + C.kp[0]] : cpx<float>{0.f, 0.f};
 #pragma unroll
-          for (int u = 0; u < KW; ++u) {
-            const cpx<float> f = C.kin[u] ? pool[tfoff[d0 + d] + C.kp[u]] : cpx<float>{0.f, 0.f};
-#pragma unroll
-            for (int rt = 0; rt < BF_RT; ++rt) {
-              if (rt >= nrt) break;
-#pragma unroll
-              for (int r = 0; r < 16; ++r) {
-                yre[u][rt][r] += f.re * tre[u][rt][r] - f.im * tim[u][rt][r];
-                yim[u][rt][r] += f.re * tim[u][rt][r] + f.im * tre[u][rt][r];
-              }
-            }
+          for (int r = 0; r < 16; ++r) {
+            yre[r] += f.re * tre[r] - f.im * tim[r];
+            yim[r] += f.re * tim[r] + f.im * tre[r];
           }
         }
       }
+      if (C.kin[0]) {
+        cpx<float>* yl = Ylev + I.lev * lev_stride;
 #pragma unroll
-      for (int u = 0; u < KW; ++u)
-        if (C.kin[u]) store_rows<BF_RT>(yre[u], yim[u], nrt, I, lh, C.kcol[u], L, Ylev + I.lev * lev_stride);
+        for (int r = 0; r < 16; ++r) {
+          const int row = 32 * wrt + 8 * (r >> 2) + 4 * lh + (r & 3);
+          if (row < I.rows) yl[int64_t(I.rb + I.r0 + row) * L + C.kcol[0]] = {yre[r], yim[r]};
+        }
+      }
     }
   }
 }
@@ -909,19 +891,19 @@ static void enqueue_bf_kernels(gcq_context* ctx, hipStream_t st, const uint4* Xg
                      F.slices.as<cpx<float>>(), F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), d_colpos, L, ng, Xg,
                      F.bftbuf.as<uint4>(), Ylev, lev_stride, counter);
   // row clusters above BF_MC rows: two tiles per wave in either case (measured
-  // faster, and one tile per wave with the T' prefetch does not fit 256 registers)
+  // faster, and one tile per wave with the T' prefetch does not fit 256 registers;
+  // one row tile per wave on 64-row items reads the T' buffer more: slower)
   const int bwaves = std::max(1, std::min(BF_WAVES / 2, (nkt + 1) / 2));
   hipLaunchKernelGGL((bf_rows<true, 2>), dim3(ctx->cus * 2), dim3(64 * bwaves), 0, st, F.d_bfitems.as<BfItem>(),
                      range + BF_NX + 1, F.d_bfrowblk.as<int>(), F.d_cols.as<int64_t>(), F.d_bcol.as<int>(),
-                     F.slices.as<cpx<float>>(), F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), d_colpos, L, ng, Xg,
-                     F.bftbuf.as<uint4>(), Ylev, lev_stride, counter + BF_NX);
-  // near blocks: one tile per wave (two would not fit the registers: per-term
-  // and item accumulators of both tiles)
-  const int nwaves = std::min(BF_WAVES, nkt);
-  hipLaunchKernelGGL(bf_near<1>, dim3(ctx->cus * 2), dim3(64 * nwaves), 0, st, F.d_bfitems.as<BfItem>(),
+                     F.slices.as<cpx<float>>(), F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), d_colpos, L, ng,
+                     Xg, F.bftbuf.as<uint4>(), Ylev, lev_stride, counter + BF_NX);
+  // near blocks: one frequency tile and one row tile per wave
+  const int nwk = std::min(BF_WAVES, nkt);
+  hipLaunchKernelGGL(bf_near, dim3(ctx->cus * 2), dim3(64 * nwk * BF_RT), 0, st, F.d_bfitems.as<BfItem>(),
                      range + 2 * (BF_NX + 1), F.d_bfrowblk.as<int>(), F.d_bterm.as<int>(), F.d_tfoff.as<int64_t>(),
                      F.slices.as<cpx<float>>(), F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), d_colpos, L, ng, Xg,
-                     Ylev, lev_stride, counter + 2 * BF_NX);
+                     Ylev, lev_stride, counter + 2 * BF_NX, nwk);
 }
 
 // kernels of one product on stream st (no allocation, no host transfer)
