@@ -445,7 +445,7 @@ __device__ __forceinline__ void store_t(uint4* __restrict__ f, const BfGroup3& a
 // KW tiles
 constexpr int BF_TG = 2;
 template <int KW>
-__global__ void __launch_bounds__(KW == 1 ? 512 : 256) bf_tfill(
+__global__ void __launch_bounds__(KW == 1 ? 512 : 256, KW == 1 ? 4 : 1) bf_tfill(
     const int* __restrict__ big, const int* __restrict__ range, int* __restrict__ counter,
     const BfBlock* __restrict__ bb, const uint4* __restrict__ bfp,
     const int* __restrict__ bcol, const int64_t* __restrict__ cols, const cpx<float>* __restrict__ pool,
