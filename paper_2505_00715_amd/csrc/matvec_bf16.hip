@@ -424,7 +424,8 @@ __device__ __forceinline__ int next_item(const int* __restrict__ range, int* __r
     *cur = got;
   }
   __syncthreads();
-  return *cur;
+  // wave-uniform: the item's and its blocks' descriptors then live in scalar registers
+  return __builtin_amdgcn_readfirstlane(*cur);
 }
 
 __device__ __forceinline__ void store_t(uint4* __restrict__ f, const BfGroup3& a) {
