@@ -85,29 +85,65 @@ static void launch_aca(bool dlp, int nw, int grid, hipStream_t st, Args... args)
     launch_aca_op<T, AF, false>(nw, grid, st, args...);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64) recompress_kernel(const PairDesc* __restrict__ pairs,
-                                                        int npairs, unsigned char* __restrict__ ws,
-                                                        const int* __restrict__ rank_in,
-                                                        int* __restrict__ out_t, double tol,
-                                                        int do_recompress, unsigned char* __restrict__ jws) {
-  __shared__ cpx<double> mats[4 * 16 * 16];
-  __shared__ RecompShared rs;
+// recompression of the pairs whose ACA rank k lies in (kmin, kmax], kmax <= MK:
+// one group of NW waves per pair, its working matrices in LDS sized for MK
+// terms (GL: in the group's slice of global scratch instead), so that groups
+// of small ranks fit many to a compute unit
+template <typename T, int MK, int NW, bool GL>
+__global__ void __launch_bounds__(NW * 64) recompress_kernel(const PairDesc* __restrict__ pairs,
+                                                             int npairs, unsigned char* __restrict__ ws,
+                                                             const int* __restrict__ rank_in,
+                                                             int* __restrict__ out_t, double tol,
+                                                             int do_recompress, unsigned char* __restrict__ jws,
+                                                             int kmin, int kmax) {
+  __shared__ cpx<double> mats[GL ? 1 : recompress_mats(MK)];
+  __shared__ RecompSharedT<MK> rs;
+  cpx<double>* M = GL ? reinterpret_cast<cpx<double>*>(jws) + int64_t(blockIdx.x) * recompress_mats(MK) : mats;
   for (int pid = blockIdx.x; pid < npairs; pid += gridDim.x) {
+    const int k = rank_in[pid];
+    if (k <= kmin || k > kmax) continue;
     __syncthreads();
     const PairDesc d = pairs[pid];
-    const int k = rank_in[pid], cap = d.cap;
+    const int cap = d.cap;
     cpx<double>* GU = reinterpret_cast<cpx<double>*>(ws + d.ws + ws_gram_off<T>(cap, d.m, d.n));
-    // working matrices in LDS when they fit, else in global memory (two call
-    // sites, so that the LDS one compiles to LDS instructions)
-    int t;
-    if (recompress_mats(k) <= 4 * 16 * 16)
-      t = recompress_wave(k, cap, GU, GU + cap * cap, tol, 0.0, do_recompress != 0, mats, rs);
-    else
-      t = recompress_wave(k, cap, GU, GU + cap * cap, tol, 0.0, do_recompress != 0,
-                          reinterpret_cast<cpx<double>*>(jws) + int64_t(blockIdx.x) * 4 * 64 * 64, rs);
+    const int t = recompress_grp<NW>(k, cap, GU, GU + cap * cap, tol, 0.0, do_recompress != 0, M, rs);
     if (threadIdx.x == 0) out_t[pid] = t;
   }
+}
+
+// the recompression of one chunk: a launch per rank class, the classes spread
+// over the context stream and the three side streams so that they run
+// together (a class of few large pairs takes about one pair's latency, which
+// the classes holding most pairs then cover)
+constexpr int RECOMP_GL_GRID = 4096;   // groups of the class whose matrices are in global scratch
+template <typename T>
+static int launch_recompress(gcq_context* ctx, int nc, const PairDesc* pairs, unsigned char* ws,
+                             const int* rank, int* t, double tol, int rec, unsigned char* jws) {
+  GCQ_TRY(ensure_side_streams(ctx));
+  hipStream_t st = ctx->stream;
+  GCQ_HIP(hipEventRecord(ctx->evfork, st));
+  for (int i = 0; i < 3; ++i) GCQ_HIP(hipStreamWaitEvent(ctx->side[i], ctx->evfork, 0));
+  const int g = std::min(nc, 8192);
+  hipLaunchKernelGGL((recompress_kernel<T, 64, 4, true>), dim3(std::min(nc, RECOMP_GL_GRID)), dim3(256), 0,
+                     ctx->side[0], pairs, nc, ws, rank, t, tol, rec, jws, 32, 64);
+  hipLaunchKernelGGL((recompress_kernel<T, 32, 4, false>), dim3(g), dim3(256), 0, ctx->side[0], pairs, nc, ws,
+                     rank, t, tol, rec, jws, 24, 32);
+  hipLaunchKernelGGL((recompress_kernel<T, 24, 2, false>), dim3(g), dim3(128), 0, ctx->side[0], pairs, nc, ws,
+                     rank, t, tol, rec, jws, 18, 24);
+  hipLaunchKernelGGL((recompress_kernel<T, 18, 2, false>), dim3(g), dim3(128), 0, ctx->side[1], pairs, nc, ws,
+                     rank, t, tol, rec, jws, 16, 18);
+  hipLaunchKernelGGL((recompress_kernel<T, 16, 2, false>), dim3(g), dim3(128), 0, st, pairs, nc, ws, rank, t, tol,
+                     rec, jws, 12, 16);
+  hipLaunchKernelGGL((recompress_kernel<T, 12, 1, false>), dim3(g), dim3(64), 0, ctx->side[2], pairs, nc, ws, rank,
+                     t, tol, rec, jws, 8, 12);
+  hipLaunchKernelGGL((recompress_kernel<T, 8, 1, false>), dim3(g), dim3(64), 0, ctx->side[2], pairs, nc, ws,
+                     rank, t, tol, rec, jws, -1, 8);
+  GCQ_HIP(hipGetLastError());
+  for (int i = 0; i < 3; ++i) {
+    GCQ_HIP(hipEventRecord(ctx->evjoin[i], ctx->side[i]));
+    GCQ_HIP(hipStreamWaitEvent(st, ctx->evjoin[i], 0));
+  }
+  return GCQ_OK;
 }
 
 // Ubar = U CU, Vbar = conj(W) CV into the compact pool
@@ -194,6 +230,8 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
     for (int a = 0; a < nc; ++a) nnf += cd[a].all_far == 0;
     const int nw = ctx->tune.aca_waves;
     const int grid = std::min(nc, dev_cus * 32 / nw);
+    // recompression scratch first: no allocation between the two timed parts
+    GCQ_TRY(ctx->scratchD.ensure(size_t(std::min(nc, RECOMP_GL_GRID)) * recompress_mats(64) * 16));
     GCQ_TRY(timed_begin(ctx));
     launch_aca<T, true>(ctx->H.dlp, nw, grid, st, ctx->tab(), (const PairDesc*)ctx->scratchB.as<PairDesc>(),
                         (const int*)nullptr, nc, ctx->scratchA.as<unsigned char>(), tol, max_rank,
@@ -204,16 +242,19 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
                            ctx->scratchA.as<unsigned char>(), tol, max_rank, d_rank, d_status,
                            d_counter + 1);
     GCQ_HIP(hipGetLastError());
-    ms_aca += timed_end(ctx, "aca");
-    // recompression; matrices above 32 terms live in global scratch
-    const int rgrid = std::min(nc, 4096);
-    GCQ_TRY(ctx->scratchD.ensure(size_t(rgrid) * 4 * 64 * 64 * 16));
-    GCQ_TRY(timed_begin(ctx));
-    hipLaunchKernelGGL(recompress_kernel<T>, dim3(rgrid), dim3(64), 0, st,
-                       ctx->scratchB.as<PairDesc>(), nc, ctx->scratchA.as<unsigned char>(),
-                       d_rank, d_t, tol, recompress ? 1 : 0, ctx->scratchD.as<unsigned char>());
+    // the recompression follows on the device without a host round trip; the
+    // split event divides the region between the two
+    GCQ_HIP(hipEventRecord(ctx->evm, st));
+    // recompression by rank classes; matrices above 32 terms live in global scratch
+    GCQ_TRY(launch_recompress<T>(ctx, nc, ctx->scratchB.as<PairDesc>(), ctx->scratchA.as<unsigned char>(), d_rank,
+                                 d_t, tol, recompress ? 1 : 0, ctx->scratchD.as<unsigned char>()));
     GCQ_HIP(hipGetLastError());
-    ms_rec += timed_end(ctx, "recompress");
+    {
+      double a = 0.0, r = 0.0;
+      GCQ_TRY(timed_end_split(ctx, "aca", "recompress", a, r));
+      ms_aca += a;
+      ms_rec += r;
+    }
     std::vector<int> hr(nc), hs(nc), ht(nc);
     GCQ_HIP(hipMemcpy(hr.data(), d_rank, sizeof(int) * nc, hipMemcpyDeviceToHost));
     GCQ_HIP(hipMemcpy(hs.data(), d_status, sizeof(int) * nc, hipMemcpyDeviceToHost));

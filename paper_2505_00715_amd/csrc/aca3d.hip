@@ -778,7 +778,7 @@ static void launch_near3(gcq_context* ctx, dim3 g1, dim3 g2, int q0, int q1, int
 }
 
 // side streams and fork/join events of the context, created on first use
-static int ensure_side_streams(gcq_context* ctx) {
+int ensure_side_streams(gcq_context* ctx) {
   if (!ctx->evfork) GCQ_HIP(hipEventCreateWithFlags(&ctx->evfork, hipEventDisableTiming));
   for (int i = 0; i < 3; ++i) {
     if (!ctx->side[i]) GCQ_HIP(hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking));

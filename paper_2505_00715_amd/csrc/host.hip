@@ -62,6 +62,20 @@ double timed_end(gcq_context* ctx, const char* name) {
   return ms;
 }
 
+int timed_end_split(gcq_context* ctx, const char* first, const char* second, double& ms_first,
+                    double& ms_second) {
+  float a = -1.f, b = -1.f;
+  GCQ_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+  GCQ_HIP(hipEventSynchronize(ctx->ev1));
+  GCQ_HIP(hipEventElapsedTime(&a, ctx->ev0, ctx->evm));
+  GCQ_HIP(hipEventElapsedTime(&b, ctx->evm, ctx->ev1));
+  ctx->kernel_ms[first] = a;
+  ctx->kernel_ms[second] = b;
+  ms_first = a;
+  ms_second = b;
+  return GCQ_OK;
+}
+
 // ---- constant tables ------------------------------------------------------------
 // 7-point degree-5 rule on the triangle (Radon): centroid and two orbits of 3.
 void radon7(double b[7][3], double w[7]) {
@@ -321,7 +335,8 @@ GCQ_API int gcq_create(int device, void* hip_stream, gcq_context** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->cus = prop.multiProcessorCount;
   }
-  if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+  if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+      hipEventCreate(&ctx->evm) != hipSuccess) {
     delete ctx;
     return fail(GCQ_ERR_HIP, "hipEventCreate failed");
   }
@@ -351,6 +366,7 @@ GCQ_API int gcq_destroy(gcq_context* ctx) {
   else (void)hipDeviceSynchronize();
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->evm) (void)hipEventDestroy(ctx->evm);
   if (ctx->evfork) (void)hipEventDestroy(ctx->evfork);
   for (int i = 0; i < 3; ++i) {
     if (ctx->side[i]) {

@@ -207,6 +207,8 @@ struct RankModel {
 int aca3d_run(gcq_context* ctx, double tol_aca, double tol, int32_t max_freq_rank, int32_t precision,
               uint32_t flags, bool near_only, gcq_aca3d_stats* stats);
 // Alg. 1 with dense slices on a batch of precomputed tensors (aca3d.hip)
+// the context's side streams and fork/join events (created on first use)
+int ensure_side_streams(gcq_context* ctx);
 void launch_dense_aca3d(int precision, int grid, hipStream_t st, const BlockDesc3* desc, const int* qlist,
                         int nq, const int* ids, const int64_t* off, int64_t base0, const void* Cn,
                         int64_t stride, int nK, double tol, int rmax, void* pool, unsigned long long* cursor,
@@ -247,7 +249,7 @@ struct gcq_context {
   int device = 0;
   int cus = 256;   // compute units of the device
   hipStream_t stream = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;   // evm: a split point inside a timed region
   std::map<std::string, double> kernel_ms;
   // side streams (default priority) for concurrent work classes, created on
   // first use, and the events that fork from / join into `stream`
@@ -332,6 +334,10 @@ int check_device_ptr(gcq_context* ctx, const void* p, const char* what);
 int noalloc_scratch_init(int device);
 int timed_begin(gcq_context* ctx);
 double timed_end(gcq_context* ctx, const char* name);
+// a timed region in two parts split at ctx->evm (recorded by the caller on the
+// context stream): the time of each part, under its name
+int timed_end_split(gcq_context* ctx, const char* first, const char* second, double& ms_first,
+                    double& ms_second);
 inline int csize(int precision) { return precision == GCQ_C128 ? 16 : 8; }
 // storage precision of a call's precision (split-bf16 products use complex64 data)
 inline int storage_precision(int precision) {

@@ -49,20 +49,25 @@ struct AcaShared {
   int nrows;   // rows evaluated by the last approximation
 };
 
-struct RecompShared {
-  double lam[64], sg[64];
-  int keep[64], order[64];
+// shared state of one recompression of at most MK terms
+template <int MK>
+struct RecompSharedT {
+  static constexpr int NP = (MK + 1) / 2;   // index pairs of a Jacobi round
+  double sg[MK];
+  int keep[MK], order[MK];
   int nkeep, tcut;
-  // one round of the parallel Jacobi ordering: pair i rotates (jp[i], jq[i])
-  // when jact[i] is set
-  int jp[32], jq[32], jact[32];
-  double jc[32], js[32], ja[32], jd[32], jtb[32];
-  cpx<double> je[32];
+  // one round of the parallel Jacobi ordering, per index pair i: the rotation
+  // {c, s, Re e, Im e} (the identity when the pair is not rotated), the new
+  // diagonal of the pair's 2 x 2 block, and the pair's indices p | q << 8
+  double4 rot[NP];
+  double2 dia[NP];
+  int pq[NP];
   double dmax;
 };
+using RecompShared = RecompSharedT<64>;
 
 // working memory of the recompression of k terms (complex doubles)
-__host__ __device__ inline int recompress_mats(int k) { return 3 * k * k; }
+__host__ __device__ constexpr int recompress_mats(int k) { return 3 * k * k; }
 
 // The reductions that end an ACA step, in one exchange: group sums of a and b
 // (per-thread partials), of c (a value each wave already holds summed), and
@@ -326,16 +331,19 @@ __device__ inline int aca_wave(Ent& ent, int m, int n, int cap, int max_rank, do
 // round-robin (tournament) ordering: every round rotates k/2 disjoint index
 // pairs at once, so a sweep is k - 1 parallel rounds instead of k (k - 1) / 2
 // sequential rotations.  Rotations of one round commute (disjoint pairs), so the
-// result equals the cyclic sweep in that pair order.  A round is two phases:
-// the rotation parameters, then G^H A G by 2 x 2 blocks (rows of pair i,
-// columns of pair j) together with Q G.  Sweeps stop when the off-diagonal
-// squared Frobenius norm is at most `thr` times the diagonal's.
+// result equals the cyclic sweep in that pair order.  A round is three phases:
+// the rotation parameters (a pair whose |b|^2 is below 1e-34 |a d| is not
+// rotated: its b is set to zero, a change below the rounding of a and d), then
+// G^H A G by 2 x 2 blocks (rows of pair i, columns of pair j) and Q G by rows,
+// each thread applying the rotations of its blocks without branches (the
+// identity for pairs not rotated).  Sweeps stop when the off-diagonal squared
+// Frobenius norm is at most `thr` times the diagonal's.
 // Always inlined: callers pass A and Q either in LDS or in global memory, and
 // the accesses compile to LDS instructions only where the pointer's origin is
 // visible.
-template <int NW>
+template <int NW, typename RS>
 __device__ __attribute__((always_inline)) inline void jacobi_grp(cpx<double>* A, cpx<double>* Q,
-                                                                 int k, RecompShared& rs, double thr) {
+                                                                 int k, RS& rs, double thr) {
   constexpr int NT = NW * WAVE;
   const int tid = threadIdx.x;
   for (int r = tid; r < k * k; r += NT) Q[r] = {(r / k == r % k) ? 1.0 : 0.0, 0.0};
@@ -343,10 +351,8 @@ __device__ __attribute__((always_inline)) inline void jacobi_grp(cpx<double>* A,
   if (k < 2) return;
   const int ke = (k + 1) & ~1;   // even number of positions (one dummy when k is odd)
   const int np = ke / 2;
-  // work items of the update phase: x = row np + j, row < np the 2 x 2 block
-  // (row, j) of A, row >= np row (row - np) of Q with pair j; a thread takes
-  // x = tid, tid + NT, ..., decomposed once and advanced with a carry
-  const int nitems = np * (np + k);
+  // work items of the update phases: (i, j) = (x / np, x % np) for x = tid,
+  // tid + NT, ...; decomposed once and advanced with a carry
   const int row0 = tid / np, j0 = tid % np, drow = NT / np, dj = NT % np;
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dg = 0.0;
@@ -370,94 +376,94 @@ __device__ __attribute__((always_inline)) inline void jacobi_grp(cpx<double>* A,
         if (p > q) { int t = p; p = q; q = t; }
         double c = 1.0, sv = 0.0, a = 0.0, d = 0.0, tb = 0.0;
         cpx<double> e = {1.0, 0.0};
-        int act = 0;
         if (q < k) {
           const cpx<double> b = A[p * k + q];
           a = A[p * k + p].re;
           d = A[q * k + q].re;
-          const double bb = sqrt(cabs2(b));
-          if (bb > 1e-300 && bb * bb > 1e-34 * fabs(a * d)) {
-            const double tau = (d - a) / (2.0 * bb);
+          const double bb2 = cabs2(b);
+          if (bb2 > 1e-300 && bb2 > 1e-34 * fabs(a * d)) {
+            const double ib = rsqrt(bb2);   // 1 / |b|
+            const double tau = 0.5 * (d - a) * ib;
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
+            c = rsqrt(1.0 + t * t);
             sv = t * c;
-            e = {b.re / bb, b.im / bb};
-            tb = t * bb;
-            act = 1;
+            e = {b.re * ib, b.im * ib};
+            tb = t * (bb2 * ib);
           }
         }
-        rs.jp[tid] = p;
-        rs.jq[tid] = q;
-        rs.jact[tid] = act;
-        rs.jc[tid] = c;
-        rs.js[tid] = sv;
-        rs.je[tid] = e;
-        rs.ja[tid] = a;
-        rs.jd[tid] = d;
-        rs.jtb[tid] = tb;
+        rs.rot[tid] = {c, sv, e.re, e.im};
+        rs.dia[tid] = {a - tb, d + tb};
+        rs.pq[tid] = p | (q << 8);
       }
       __syncthreads();
-      int rowc = row0, jc = j0;
-      for (int x = tid; x < nitems; x += NT) {
-        const int row = rowc, j = jc;
-        rowc += drow;
-        jc += dj;
-        if (jc >= np) { jc -= np; ++rowc; }
-        if (row < np) {
-          // block (rows of pair i, columns of pair j) of G^H A G
-          const int i = row;
-          const int pi = rs.jp[i], qi = rs.jq[i], pj = rs.jp[j], qj = rs.jq[j];
-          const bool ai = rs.jact[i] != 0, aj = rs.jact[j] != 0;
-          if (!ai && !aj) continue;
-          if (i == j) {   // rotated pair: its 2 x 2 block becomes diagonal
-            A[pi * k + qi] = {0.0, 0.0};
-            A[qi * k + pi] = {0.0, 0.0};
-            A[pi * k + pi] = {rs.ja[i] - rs.jtb[i], 0.0};
-            A[qi * k + qi] = {rs.jd[i] + rs.jtb[i], 0.0};
+      {   // G^H A G: block (rows of pair i, columns of pair j)
+        int i = row0, j = j0;
+        for (int x = tid; x < np * np; x += NT) {
+          const int ci = i, cj = j;
+          i += drow;
+          j += dj;
+          if (j >= np) { j -= np; ++i; }
+          const int pqi = rs.pq[ci], pqj = rs.pq[cj];
+          const int pi = pqi & 255, qi = pqi >> 8, pj = pqj & 255, qj = pqj >> 8;
+          const bool qiv = qi < k, qjv = qj < k;
+          if (ci == cj) {   // the pair's own block becomes diagonal
+            if (qiv) {
+              const double2 dd = rs.dia[ci];
+              A[pi * k + qi] = {0.0, 0.0};
+              A[qi * k + pi] = {0.0, 0.0};
+              A[pi * k + pi] = {dd.x, 0.0};
+              A[qi * k + qi] = {dd.y, 0.0};
+            }
             continue;
           }
-          const bool qiv = qi < k, qjv = qj < k;
           cpx<double> app = A[pi * k + pj];
           cpx<double> apq = qjv ? A[pi * k + qj] : cpx<double>{0.0, 0.0};
           cpx<double> aqp = qiv ? A[qi * k + pj] : cpx<double>{0.0, 0.0};
           cpx<double> aqq = qiv && qjv ? A[qi * k + qj] : cpx<double>{0.0, 0.0};
-          if (aj) {   // columns: [u, v] -> [c u - s conj(e) v, s u + c conj(e) v]
-            const double c = rs.jc[j], sv = rs.js[j];
-            const cpx<double> ec = {rs.je[j].re, -rs.je[j].im};
+          {   // columns: [u, v] -> [c u - s conj(e) v, s u + c conj(e) v]
+            const double4 R = rs.rot[cj];
+            const cpx<double> ec = {R.z, -R.w};
             cpx<double> ev = cmul(ec, apq);
-            const cpx<double> n0 = {c * app.re - sv * ev.re, c * app.im - sv * ev.im};
-            const cpx<double> n1 = {sv * app.re + c * ev.re, sv * app.im + c * ev.im};
+            const cpx<double> n0 = {R.x * app.re - R.y * ev.re, R.x * app.im - R.y * ev.im};
+            const cpx<double> n1 = {R.y * app.re + R.x * ev.re, R.y * app.im + R.x * ev.im};
             ev = cmul(ec, aqq);
-            const cpx<double> n2 = {c * aqp.re - sv * ev.re, c * aqp.im - sv * ev.im};
-            const cpx<double> n3 = {sv * aqp.re + c * ev.re, sv * aqp.im + c * ev.im};
+            const cpx<double> n2 = {R.x * aqp.re - R.y * ev.re, R.x * aqp.im - R.y * ev.im};
+            const cpx<double> n3 = {R.y * aqp.re + R.x * ev.re, R.y * aqp.im + R.x * ev.im};
             app = n0; apq = n1; aqp = n2; aqq = n3;
           }
-          if (ai) {   // rows: [u; v] -> [c u - s e v; s u + c e v]
-            const double c = rs.jc[i], sv = rs.js[i];
-            const cpx<double> e = rs.je[i];
+          {   // rows: [u; v] -> [c u - s e v; s u + c e v]
+            const double4 R = rs.rot[ci];
+            const cpx<double> e = {R.z, R.w};
             cpx<double> ev = cmul(e, aqp);
-            const cpx<double> n0 = {c * app.re - sv * ev.re, c * app.im - sv * ev.im};
-            const cpx<double> n2 = {sv * app.re + c * ev.re, sv * app.im + c * ev.im};
+            const cpx<double> n0 = {R.x * app.re - R.y * ev.re, R.x * app.im - R.y * ev.im};
+            const cpx<double> n2 = {R.y * app.re + R.x * ev.re, R.y * app.im + R.x * ev.im};
             ev = cmul(e, aqq);
-            const cpx<double> n1 = {c * apq.re - sv * ev.re, c * apq.im - sv * ev.im};
-            const cpx<double> n3 = {sv * apq.re + c * ev.re, sv * apq.im + c * ev.im};
+            const cpx<double> n1 = {R.x * apq.re - R.y * ev.re, R.x * apq.im - R.y * ev.im};
+            const cpx<double> n3 = {R.y * apq.re + R.x * ev.re, R.y * apq.im + R.x * ev.im};
             app = n0; apq = n1; aqp = n2; aqq = n3;
           }
           A[pi * k + pj] = app;
           if (qjv) A[pi * k + qj] = apq;
           if (qiv) A[qi * k + pj] = aqp;
           if (qiv && qjv) A[qi * k + qj] = aqq;
-        } else {
-          // Q G: row r, columns of pair j
-          const int r = row - np;
-          if (!rs.jact[j]) continue;
-          const int p = rs.jp[j], q = rs.jq[j];
-          const double c = rs.jc[j], sv = rs.js[j];
-          const cpx<double> ec = {rs.je[j].re, -rs.je[j].im};
-          const cpx<double> u = Q[r * k + p], v = Q[r * k + q];
+        }
+      }
+      {   // Q G: row r, columns of pair j
+        int r = row0, j = j0;
+        for (int x = tid; x < k * np; x += NT) {
+          const int cr = r, cj = j;
+          r += drow;
+          j += dj;
+          if (j >= np) { j -= np; ++r; }
+          const int pqj = rs.pq[cj];
+          const int p = pqj & 255, q = pqj >> 8;
+          if (q >= k) continue;
+          const double4 R = rs.rot[cj];
+          const cpx<double> ec = {R.z, -R.w};
+          const cpx<double> u = Q[cr * k + p], v = Q[cr * k + q];
           const cpx<double> ev = cmul(ec, v);
-          Q[r * k + p] = {c * u.re - sv * ev.re, c * u.im - sv * ev.im};
-          Q[r * k + q] = {sv * u.re + c * ev.re, sv * u.im + c * ev.im};
+          Q[cr * k + p] = {R.x * u.re - R.y * ev.re, R.x * u.im - R.y * ev.im};
+          Q[cr * k + q] = {R.y * u.re + R.x * ev.re, R.y * u.im + R.x * ev.im};
         }
       }
       __syncthreads();
@@ -479,10 +485,10 @@ __device__ __attribute__((always_inline)) inline void jacobi_grp(cpx<double>* A,
 // CU and CV (k x t, leading dimension t) are written over GU and GV.  Without
 // recompression CU = CV = I, t = k.  Returns t.
 // Always inlined, for the reason given at jacobi_grp.
-template <int NW>
+template <int NW, typename RS>
 __device__ __attribute__((always_inline)) inline int recompress_grp(
     int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol, double nu, bool do_recompress,
-    cpx<double>* mats, RecompShared& rs) {
+    cpx<double>* mats, RS& rs) {
   constexpr int NT = NW * WAVE;
   const int tid = threadIdx.x;
   if (k == 0 || !do_recompress) {
@@ -655,9 +661,11 @@ __device__ __attribute__((always_inline)) inline int recompress_grp(
   return t;
 }
 
-__device__ __attribute__((always_inline)) inline int recompress_wave(int k, int cap, cpx<double>* GU, cpx<double>* GV, double tol,
-                                      double nu, bool do_recompress, cpx<double>* mats,
-                                      RecompShared& rs) {
+template <typename RS>
+__device__ __attribute__((always_inline)) inline int recompress_wave(int k, int cap, cpx<double>* GU,
+                                                                     cpx<double>* GV, double tol, double nu,
+                                                                     bool do_recompress, cpx<double>* mats,
+                                                                     RS& rs) {
   return recompress_grp<1>(k, cap, GU, GV, tol, nu, do_recompress, mats, rs);
 }
 
