@@ -487,7 +487,7 @@ GCQ_API int gcq_aca_blocks(gcq_context* ctx, const int32_t* freq_idx, int32_t n_
   int64_t pool_used = 0;
   double ms_aca = 0, ms_rec = 0, ms_apply = 0;
   const bool rec = (flags & GCQ_FLAG_RECOMPRESS) != 0;
-  const int64_t budget = int64_t(6) << 30;
+  const int64_t budget = int64_t(16) << 30;
   int64_t n_overflow_pairs = 0;
   int rc;
   if (flags & GCQ_FLAG_PER_FREQ_LAUNCH) {
