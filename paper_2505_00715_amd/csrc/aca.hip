@@ -146,14 +146,19 @@ static int launch_recompress(gcq_context* ctx, int nc, const PairDesc* pairs, un
   return GCQ_OK;
 }
 
-// Ubar = U CU, Vbar = conj(W) CV into the compact pool
+// Ubar = U CU, Vbar = conj(W) CV into the compact pool; a group of two waves
+// per pair, the coefficients staged in LDS when they fit (two call sites, so
+// that the LDS one compiles to LDS reads)
+constexpr int APPLY_THREADS = 128;
+constexpr int APPLY_LDS = 512;   // coefficients of CU (and of CV) held in LDS
 template <typename T>
-__global__ void __launch_bounds__(256) apply_kernel(const PairDesc* __restrict__ pairs, int npairs,
-                                                    const unsigned char* __restrict__ ws,
-                                                    const int* __restrict__ rank_in,
-                                                    const int* __restrict__ tcut,
-                                                    const int64_t* __restrict__ out_off,
-                                                    cpx<T>* __restrict__ pool) {
+__global__ void __launch_bounds__(APPLY_THREADS) apply_kernel(const PairDesc* __restrict__ pairs, int npairs,
+                                                              const unsigned char* __restrict__ ws,
+                                                              const int* __restrict__ rank_in,
+                                                              const int* __restrict__ tcut,
+                                                              const int64_t* __restrict__ out_off,
+                                                              cpx<T>* __restrict__ pool) {
+  __shared__ cpx<double> cs[2 * APPLY_LDS];
   for (int pid = blockIdx.x; pid < npairs; pid += gridDim.x) {
     const PairDesc d = pairs[pid];
     const int k = rank_in[pid], t = tcut[pid], cap = d.cap, m = d.m, n = d.n;
@@ -162,8 +167,19 @@ __global__ void __launch_bounds__(256) apply_kernel(const PairDesc* __restrict__
     const cpx<double>* CU =
         reinterpret_cast<const cpx<double>*>(ws + d.ws + ws_gram_off<T>(cap, m, n));
     cpx<T>* OU = pool + out_off[pid];
-    apply_factors<T>(k, t, m, n, U, U + int64_t(cap) * m, CU, CU + cap * cap, OU,
-                     OU + int64_t(t) * m, threadIdx.x, blockDim.x);
+    if (k * t <= APPLY_LDS) {
+      __syncthreads();   // the previous pair's readers are done
+      for (int e = threadIdx.x; e < k * t; e += APPLY_THREADS) {
+        cs[e] = CU[e];
+        cs[APPLY_LDS + e] = CU[cap * cap + e];
+      }
+      __syncthreads();
+      apply_factors<T>(k, t, m, n, U, U + int64_t(cap) * m, cs, cs + APPLY_LDS, OU, OU + int64_t(t) * m,
+                       threadIdx.x, APPLY_THREADS);
+    } else {
+      apply_factors<T>(k, t, m, n, U, U + int64_t(cap) * m, CU, CU + cap * cap, OU, OU + int64_t(t) * m,
+                       threadIdx.x, APPLY_THREADS);
+    }
   }
 }
 
@@ -284,7 +300,7 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
     }
     GCQ_TRY(upload(ctx->scratchD, off, st));  // jacobi scratch no longer needed
     GCQ_TRY(timed_begin(ctx));
-    hipLaunchKernelGGL(apply_kernel<T>, dim3(std::min(nc, 65536)), dim3(256), 0, st,
+    hipLaunchKernelGGL(apply_kernel<T>, dim3(std::min(nc, 65536)), dim3(APPLY_THREADS), 0, st,
                        ctx->scratchB.as<PairDesc>(), nc, ctx->scratchA.as<unsigned char>(), d_rank,
                        d_t, ctx->scratchD.as<int64_t>(), pool.as<cpx<T>>());
     GCQ_HIP(hipGetLastError());

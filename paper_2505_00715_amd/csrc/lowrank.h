@@ -676,7 +676,7 @@ __device__ __attribute__((always_inline)) inline int recompress_wave(int k, int 
 // order as a per-element loop would.
 constexpr int APPLY_COLS = 8;
 template <typename T>
-__device__ inline void apply_factors(int k, int t, int m, int n, const cpx<T>* U, const cpx<T>* W,
+__device__ __attribute__((always_inline)) inline void apply_factors(int k, int t, int m, int n, const cpx<T>* U, const cpx<T>* W,
                                      const cpx<double>* CU, const cpx<double>* CV, cpx<T>* OU,
                                      cpx<T>* OV, int tid, int nthreads) {
   const int rows = m + n;
