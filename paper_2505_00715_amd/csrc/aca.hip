@@ -85,24 +85,70 @@ static void launch_aca(bool dlp, int nw, int grid, hipStream_t st, Args... args)
     launch_aca_op<T, AF, false>(nw, grid, st, args...);
 }
 
-// recompression of the pairs whose ACA rank k lies in (kmin, kmax], kmax <= MK:
-// one group of NW waves per pair, its working matrices in LDS sized for MK
+// rank classes of the recompression: class c holds the pairs whose ACA rank k
+// lies in (RC_LO[c], RC_LO[c + 1]]
+constexpr int RC_N = 7;
+__constant__ int RC_LO[RC_N + 1] = {-1, 8, 12, 16, 18, 24, 32, 64};
+__device__ __forceinline__ int rank_class(int k) {
+  int c = 0;
+  while (c < RC_N - 1 && k > RC_LO[c + 1]) ++c;
+  return c;
+}
+
+// the pairs of each class, in one list (class by class): cls[0 .. RC_N) the
+// class sizes, cls[RC_N .. 2 RC_N) scatter cursors, cls[2 RC_N .. 3 RC_N)
+// the classes' queue heads, all zero on entry; pass 0 counts, pass 1
+// scatters (the class offsets are the sums of the sizes before)
+__global__ void __launch_bounds__(256) recompress_classify(const int* __restrict__ rank, int nc,
+                                                           int* __restrict__ cls, int* __restrict__ list,
+                                                           int pass) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = i < nc ? rank_class(rank[i]) : -1;
+  const int lane = threadIdx.x & 63;
+  for (int q = 0; q < RC_N; ++q) {
+    // one atomic per wave and class: the lanes of class q take consecutive slots
+    const unsigned long long mask = __ballot(c == q);
+    if (mask == 0) continue;
+    const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+    const int cnt = __popcll(mask);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cls + (pass == 0 ? q : RC_N + q), cnt);
+    base = __shfl(base, leader, 64);
+    if (pass == 1 && c == q) {
+      int off = 0;
+      for (int r = 0; r < q; ++r) off += cls[r];
+      list[off + base + __popcll(mask & ((1ull << lane) - 1ull))] = i;
+    }
+  }
+}
+
+// recompression of the pairs of class `c` (ranks up to MK): groups of NW waves
+// take pairs from the class's queue; their working matrices in LDS sized for MK
 // terms (GL: in the group's slice of global scratch instead), so that groups
 // of small ranks fit many to a compute unit
 template <typename T, int MK, int NW, bool GL>
 __global__ void __launch_bounds__(NW * 64) recompress_kernel(const PairDesc* __restrict__ pairs,
-                                                             int npairs, unsigned char* __restrict__ ws,
+                                                             unsigned char* __restrict__ ws,
                                                              const int* __restrict__ rank_in,
                                                              int* __restrict__ out_t, double tol,
                                                              int do_recompress, unsigned char* __restrict__ jws,
-                                                             int kmin, int kmax) {
+                                                             int c, int* __restrict__ cls,
+                                                             const int* __restrict__ list) {
   __shared__ cpx<double> mats[GL ? 1 : recompress_mats(MK)];
   __shared__ RecompSharedT<MK> rs;
+  __shared__ int slot;
   cpx<double>* M = GL ? reinterpret_cast<cpx<double>*>(jws) + int64_t(blockIdx.x) * recompress_mats(MK) : mats;
-  for (int pid = blockIdx.x; pid < npairs; pid += gridDim.x) {
-    const int k = rank_in[pid];
-    if (k <= kmin || k > kmax) continue;
+  int off = 0;
+  for (int r = 0; r < c; ++r) off += cls[r];
+  const int size = cls[c];
+  for (;;) {
     __syncthreads();
+    if (threadIdx.x == 0) slot = atomicAdd(cls + 2 * RC_N + c, 1);
+    __syncthreads();
+    const int q = uni(slot);
+    if (q >= size) break;
+    const int pid = list[off + q];
+    const int k = rank_in[pid];
     const PairDesc d = pairs[pid];
     const int cap = d.cap;
     cpx<double>* GU = reinterpret_cast<cpx<double>*>(ws + d.ws + ws_gram_off<T>(cap, d.m, d.n));
@@ -115,29 +161,33 @@ __global__ void __launch_bounds__(NW * 64) recompress_kernel(const PairDesc* __r
 // over the context stream and the three side streams so that they run
 // together (a class of few large pairs takes about one pair's latency, which
 // the classes holding most pairs then cover)
-constexpr int RECOMP_GL_GRID = 4096;   // groups of the class whose matrices are in global scratch
+constexpr int RECOMP_GL_GRID = 1024;   // groups of the class whose matrices are in global scratch
 template <typename T>
 static int launch_recompress(gcq_context* ctx, int nc, const PairDesc* pairs, unsigned char* ws,
-                             const int* rank, int* t, double tol, int rec, unsigned char* jws) {
+                             const int* rank, int* t, double tol, int rec, unsigned char* jws, int* cls,
+                             int* list) {
   GCQ_TRY(ensure_side_streams(ctx));
   hipStream_t st = ctx->stream;
+  const int cg = (nc + 255) / 256;
+  hipLaunchKernelGGL(recompress_classify, dim3(cg), dim3(256), 0, st, rank, nc, cls, list, 0);
+  hipLaunchKernelGGL(recompress_classify, dim3(cg), dim3(256), 0, st, rank, nc, cls, list, 1);
   GCQ_HIP(hipEventRecord(ctx->evfork, st));
   for (int i = 0; i < 3; ++i) GCQ_HIP(hipStreamWaitEvent(ctx->side[i], ctx->evfork, 0));
-  const int g = std::min(nc, 8192);
+  const int g1 = std::min(nc, 5120), g2 = std::min(nc, 2560), g4 = std::min(nc, 1024);
   hipLaunchKernelGGL((recompress_kernel<T, 64, 4, true>), dim3(std::min(nc, RECOMP_GL_GRID)), dim3(256), 0,
-                     ctx->side[0], pairs, nc, ws, rank, t, tol, rec, jws, 32, 64);
-  hipLaunchKernelGGL((recompress_kernel<T, 32, 4, false>), dim3(g), dim3(256), 0, ctx->side[0], pairs, nc, ws,
-                     rank, t, tol, rec, jws, 24, 32);
-  hipLaunchKernelGGL((recompress_kernel<T, 24, 2, false>), dim3(g), dim3(128), 0, ctx->side[0], pairs, nc, ws,
-                     rank, t, tol, rec, jws, 18, 24);
-  hipLaunchKernelGGL((recompress_kernel<T, 18, 2, false>), dim3(g), dim3(128), 0, ctx->side[1], pairs, nc, ws,
-                     rank, t, tol, rec, jws, 16, 18);
-  hipLaunchKernelGGL((recompress_kernel<T, 16, 2, false>), dim3(g), dim3(128), 0, st, pairs, nc, ws, rank, t, tol,
-                     rec, jws, 12, 16);
-  hipLaunchKernelGGL((recompress_kernel<T, 12, 1, false>), dim3(g), dim3(64), 0, ctx->side[2], pairs, nc, ws, rank,
-                     t, tol, rec, jws, 8, 12);
-  hipLaunchKernelGGL((recompress_kernel<T, 8, 1, false>), dim3(g), dim3(64), 0, ctx->side[2], pairs, nc, ws,
-                     rank, t, tol, rec, jws, -1, 8);
+                     ctx->side[0], pairs, ws, rank, t, tol, rec, jws, 6, cls, list);
+  hipLaunchKernelGGL((recompress_kernel<T, 32, 4, false>), dim3(g4), dim3(256), 0, ctx->side[0], pairs, ws,
+                     rank, t, tol, rec, jws, 5, cls, list);
+  hipLaunchKernelGGL((recompress_kernel<T, 24, 2, false>), dim3(g2), dim3(128), 0, ctx->side[0], pairs, ws,
+                     rank, t, tol, rec, jws, 4, cls, list);
+  hipLaunchKernelGGL((recompress_kernel<T, 18, 2, false>), dim3(g2), dim3(128), 0, ctx->side[1], pairs, ws,
+                     rank, t, tol, rec, jws, 3, cls, list);
+  hipLaunchKernelGGL((recompress_kernel<T, 16, 2, false>), dim3(g2), dim3(128), 0, st, pairs, ws, rank, t, tol,
+                     rec, jws, 2, cls, list);
+  hipLaunchKernelGGL((recompress_kernel<T, 12, 1, false>), dim3(g1), dim3(64), 0, ctx->side[2], pairs, ws, rank,
+                     t, tol, rec, jws, 1, cls, list);
+  hipLaunchKernelGGL((recompress_kernel<T, 8, 1, false>), dim3(g1), dim3(64), 0, ctx->side[2], pairs, ws,
+                     rank, t, tol, rec, jws, 0, cls, list);
   GCQ_HIP(hipGetLastError());
   for (int i = 0; i < 3; ++i) {
     GCQ_HIP(hipEventRecord(ctx->evjoin[i], ctx->side[i]));
@@ -236,12 +286,14 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
     for (int a = 0; a < nc; ++a) cd[a] = desc[chunk[a]];
     GCQ_TRY(ctx->scratchA.ensure(size_t(wsz) + 256));
     GCQ_TRY(upload(ctx->scratchB, cd, st));
-    GCQ_TRY(ctx->scratchC.ensure(sizeof(int) * (3 * size_t(nc) + 8)));
+    GCQ_TRY(ctx->scratchC.ensure(sizeof(int) * (4 * size_t(nc) + 32)));
     int* d_rank = ctx->scratchC.as<int>();
     int* d_status = d_rank + nc;
     int* d_t = d_status + nc;
     int* d_counter = d_t + nc;
-    hipLaunchKernelGGL(zero_int, dim3(1), dim3(64), 0, st, d_counter, 8);
+    int* d_cls = d_counter + 8;      // rank classes of the recompression (3 x 7 counters)
+    int* d_list = d_counter + 32;    // the pairs class by class
+    hipLaunchKernelGGL(zero_int, dim3(1), dim3(64), 0, st, d_counter, 32);
     int nnf = 0;
     for (int a = 0; a < nc; ++a) nnf += cd[a].all_far == 0;
     const int nw = ctx->tune.aca_waves;
@@ -263,7 +315,7 @@ static int run_aca_pairs(gcq_context* ctx, std::vector<PairDesc>& desc, std::vec
     GCQ_HIP(hipEventRecord(ctx->evm, st));
     // recompression by rank classes; matrices above 32 terms live in global scratch
     GCQ_TRY(launch_recompress<T>(ctx, nc, ctx->scratchB.as<PairDesc>(), ctx->scratchA.as<unsigned char>(), d_rank,
-                                 d_t, tol, recompress ? 1 : 0, ctx->scratchD.as<unsigned char>()));
+                                 d_t, tol, recompress ? 1 : 0, ctx->scratchD.as<unsigned char>(), d_cls, d_list));
     GCQ_HIP(hipGetLastError());
     {
       double a = 0.0, r = 0.0;
