@@ -292,8 +292,18 @@ def main():
         st = ctx.aca_blocks(tol, 64, g.C128, g.FLAG_RECOMPRESS | g.FLAG_PER_FREQ_LAUNCH, freq_idx=fr)
         plain = dict(aca_blocks_per_s=st.n_pairs / (st.device_ms / 1e3), aca_ms=st.device_ms,
                      freqs=[int(k) for k in fr], pairs=int(st.n_pairs), precision="c128")
-        say(f"[bench] plain ACA (float64, per-frequency launches, {len(fr)} frequencies): "
-            f"{plain['aca_blocks_per_s']:.0f} pairs/s")
+        # the same frequencies in complex64 with one launch per frequency and no rank
+        # model, and batched with the rank model: precision and batching apart
+        s32 = ctx.aca_blocks(tol, 64, g.C64, g.FLAG_RECOMPRESS | g.FLAG_PER_FREQ_LAUNCH, freq_idx=fr)
+        sb = ctx.aca_blocks(tol, 64, g.C64, g.FLAG_RECOMPRESS | g.FLAG_USE_PREDICTOR, freq_idx=fr)
+        plain["c64_per_frequency_launches"] = dict(aca_blocks_per_s=s32.n_pairs / (s32.device_ms / 1e3),
+                                                   aca_ms=s32.device_ms)
+        plain["c64_batched_rank_model"] = dict(aca_blocks_per_s=sb.n_pairs / (sb.device_ms / 1e3),
+                                               aca_ms=sb.device_ms)
+        say(f"[bench] plain ACA on {len(fr)} frequencies: float64 per-frequency launches "
+            f"{plain['aca_blocks_per_s']:.0f} pairs/s, complex64 per-frequency launches "
+            f"{plain['c64_per_frequency_launches']['aca_blocks_per_s']:.0f}, complex64 batched with the rank "
+            f"model {plain['c64_batched_rank_model']['aca_blocks_per_s']:.0f}")
         torch.cuda.empty_cache()
 
     X = rhs.random_complex(L, n, 0)
