@@ -63,7 +63,9 @@ __global__ void gm_sub(const zc* __restrict__ V, zc* __restrict__ w, const zc* _
   }
 }
 
-// x[k][p] += sum_{c < nc} V_c[k][p] y[c * L + k]
+// x[k][p] += sum_{c < nc} V_c[k][p] y[c * L + k] (terms with y = 0 skipped:
+// the basis vectors of a system beyond the steps its product computed are
+// not read)
 __global__ void gm_update(const zc* __restrict__ V, zc* __restrict__ x, const zc* __restrict__ y,
                           int nc, int L, int n) {
   const int64_t total = int64_t(L) * n;
@@ -72,7 +74,9 @@ __global__ void gm_update(const zc* __restrict__ V, zc* __restrict__ x, const zc
     const int k = int(e / n);
     zc acc = x[e];
     for (int c = 0; c < nc; ++c) {
-      zc p = cmul(V[int64_t(c) * total + e], y[int64_t(c) * L + k]);
+      const zc yc = y[int64_t(c) * L + k];
+      if (yc.re == 0.0 && yc.im == 0.0) continue;
+      zc p = cmul(V[int64_t(c) * total + e], yc);
       acc.re += p.re;
       acc.im += p.im;
     }
@@ -231,7 +235,8 @@ __global__ void gm_givens(const int* __restrict__ dj, const zc* __restrict__ h1,
                           const double* __restrict__ nrm, zc* __restrict__ H, double* __restrict__ cs,
                           zc* __restrict__ sn, zc* __restrict__ g, int* __restrict__ done,
                           int* __restrict__ iters, const double* __restrict__ bn, double rtol,
-                          double* __restrict__ scale, int* __restrict__ active, int m, int L) {
+                          double* __restrict__ scale, int* __restrict__ active, int* __restrict__ deep, int m,
+                          int L) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= L) return;
   const int j = *dj;
@@ -279,12 +284,15 @@ __global__ void gm_givens(const int* __restrict__ dj, const zc* __restrict__ h1,
   gk[j + 1] = {-(sv.re * gj.re + sv.im * gj.im), -(sv.re * gj.im - sv.im * gj.re)};
   gk[j] = {c * gj.re, c * gj.im};
   int dk = done[k];
+  const double r = sqrt(gk[j + 1].re * gk[j + 1].re + gk[j + 1].im * gk[j + 1].im);
   if (!dk) {
     iters[k] += 1;
-    const double r = sqrt(gk[j + 1].re * gk[j + 1].re + gk[j + 1].im * gk[j + 1].im);
     if (r <= rtol * bn[k] || hn == 0.0) dk = 2;
     done[k] = dk;
   }
+  // below half the tolerance: the system's product may stop (its residual at
+  // the restart then stays below the tolerance)
+  if (r <= 0.5 * rtol * bn[k] || hn == 0.0) deep[k] = 1;
   scale[k] = hn > 0 ? 1.0 / hn : 0.0;
   if (!dk) atomicAdd(active, 1);
 }
@@ -300,9 +308,21 @@ __global__ void gm_scale_j(const zc* __restrict__ a, zc* __restrict__ V, const i
   }
 }
 
-// start of a step: the unconverged count starts at 0
-__global__ void gm_begin_step(int* __restrict__ active) {
+// start of step j = *dj: the unconverged count starts at 0; a 32-column
+// frequency tile whose systems are all below half the tolerance (deep) is left
+// out of this step's product (mask 0), the others record that their basis is
+// valid through step j (tvalid: the steps a tile's systems may use in the back
+// substitution)
+__global__ void gm_begin_step(int* __restrict__ active, const int* __restrict__ dj, const int* __restrict__ deep,
+                              int* __restrict__ mask, int* __restrict__ tvalid, int L) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *active = 0;
+  const int nkt = (L + 31) / 32, j = *dj;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nkt; t += gridDim.x * blockDim.x) {
+    int any = 0;
+    for (int k = 32 * t; k < min(L, 32 * t + 32); ++k) any |= deep[k] == 0;
+    mask[t] = any;
+    if (any) tvalid[t] = j + 1;
+  }
 }
 
 // end of a step: j + 1
@@ -310,18 +330,23 @@ __global__ void gm_next_j(int* __restrict__ dj) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dj += 1;
 }
 
-// back substitution per column over the first jdone rows: y[c * L + k]
+// back substitution per column over its first min(jdone, tvalid of its tile)
+// rows (the steps whose basis vectors its product computed): y[c * L + k],
+// zero in the rows beyond
 __global__ void gm_backsub(const zc* __restrict__ H, const zc* __restrict__ g, const double* __restrict__ beta,
-                           const double* __restrict__ bn, int jdone, int m, int L, zc* __restrict__ y) {
+                           const double* __restrict__ bn, const int* __restrict__ tvalid, int jdone, int m, int L,
+                           zc* __restrict__ y) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= L) return;
   const zc* Hk = H + int64_t(k) * (m + 1) * m;
   const zc* gk = g + int64_t(k) * (m + 1);
   const bool act = beta[k] > 0 && !(bn[k] == 0.0);
-  for (int i = jdone - 1; i >= 0; --i) {
+  const int jd = min(jdone, tvalid[k / 32]);
+  for (int i = jdone - 1; i >= jd; --i) y[int64_t(i) * L + k] = {0.0, 0.0};
+  for (int i = jd - 1; i >= 0; --i) {
     zc acc = act ? gk[i] : zc{0.0, 0.0};
     if (act)
-      for (int c = i + 1; c < jdone; ++c) {
+      for (int c = i + 1; c < jd; ++c) {
         const zc p = cmul(Hk[i * m + c], y[int64_t(c) * L + k]);
         acc.re -= p.re;
         acc.im -= p.im;
@@ -343,6 +368,8 @@ struct DevState {
   zc *H = nullptr, *sn = nullptr, *g = nullptr, *h2 = nullptr;
   double *cs = nullptr, *bn = nullptr, *beta = nullptr, *scale = nullptr;
   int *done = nullptr, *iters = nullptr, *dj = nullptr, *active = nullptr;
+  int *mask = nullptr, *tvalid = nullptr;   // per 32-column frequency tile
+  int* deep = nullptr;                      // per system: residual below half the tolerance
   int* host_active = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -357,14 +384,14 @@ static int capture_step(gcq_context* ctx, Solver& S, DevState& D, zc* V, int m, 
   const dim3 G(2048), Bk(256);
   hipGraph_t graph = nullptr;
   GCQ_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  hipLaunchKernelGGL(gm_begin_step, dim3(1), dim3(64), 0, cs, D.active);
+  hipLaunchKernelGGL(gm_begin_step, dim3(1), dim3(64), 0, cs, D.active, D.dj, D.deep, D.mask, D.tvalid, L);
   if (S.precision == GCQ_C128) {
     zc* tmp = reinterpret_cast<zc*>(S.t32);
     hipLaunchKernelGGL(gm_copy_j, G, Bk, 0, cs, V, D.dj, tmp, total);
-    enqueue_perfreq_any(ctx, cs, S.precision, tmp, S.w);
+    enqueue_perfreq_any(ctx, cs, S.precision, tmp, S.w, D.mask);
   } else {
     hipLaunchKernelGGL(gm_to32_j, G, Bk, 0, cs, V, D.dj, S.t32, total);
-    enqueue_perfreq_any(ctx, cs, S.precision, S.t32, S.t32 + total);
+    enqueue_perfreq_any(ctx, cs, S.precision, S.t32, S.t32 + total, D.mask);
     hipLaunchKernelGGL(gm_from32, G, Bk, 0, cs, S.t32 + total, S.w, total);
   }
   hipLaunchKernelGGL(gm_dots_j, dim3((m + 1) * L), Bk, 0, cs, V, S.w, D.dj, L, n, S.h);
@@ -373,7 +400,7 @@ static int capture_step(gcq_context* ctx, Solver& S, DevState& D, zc* V, int m, 
   hipLaunchKernelGGL(gm_sub_j, G, Bk, 0, cs, V, S.w, D.h2, D.dj, L, n);
   hipLaunchKernelGGL(gm_norm2, dim3(L), Bk, 0, cs, S.w, n, S.nrm);
   hipLaunchKernelGGL(gm_givens, dim3((L + 255) / 256), Bk, 0, cs, D.dj, S.h, D.h2, S.nrm, D.H, D.cs, D.sn, D.g,
-                     D.done, D.iters, D.bn, rtol, D.scale, D.active, m, L);
+                     D.done, D.iters, D.bn, rtol, D.scale, D.active, D.deep, m, L);
   hipLaunchKernelGGL(gm_scale_j, G, Bk, 0, cs, S.w, V, D.dj, D.scale, L, n);
   hipLaunchKernelGGL(gm_next_j, dim3(1), dim3(64), 0, cs, D.dj);
   const hipError_t ce = hipGetLastError();
@@ -435,7 +462,7 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
   hipLaunchKernelGGL(gm_zero, G, Bk, 0, st, x, total);
   std::vector<double> bn;
   GCQ_TRY(S.norms(b, bn));
-  std::vector<int> iters(L, 0), done(L, 0);
+  std::vector<int> iters(L, 0), done(L, 0), deep(L, 0);
   std::vector<double> resid(L, 0.0);
   std::vector<std::complex<double>> H(size_t(L) * (m + 1) * m), g(size_t(L) * (m + 1)), sn(size_t(L) * m);
   std::vector<double> cs(size_t(L) * m);
@@ -454,8 +481,10 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
   if (use_graph) {
     GCQ_TRY(prepare_perfreq(ctx, precision));
     const size_t zc_n = size_t(L) * (m + 1) * m + size_t(L) * m + size_t(L) * (m + 1) + size_t(m + 1) * L;
-    // eleven arrays, each rounded up to 256 bytes
-    const size_t bytes = zc_n * sizeof(zc) + sizeof(double) * (size_t(L) * m + 2 * L) + sizeof(int) * (2 * L + 2) + 11 * 256;
+    const int nkt = (L + 31) / 32;
+    // fourteen arrays, each rounded up to 256 bytes
+    const size_t bytes = zc_n * sizeof(zc) + sizeof(double) * (size_t(L) * m + 2 * L) +
+                         sizeof(int) * (3 * L + 2 + 2 * nkt) + 14 * 256;
     GCQ_TRY(dstate.ensure(bytes));
     unsigned char* q = dstate.as<unsigned char>();
     auto take = [&](size_t b) { unsigned char* r = q; q += (b + 255) & ~size_t(255); return r; };
@@ -470,6 +499,9 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
     D.iters = reinterpret_cast<int*>(take(sizeof(int) * L));
     D.dj = reinterpret_cast<int*>(take(sizeof(int)));
     D.active = reinterpret_cast<int*>(take(sizeof(int)));
+    D.mask = reinterpret_cast<int*>(take(sizeof(int) * nkt));
+    D.tvalid = reinterpret_cast<int*>(take(sizeof(int) * nkt));
+    D.deep = reinterpret_cast<int*>(take(sizeof(int) * L));
     D.scale = d_scale;
     GCQ_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned_active), sizeof(int), hipHostMallocDefault));
     D.host_active = pinned_active;
@@ -494,6 +526,7 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
     for (int k = 0; k < L; ++k) {
       resid[k] = bn[k] > 0 ? beta[k] / bn[k] : 0.0;
       done[k] = bn[k] == 0.0 || beta[k] <= rtol * bn[k];
+      deep[k] = bn[k] == 0.0 || beta[k] <= 0.5 * rtol * bn[k];
       all = all && done[k];
     }
     if (all || total_iters >= max_iter) break;
@@ -507,9 +540,11 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
       std::vector<int> dn(done.begin(), done.end());
       GCQ_HIP(hipMemcpyAsync(D.g, g0.data(), sizeof(zc) * g0.size(), hipMemcpyHostToDevice, st));
       GCQ_HIP(hipMemcpyAsync(D.done, dn.data(), sizeof(int) * L, hipMemcpyHostToDevice, st));
+      GCQ_HIP(hipMemcpyAsync(D.deep, deep.data(), sizeof(int) * L, hipMemcpyHostToDevice, st));
       GCQ_HIP(hipMemcpyAsync(D.beta, beta.data(), sizeof(double) * L, hipMemcpyHostToDevice, st));
       hipLaunchKernelGGL(gm_zero_d, G, Bk, 0, st, reinterpret_cast<double*>(D.H), int64_t(L) * (m + 1) * m * 2);
       GCQ_HIP(hipMemsetAsync(D.dj, 0, sizeof(int), st));
+      GCQ_HIP(hipMemsetAsync(D.tvalid, 0, sizeof(int) * ((L + 31) / 32), st));
       if (!D.exec) GCQ_TRY(capture_step(ctx, S, D, V, m, rtol));
       int jdone = 0;
       for (int j = 0; j < m; ++j) {
@@ -522,7 +557,8 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
         jdone = j + 1;
         if (act == 0 || total_iters >= max_iter) break;
       }
-      hipLaunchKernelGGL(gm_backsub, dim3((L + 255) / 256), Bk, 0, st, D.H, D.g, D.beta, D.bn, jdone, m, L, d_y);
+      hipLaunchKernelGGL(gm_backsub, dim3((L + 255) / 256), Bk, 0, st, D.H, D.g, D.beta, D.bn, D.tvalid, jdone, m,
+                         L, d_y);
       hipLaunchKernelGGL(gm_update, G, Bk, 0, st, V, x, d_y, jdone, L, n);
       GCQ_HIP(hipGetLastError());
       continue;
@@ -531,7 +567,15 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
     std::fill(g.begin(), g.end(), 0.0);
     for (int k = 0; k < L; ++k) g[size_t(k) * (m + 1)] = beta[k];
     int jdone = 0;
+    // steps whose basis each 32-column tile may use (as the graph path, whose
+    // product leaves out tiles whose systems have all converged)
+    std::vector<int> tvalid((L + 31) / 32, 0);
     for (int j = 0; j < m; ++j) {
+      for (int t = 0; t < int(tvalid.size()); ++t) {
+        bool any = false;
+        for (int k = 32 * t; k < std::min(L, 32 * t + 32); ++k) any = any || !deep[k];
+        if (any) tvalid[t] = j + 1;
+      }
       zc* vj = V + int64_t(j) * total;
       GCQ_TRY(S.apply(vj, S.w));
       // classical Gram-Schmidt, twice
@@ -585,6 +629,7 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
           iters[k] += 1;
           if (std::abs(gk[j + 1]) <= rtol * bn[k] || hn[k] == 0.0) done[k] = 2;
         }
+        if (std::abs(gk[j + 1]) <= 0.5 * rtol * bn[k] || hn[k] == 0.0) deep[k] = 1;
         conv_all = conv_all && done[k];
       }
       jdone = j + 1;
@@ -596,9 +641,10 @@ extern "C" GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_de
       std::complex<double>* gk = &g[size_t(k) * (m + 1)];
       std::vector<std::complex<double>> y(jdone, 0.0);
       const bool active = beta[k] > 0 && !(bn[k] == 0.0);
-      for (int i = jdone - 1; i >= 0 && active; --i) {
+      const int jd = std::min(jdone, tvalid[k / 32]);
+      for (int i = jd - 1; i >= 0 && active; --i) {
         std::complex<double> acc = gk[i];
-        for (int c = i + 1; c < jdone; ++c) acc -= Hk[size_t(i) * m + c] * y[c];
+        for (int c = i + 1; c < jd; ++c) acc -= Hk[size_t(i) * m + c] * y[c];
         std::complex<double> d = Hk[size_t(i) * m + i];
         y[i] = std::abs(d) > 0 ? acc / d : 0.0;
       }

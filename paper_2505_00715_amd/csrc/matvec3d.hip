@@ -682,9 +682,10 @@ int prepare_perfreq(gcq_context* ctx, int precision) {
 
 // the per-frequency product's kernels on stream s (no allocation, no host
 // transfer: capturable after prepare_perfreq)
-void enqueue_perfreq_any(gcq_context* ctx, hipStream_t s, int precision, const void* X, void* Y) {
+void enqueue_perfreq_any(gcq_context* ctx, hipStream_t s, int precision, const void* X, void* Y,
+                         const int* tile_mask) {
   if (precision == GCQ_C64_SPLIT_BF16)
-    enqueue_perfreq_bf16(ctx, s, X, Y);
+    enqueue_perfreq_bf16(ctx, s, X, Y, tile_mask);
   else if (precision == GCQ_C128)
     enqueue_perfreq<double>(ctx, s, precision, X, Y);
   else

@@ -333,6 +333,16 @@ __device__ __forceinline__ BfGroup3 load_x(const uint4* __restrict__ xk, int g, 
 
 
 
+// some of the tiles kt0 .. kt0 + KW - 1 is to be computed (no mask: all are)
+template <int KW>
+__device__ __forceinline__ bool tiles_active(const int* __restrict__ tmask, int kt0, int nkt) {
+  if (!tmask) return true;
+  bool any = false;
+#pragma unroll
+  for (int u = 0; u < KW; ++u) any = any || (kt0 + u < nkt && tmask[kt0 + u] != 0);
+  return any;
+}
+
 // the KW 32-column frequency tiles kt0 .. kt0 + KW - 1 that a wave owns
 template <int KW>
 struct Tiles {
@@ -450,7 +460,8 @@ __global__ void __launch_bounds__(KW == 1 ? 512 : 256, KW == 1 ? 4 : 1) bf_tfill
     const int* __restrict__ big, const int* __restrict__ range, int* __restrict__ counter,
     const BfBlock* __restrict__ bb, const uint4* __restrict__ bfp,
     const int* __restrict__ bcol, const int64_t* __restrict__ cols, const cpx<float>* __restrict__ pool,
-    const int* __restrict__ colpos, int L, int ng, const uint4* __restrict__ Xg, uint4* __restrict__ Tbuf) {
+    const int* __restrict__ colpos, int L, int ng, const uint4* __restrict__ Xg, uint4* __restrict__ Tbuf,
+    const int* __restrict__ tmask) {
   const int lane = threadIdx.x & 63, lr = lane & 31, lh = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
   const int nkt = (L + 31) >> 5;
@@ -461,6 +472,7 @@ __global__ void __launch_bounds__(KW == 1 ? 512 : 256, KW == 1 ? 4 : 1) bf_tfill
     const BfBlock B = bb[b];
     const uint4* Vg = bfp + B.off * FRAG;
     for (int kt0 = w * KW; kt0 < nkt; kt0 += nw * KW) {
+      if (!tiles_active<KW>(tmask, kt0, nkt)) continue;
       const Tiles<KW> C(kt0, nkt, L, lr, ng, colpos, Xg);
       for (int t0 = 0; t0 < B.T; t0 += BF_TG) {
         const int nt = min(BF_TG, B.T - t0);
@@ -541,7 +553,7 @@ __global__ void __launch_bounds__(KW == 1 ? 512 : 256) bf_rows(
     const int64_t* __restrict__ cols, const int* __restrict__ bcol, const cpx<float>* __restrict__ pool,
     const BfBlock* __restrict__ bb, const uint4* __restrict__ bfp, const int* __restrict__ colpos, int L, int ng,
     const uint4* __restrict__ Xg, const uint4* __restrict__ Tbuf, cpx<float>* __restrict__ Ylev,
-    int64_t lev_stride, int* __restrict__ counter) {
+    int64_t lev_stride, int* __restrict__ counter, const int* __restrict__ tmask) {
   constexpr int RT = BIG ? BF_RTB : BF_RT;
   __shared__ int cur;
   const int lane = threadIdx.x & 63, lr = lane & 31, lh = lane >> 5;
@@ -553,6 +565,7 @@ __global__ void __launch_bounds__(KW == 1 ? 512 : 256) bf_rows(
     const int nrt = (I.rows + 31) >> 5;
     const int rt0 = I.r0 >> 5;
     for (int kt0 = w * KW; kt0 < nkt; kt0 += nw * KW) {
+      if (!tiles_active<KW>(tmask, kt0, nkt)) continue;
       const Tiles<KW> C(kt0, nkt, L, lr, ng, colpos, Xg);
       f16v yre[KW][RT], yim[KW][RT];
 #pragma unroll
@@ -634,7 +647,7 @@ __global__ void __launch_bounds__(BF_WAVES * BF_RT * 64) bf_near(
     const int* __restrict__ bterm, const int64_t* __restrict__ tfoff, const cpx<float>* __restrict__ pool,
     const BfBlock* __restrict__ bb, const uint4* __restrict__ bfp, const int* __restrict__ colpos, int L, int ng,
     const uint4* __restrict__ Xg, cpx<float>* __restrict__ Ylev, int64_t lev_stride, int* __restrict__ counter,
-    int wk) {
+    int wk, const int* __restrict__ tmask) {
   __shared__ int cur;
   const int lane = threadIdx.x & 63, lr = lane & 31, lh = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -647,6 +660,7 @@ __global__ void __launch_bounds__(BF_WAVES * BF_RT * 64) bf_near(
     if (wrt >= nrt) continue;   // (next_item's barriers are reached by every wave)
     const int rt = (I.r0 >> 5) + wrt;
     for (int kt = wkt; kt < nkt; kt += wk) {
+      if (tmask && !tmask[kt]) continue;
       const Tiles<1> C(kt, nkt, L, lr, ng, colpos, Xg);
       f16v yre = f16_zero(), yim = f16_zero();
       for (int bi = 0; bi < I.nb; ++bi) {
@@ -877,7 +891,7 @@ size_t bf16_buffer_bytes(gcq_context* ctx) {
 // the T' fill and the row kernels with KW 32-column tiles per wave
 template <int KW>
 static void enqueue_bf_kernels(gcq_context* ctx, hipStream_t st, const uint4* Xg, int* counter, cpx<float>* Ylev,
-                               int64_t lev_stride, const int* d_colpos) {
+                               int64_t lev_stride, const int* d_colpos, const int* tmask) {
   Faces3D& F = ctx->F;
   const int n = ctx->n, L = ctx->L, ng = (n + 7) / 8, nkt = (L + 31) / 32;
   const int waves = std::max(1, std::min(BF_WAVES / KW, (nkt + KW - 1) / KW));
@@ -886,11 +900,11 @@ static void enqueue_bf_kernels(gcq_context* ctx, hipStream_t st, const uint4* Xg
     hipLaunchKernelGGL(bf_tfill<KW>, dim3(ctx->cus * 2), dim3(64 * waves), 0, st, F.d_bfbig.as<int>(),
                        range + 3 * (BF_NX + 1), counter + 3 * BF_NX, F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(),
                        F.d_bcol.as<int>(), F.d_cols.as<int64_t>(), F.slices.as<cpx<float>>(), d_colpos, L, ng, Xg,
-                       F.bftbuf.as<uint4>());
+                       F.bftbuf.as<uint4>(), tmask);
   hipLaunchKernelGGL((bf_rows<false, KW>), dim3(ctx->cus * 2), dim3(64 * waves), 0, st, F.d_bfitems.as<BfItem>(),
                      range, F.d_bfrowblk.as<int>(), F.d_cols.as<int64_t>(), F.d_bcol.as<int>(),
                      F.slices.as<cpx<float>>(), F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), d_colpos, L, ng, Xg,
-                     F.bftbuf.as<uint4>(), Ylev, lev_stride, counter);
+                     F.bftbuf.as<uint4>(), Ylev, lev_stride, counter, tmask);
   // row clusters above BF_MC rows: two tiles per wave in either case (measured
   // faster, and one tile per wave with the T' prefetch does not fit 256 registers;
   // one row tile per wave on 64-row items reads the T' buffer more: slower)
@@ -898,17 +912,17 @@ static void enqueue_bf_kernels(gcq_context* ctx, hipStream_t st, const uint4* Xg
   hipLaunchKernelGGL((bf_rows<true, 2>), dim3(ctx->cus * 2), dim3(64 * bwaves), 0, st, F.d_bfitems.as<BfItem>(),
                      range + BF_NX + 1, F.d_bfrowblk.as<int>(), F.d_cols.as<int64_t>(), F.d_bcol.as<int>(),
                      F.slices.as<cpx<float>>(), F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), d_colpos, L, ng,
-                     Xg, F.bftbuf.as<uint4>(), Ylev, lev_stride, counter + BF_NX);
+                     Xg, F.bftbuf.as<uint4>(), Ylev, lev_stride, counter + BF_NX, tmask);
   // near blocks: one frequency tile and one row tile per wave
   const int nwk = std::min(BF_WAVES, nkt);
   hipLaunchKernelGGL(bf_near, dim3(ctx->cus * 2), dim3(64 * nwk * BF_RT), 0, st, F.d_bfitems.as<BfItem>(),
                      range + 2 * (BF_NX + 1), F.d_bfrowblk.as<int>(), F.d_bterm.as<int>(), F.d_tfoff.as<int64_t>(),
                      F.slices.as<cpx<float>>(), F.d_bfblk.as<BfBlock>(), F.bfpool.as<uint4>(), d_colpos, L, ng, Xg,
-                     Ylev, lev_stride, counter + 2 * BF_NX, nwk);
+                     Ylev, lev_stride, counter + 2 * BF_NX, nwk, tmask);
 }
 
 // kernels of one product on stream st (no allocation, no host transfer)
-void enqueue_perfreq_bf16(gcq_context* ctx, hipStream_t st, const void* X, void* Y) {
+void enqueue_perfreq_bf16(gcq_context* ctx, hipStream_t st, const void* X, void* Y, const int* tile_mask) {
   Faces3D& F = ctx->F;
   const int n = ctx->n, L = ctx->L, ng = (n + 7) / 8, nkt = (L + 31) / 32;
   unsigned char* base = F.pxy.as<unsigned char>();
@@ -922,9 +936,9 @@ void enqueue_perfreq_bf16(gcq_context* ctx, hipStream_t st, const void* X, void*
   hipLaunchKernelGGL(bf_x_in, dim3(4096), dim3(256), 0, st, (const cpx<float>*)X, Xg, perm, d_conj, n, L, ng, nkt,
                      counter);
   if (ctx->tune.product_cols_per_wave == 64)
-    enqueue_bf_kernels<2>(ctx, st, Xg, counter, Ylev, lev_stride, d_colpos);
+    enqueue_bf_kernels<2>(ctx, st, Xg, counter, Ylev, lev_stride, d_colpos, tile_mask);
   else
-    enqueue_bf_kernels<1>(ctx, st, Xg, counter, Ylev, lev_stride, d_colpos);
+    enqueue_bf_kernels<1>(ctx, st, Xg, counter, Ylev, lev_stride, d_colpos, tile_mask);
   hipLaunchKernelGGL(bf_reduce_out, dim3(4096), dim3(256), 0, st, Ylev, lev_stride, F.d_bfmask.as<unsigned>(),
                      (cpx<float>*)Y, perm, d_conj, n, L);
 }

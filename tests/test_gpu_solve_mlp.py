@@ -72,6 +72,45 @@ def test_gmres_graph_step_matches_host_path(prec):
     assert ig2 == ig and rel(xg2, xg) <= (1e-12 if prec == g.C128 else 10 * rtol)
 
 
+@pytest.mark.parametrize("prec", [g.C64_SPLIT_BF16, g.C64])
+def test_gmres_converged_tiles_left_out(prec):
+    """96 frequencies (three 32-column tiles; the middle one, of large |s|,
+    converges first): the graph path leaves a tile whose systems have all
+    converged out of the split-bf16 product and back-substitutes each system
+    over the steps its tile computed; the host path computes every product and
+    applies the same rule. Both give the same iterations and solutions, every
+    system converges, and sampled systems hold the tolerance against the
+    dense oracle matrix."""
+    xyz, tri = mesh.icosphere(2)
+    s = freq.bdf2_circle(96, 0.05, 1e-8 ** (1 / 48))
+    L = len(s)
+    assert L == 96
+    ctx = make_ctx(xyz, tri, 1.0, s, 16, 1.0)
+    ctx.aca3d(1e-8, 1e-8, 40, g.C64)
+    rtol = 1e-6
+    Bh = rhs.random_complex(L, 320, 3)
+    B = to_dev(Bh, g.C128).reshape(-1)
+    out = {}
+    for graph in (1, 0):
+        ctx.set_tuning(product_graph=graph)
+        X = torch.zeros_like(B)
+        st = ctx.solve(B, X, rtol=rtol, max_iter=300, restart=20, precision=prec)
+        assert st.status == g.OK and st.n_converged == L
+        out[graph] = (st.iters_max, from_dev(X).reshape(L, 320))
+    ctx.set_tuning(product_graph=1)
+    (ig, xg), (ih, xh) = out[1], out[0]
+    assert abs(ig - ih) <= 1, (ig, ih)
+    assert rel(xg, xh) <= 100 * rtol
+    kk = np.array([0, 31, 40, 55, 70, 95])
+    A = entries.dense(Panels(xyz, tri), s[kk], 1.0)
+    for a, k in zip(A, kk):
+        res = np.linalg.norm(a @ xg[k] - Bh[k]) / np.linalg.norm(Bh[k])
+        pert = 0.0 if prec != g.C64_SPLIT_BF16 else \
+            2.0 ** -18 * np.linalg.norm(np.abs(a), 2) * np.linalg.norm(xg[k]) / np.linalg.norm(Bh[k])
+        # 3D-ACA tolerance 1e-8 and float products on top of rtol
+        assert res <= 3 * rtol + 1e-7 + pert, (k, res, pert)
+
+
 def test_gmres_not_converged_flag():
     xyz, tri = mesh.icosphere(2)
     s = freq.bdf2_circle(8, 0.05, 1e-8 ** (1 / 8))
