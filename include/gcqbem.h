@@ -547,8 +547,12 @@ GCQ_API int gcq_compressed_matvec(gcq_context* ctx, int32_t mode, int32_t precis
  *   float64 (classical Gram-Schmidt twice), until |b - A x| <= rtol |b| or
  *   max_iter iterations.  B_dev, X_dev: complex128 device arrays shaped like
  *   the products' X.  The product inside uses `precision` (GCQ_C64_SPLIT_BF16
- *   with an operator built at GCQ_C64).  Returns
- *   GCQ_NOT_CONVERGED if some system missed the tolerance. */
+ *   with an operator built at GCQ_C64).  With product_graph set (default)
+ *   each Arnoldi step runs as a replayed graph, and a 32-column frequency tile
+ *   whose systems all have residual estimates below rtol / 2 is left out of
+ *   the split-bf16 products; every system's update uses the steps its tile
+ *   computed (likewise with the graph off).  Returns GCQ_NOT_CONVERGED if some
+ *   system missed the tolerance. */
 GCQ_API int gcq_solve(gcq_context* ctx, const void* B_dev, void* X_dev, double rtol,
                       int32_t max_iter, int32_t restart, int32_t precision,
                       gcq_solve_stats* stats);
