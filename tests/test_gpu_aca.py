@@ -60,6 +60,41 @@ def test_aca_blocks_match_oracle(prec, waves):
         assert same_rank >= 0.8 * total
 
 
+def test_recompression_rank_classes():
+    """At ACA tolerance 1e-10 the ACA ranks of the 1280-triangle sphere's far
+    blocks reach past 32, so every rank class of the recompression runs
+    (LDS matrices sized for ranks up to 8, 12, 16, 18, 24, 32 with one to four
+    waves per pair, global scratch above): the approximants of the largest
+    blocks and of random ones hold the tolerance against the dense blocks and
+    agree with the oracle's ACA with recompression."""
+    xyz, tri, s = _problem()
+    tol = 1e-10
+    P, T, B, perm, blocks = oracle_tree(xyz, tri, 32, 1.0)
+    ctx = make_ctx(xyz, tri, 1.0, s, 32, 1.0)
+    st = ctx.aca_blocks(tol, 64, g.C128, g.FLAG_RECOMPRESS)
+    assert st.status == g.OK
+    rep, conj, K, kpos = kpos_map(s)
+    r = ctx.aca_ranks(len(K))
+    # recompressed ranks bound the ACA ranks from below: classes above 18, 24, 32 ran
+    assert r.max() > 32 and ((r > 18) & (r <= 24)).any() and ((r > 24) & (r <= 32)).any()
+    far = np.nonzero(blocks[:, 4])[0]
+    big = sorted(far, key=lambda b: -(len(T.indices(B[b][0])) + len(T.indices(B[b][1]))))[:8]
+    rng = np.random.default_rng(2)
+    pick = list(big) + list(rng.choice(far, 8, replace=False))
+    num = den = 0.0
+    for b in pick:
+        I, J = T.indices(B[b][0]), T.indices(B[b][1])
+        for k in (K[0], K[len(K) // 2], K[-1]):
+            A = entries.block(P, I, J, [s[k]], 1.0)[0]
+            Ug, Vg = ctx.get_block_factors(int(b), int(k))
+            Sg = Ug @ Vg.conj().T
+            assert np.linalg.norm(Sg - A) <= 40 * tol * np.linalg.norm(A) + 1e-30, (b, k)
+            Uo, Vo, _ = aca.aca_block(P, I, J, s[k], 1.0, tol, 64, recompress_tol=tol)
+            num += np.linalg.norm(Sg - Uo @ Vo.conj().T) ** 2
+            den += np.linalg.norm(A) ** 2
+    assert np.sqrt(num / den) <= 40 * tol
+
+
 @pytest.mark.parametrize("prec", [g.C128, g.C64])
 def test_plain_h_product(prec):
     xyz, tri, s = _problem()
