@@ -196,10 +196,10 @@ static int launch_recompress(gcq_context* ctx, int nc, const PairDesc* pairs, un
   return GCQ_OK;
 }
 
-// Ubar = U CU, Vbar = conj(W) CV into the compact pool; a group of two waves
+// Ubar = U CU, Vbar = conj(W) CV into the compact pool; a group of four waves
 // per pair, the coefficients staged in LDS when they fit (two call sites, so
 // that the LDS one compiles to LDS reads)
-constexpr int APPLY_THREADS = 128;
+constexpr int APPLY_THREADS = 256;
 constexpr int APPLY_LDS = 512;   // coefficients of CU (and of CV) held in LDS
 template <typename T>
 __global__ void __launch_bounds__(APPLY_THREADS) apply_kernel(const PairDesc* __restrict__ pairs, int npairs,
