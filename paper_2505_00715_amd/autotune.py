@@ -25,6 +25,14 @@ ACA3D_CANDIDATES = [(4, 4, 4, 4), (2, 4, 4, 4), (2, 2, 4, 4), (4, 4, 4, 8), (1, 
 STACK_CANDIDATES = [4, 8, 16]
 
 
+def choose_product_graph(times: dict) -> int:
+    """Graph replay (1) or plain launches (0) from the product's times under
+    each.  The graph setting also runs the solver's Arnoldi step on the device,
+    which leaves converged frequency tiles out of the product (a gain the single
+    product does not show), so plain launches win only when clearly faster."""
+    return 0 if times[0] < 0.97 * times[1] else 1
+
+
 def default_cache_path() -> str:
     base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
     return os.path.join(base, "gcqbem", "tuning.json")
@@ -142,10 +150,7 @@ def tune(ctx, workload: str, precision: int, tol: float, max_rank: int = 64, max
             ctx.set_tuning(product_graph=gr)
             times[gr] = product_ms()
             say(f"[autotune] product_graph {gr}: {times[gr]:.3f} ms")
-        # the graph setting also runs the solver's Arnoldi step on the device,
-        # which leaves converged frequency tiles out of the product (a gain the
-        # single product does not show): plain launches only when clearly faster
-        best["product_graph"] = 0 if times[0] < 0.97 * times[1] else 1
+        best["product_graph"] = choose_product_graph(times)
         ctx.set_tuning(product_graph=best["product_graph"])
         if pprec == C64_SPLIT_BF16:
             times = {}

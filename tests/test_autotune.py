@@ -35,3 +35,9 @@ def test_apply_sets_every_parameter():
     t = ctx.get_tuning()
     assert (t.aca_waves, list(t.aca3d_waves), t.aca3d_stack_slices, t.product_graph) == \
         (4, [1, 2, 4, 8], 16, 0)
+
+
+def test_product_graph_choice_prefers_the_graph():
+    assert autotune.choose_product_graph({0: 1.00, 1: 1.02}) == 1
+    assert autotune.choose_product_graph({0: 1.02, 1: 1.00}) == 1
+    assert autotune.choose_product_graph({0: 0.90, 1: 1.00}) == 0
